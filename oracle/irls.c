@@ -1,0 +1,328 @@
+/*
+ * Oracle IRLS rounds (test infrastructure only).
+ *
+ * Section 2.1: each round computes conductances from the previous
+ * potentials (Step 1, eq. define-reweight-vector with the reweighted
+ * Laplacian of eq. reweighted-laplacian), then solves the weighted least
+ * squares problem (Step 2, eq. constrained-wls) through the reduced
+ * Laplacian system L~ v = b of eq. reduced-laplacian-system, where L~ drops
+ * the rows and columns of s and t and b_u is the conductance of edge {u,s}.
+ * Round 0 uses W = C, i.e. conductance = capacity.
+ *
+ * Section 3.1: the system is solved by preconditioned CG (Saad's PCG) with a
+ * Jacobi preconditioner here (diagonal blocks of size one), warm-started
+ * from the previous round's solution when requested.
+ *
+ * Two conductance forms are provided:
+ *   form 0: g = c / sqrt(d^2 + eps)
+ *   form 1: g = c^2 / sqrt((c d)^2 + eps)   (paper's w with eps^2 -> eps)
+ * with d = x_u - x_v.
+ *
+ * Dot products are summed in fixed chunks of 4096 entries, chunk partials in
+ * chunk order, so the result does not depend on the thread count.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include "ograph.h"
+
+#define CHUNK 4096
+
+void orc_options_default(orc_options *o) {
+  o->rounds = 30;
+  o->eps0 = 0.1;
+  o->eps_factor = 0.5;
+  o->weight_form = 0;
+  o->init = 0;
+  o->warm_start = 1;
+  o->cg_rtol = 1e-10;
+  o->cg_maxit = 100000;
+  o->threads = 0;
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+static double cond(double c, double d, double eps, int form) {
+  if (form == 0) return c / sqrt(d * d + eps);
+  return (c * c) / sqrt((c * d) * (c * d) + eps);
+}
+
+static double dot(const double *a, const double *b, int64_t n) {
+  int64_t nc = (n + CHUNK - 1) / CHUNK;
+  double *part = (double *)malloc(sizeof(double) * (size_t)(nc ? nc : 1));
+  #pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < nc; c++) {
+    int64_t lo = c * CHUNK, hi = lo + CHUNK < n ? lo + CHUNK : n;
+    double acc = 0.0;
+    for (int64_t i = lo; i < hi; i++) acc += a[i] * b[i];
+    part[c] = acc;
+  }
+  double tot = 0.0;
+  for (int64_t c = 0; c < nc; c++) tot += part[c];
+  free(part);
+  return tot;
+}
+
+/* one round's reduced system: conductances, diagonal and right-hand side */
+typedef struct {
+  double *w;          /* conductance per interior adjacency entry */
+  double *ws, *wt;    /* conductance of the s-edge / t-edge per row */
+  double  wst;        /* conductance of the s-t edge */
+  double *D, *b;
+} osys;
+
+static void assemble(const ograph *g, osys *S, const double *v, int round0,
+                     double eps, int form) {
+  int64_t nt = g->nt;
+  #pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nt; i++) {
+    double diag = 0.0;
+    for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) {
+      double c = g->nc[a];
+      S->w[a] = round0 ? c : cond(c, v[i] - v[g->nb[a]], eps, form);
+      diag += S->w[a];
+    }
+    double cs = g->cs[i], ct = g->ct[i];
+    S->ws[i] = cs > 0.0 ? (round0 ? cs : cond(cs, 1.0 - v[i], eps, form)) : 0.0;
+    S->wt[i] = ct > 0.0 ? (round0 ? ct : cond(ct, v[i] - 0.0, eps, form)) : 0.0;
+    S->D[i] = diag + S->ws[i] + S->wt[i];
+    S->b[i] = S->ws[i];
+  }
+  S->wst = g->cst > 0.0 ? (round0 ? g->cst : cond(g->cst, 1.0, eps, form)) : 0.0;
+}
+
+/* q = L~ p */
+static void spmv(const ograph *g, const osys *S, const double *p, double *q) {
+  int64_t nt = g->nt;
+  #pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < nt; i++) {
+    double acc = S->D[i] * p[i];
+    for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) acc -= S->w[a] * p[g->nb[a]];
+    q[i] = acc;
+  }
+}
+
+/* Jacobi PCG from the initial guess in v; returns status, fills iters/res */
+static int pcg(const ograph *g, const osys *S, double *v, double rtol, int64_t maxit,
+               double *r, double *z, double *p, double *q, int64_t *iters, double *relres) {
+  int64_t nt = g->nt;
+  double bnorm = sqrt(dot(S->b, S->b, nt));
+  *iters = 0;
+  if (bnorm == 0.0) {                   /* b = 0: the unique solution is v = 0 */
+    for (int64_t i = 0; i < nt; i++) v[i] = 0.0;
+    *relres = 0.0;
+    return ORC_OK;
+  }
+  spmv(g, S, v, q);
+  for (int64_t i = 0; i < nt; i++) r[i] = S->b[i] - q[i];
+  double rnorm = sqrt(dot(r, r, nt));
+  if (rnorm <= rtol * bnorm) { *relres = rnorm / bnorm; return ORC_OK; }
+  for (int64_t i = 0; i < nt; i++) { z[i] = r[i] / S->D[i]; p[i] = z[i]; }
+  double rho = dot(r, z, nt);
+  int64_t k = 0;
+  while (k < maxit) {
+    spmv(g, S, p, q);
+    double pq = dot(p, q, nt);
+    if (!(pq > 0.0) || !isfinite(pq)) { *iters = k; *relres = rnorm / bnorm; return ORC_ERR_BREAKDOWN; }
+    double alpha = rho / pq;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nt; i++) { v[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+    k++;
+    rnorm = sqrt(dot(r, r, nt));
+    if (rnorm <= rtol * bnorm) break;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nt; i++) z[i] = r[i] / S->D[i];
+    double rho_new = dot(r, z, nt);
+    double beta = rho_new / rho;
+    rho = rho_new;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nt; i++) p[i] = z[i] + beta * p[i];
+  }
+  *iters = k;
+  *relres = rnorm / bnorm;
+  if (!isfinite(rnorm)) return ORC_ERR_BREAKDOWN;
+  return rnorm <= rtol * bnorm ? ORC_OK : ORC_WARN_MAXIT;
+}
+
+/* per-round diagnostics at potentials v (x_s = 1, x_t = 0) */
+static void round_stats(const ograph *g, const osys *S, const double *v, double eps_next,
+                        int form, double *q, orc_round *R) {
+  int64_t nt = g->nt;
+  double se = 0.0, l1 = 0.0, fl = 0.0, fs = 0.0, ft = 0.0;
+  double vmin = nt ? v[0] : 0.0, vmax = nt ? v[0] : 0.0;
+  for (int64_t i = 0; i < nt; i++) {
+    for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) {
+      if (g->nb[a] <= i) continue;                      /* each interior edge once */
+      double c = g->nc[a], d = v[i] - v[g->nb[a]];
+      se += form == 0 ? c * sqrt(d * d + eps_next) : sqrt((c * d) * (c * d) + eps_next);
+      l1 += c * fabs(d);
+      fl += S->w[a] * d * d;
+    }
+    if (g->cs[i] > 0.0) {
+      double c = g->cs[i], d = 1.0 - v[i];
+      se += form == 0 ? c * sqrt(d * d + eps_next) : sqrt((c * d) * (c * d) + eps_next);
+      l1 += c * fabs(d);
+      fl += S->ws[i] * d * d;
+      fs += S->ws[i] * d;
+    }
+    if (g->ct[i] > 0.0) {
+      double c = g->ct[i], d = v[i];
+      se += form == 0 ? c * sqrt(d * d + eps_next) : sqrt((c * d) * (c * d) + eps_next);
+      l1 += c * fabs(d);
+      fl += S->wt[i] * d * d;
+      ft += S->wt[i] * d;
+    }
+    if (v[i] < vmin) vmin = v[i];
+    if (v[i] > vmax) vmax = v[i];
+  }
+  if (g->cst > 0.0) {
+    double c = g->cst;
+    se += form == 0 ? c * sqrt(1.0 + eps_next) : sqrt(c * c + eps_next);
+    l1 += c;
+    fl += S->wst;
+    fs += S->wst;
+    ft += S->wst;
+  }
+  R->s_eps = se; R->l1 = l1; R->flow = fl; R->flow_s = fs; R->flow_t = ft;
+  R->vmin = vmin; R->vmax = vmax;
+  /* true residual of this round's system */
+  if (nt > 0) {
+    spmv(g, S, v, q);
+    for (int64_t i = 0; i < nt; i++) q[i] = S->b[i] - q[i];
+    double bn = sqrt(dot(S->b, S->b, nt));
+    R->true_rel_res = bn > 0.0 ? sqrt(dot(q, q, nt)) / bn : 0.0;
+  } else {
+    R->true_rel_res = 0.0;
+  }
+}
+
+int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
+             const double *cap, int64_t s, int64_t t, const orc_options *opt,
+             const double *x0, double *x_out, orc_round *rounds_out) {
+  orc_options o;
+  if (opt) o = *opt; else orc_options_default(&o);
+  if (!x_out) return ORC_ERR_NULL;
+  if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
+      !(o.cg_rtol > 0.0) || o.cg_maxit < 1 || (o.rounds > 0 && !(o.eps0 > 0.0)) ||
+      !(o.eps_factor > 0.0) || o.eps_factor > 1.0)
+    return ORC_ERR_OPTIONS;
+  if (o.init == 2 && !x0) return ORC_ERR_NULL;
+#ifdef _OPENMP
+  if (o.threads > 0) omp_set_num_threads(o.threads);
+#endif
+  ograph g;
+  int rc = og_build(&g, n, m, eu, ev, cap, s, t);
+  if (rc) return rc;
+  int64_t nt = g.nt, na = g.rp[nt];
+  size_t nv = (size_t)(nt ? nt : 1);
+  osys S;
+  S.w = (double *)malloc(sizeof(double) * (size_t)(na ? na : 1));
+  S.ws = (double *)malloc(sizeof(double) * nv);
+  S.wt = (double *)malloc(sizeof(double) * nv);
+  S.D = (double *)malloc(sizeof(double) * nv);
+  S.b = (double *)malloc(sizeof(double) * nv);
+  double *v = (double *)calloc(nv, sizeof(double));
+  double *r = (double *)malloc(sizeof(double) * nv);
+  double *z = (double *)malloc(sizeof(double) * nv);
+  double *p = (double *)malloc(sizeof(double) * nv);
+  double *q = (double *)malloc(sizeof(double) * nv);
+  int status = ORC_OK;
+  if (!S.w || !S.ws || !S.wt || !S.D || !S.b || !v || !r || !z || !p || !q) { status = ORC_ERR_NOMEM; goto done; }
+
+  if (o.init == 2) {
+    for (int64_t i = 0; i < nt; i++) {
+      v[i] = x0[g.orig[i]];
+      if (!isfinite(v[i])) { status = ORC_ERR_RANGE; goto done; }
+    }
+  } else if (o.init == 1) {
+    for (int64_t i = 0; i < nt; i++) v[i] = 0.5;
+  }
+
+  double eps = o.eps0;
+  for (int32_t l = 0; l <= o.rounds; l++) {
+    orc_round R;
+    memset(&R, 0, sizeof(R));
+    int64_t it = 0;
+    double rel = 0.0;
+    int st = ORC_OK;
+    if (l == 0) {
+      assemble(&g, &S, v, 1, 0.0, o.weight_form);
+      if (o.init == 0) {                          /* x(0): WLS with W0 = C, cold start */
+        for (int64_t i = 0; i < nt; i++) v[i] = 0.0;
+        st = nt ? pcg(&g, &S, v, o.cg_rtol, o.cg_maxit, r, z, p, q, &it, &rel) : ORC_OK;
+      }
+      R.eps = 0.0;
+    } else {
+      assemble(&g, &S, v, 0, eps, o.weight_form);
+      if (!o.warm_start) for (int64_t i = 0; i < nt; i++) v[i] = 0.0;
+      st = nt ? pcg(&g, &S, v, o.cg_rtol, o.cg_maxit, r, z, p, q, &it, &rel) : ORC_OK;
+      R.eps = eps;
+    }
+    R.cg_iters = it;
+    R.rel_res = rel;
+    R.status = st;
+    double eps_next = l == 0 ? o.eps0 : eps * o.eps_factor;
+    round_stats(&g, &S, v, eps_next, o.weight_form, q, &R);
+    if (rounds_out) rounds_out[l] = R;
+    if (st == ORC_ERR_BREAKDOWN) { status = st; goto done; }
+    if (st == ORC_WARN_MAXIT) status = ORC_WARN_MAXIT;
+    if (l >= 1) eps = eps * o.eps_factor;
+  }
+  for (int64_t u = 0; u < n; u++) x_out[u] = 0.0;
+  for (int64_t i = 0; i < nt; i++) x_out[g.orig[i]] = v[i];
+  x_out[s] = 1.0;
+  x_out[t] = 0.0;
+done:
+  free(S.w); free(S.ws); free(S.wt); free(S.D); free(S.b);
+  free(v); free(r); free(z); free(p); free(q);
+  og_free(&g);
+  return status;
+}
+
+int orc_reduced_system(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
+                       const double *cap, int64_t s, int64_t t, const double *x,
+                       double eps, int32_t weight_form, int64_t *rowptr, int64_t *col,
+                       double *val, double *b, int64_t *nnz_out) {
+  if (!rowptr || !nnz_out) return ORC_ERR_NULL;
+  ograph g;
+  int rc = og_build(&g, n, m, eu, ev, cap, s, t);
+  if (rc) return rc;
+  int64_t nt = g.nt;
+  rowptr[0] = 0;
+  for (int64_t i = 0; i < nt; i++) rowptr[i + 1] = rowptr[i] + (g.rp[i + 1] - g.rp[i]) + 1;
+  *nnz_out = rowptr[nt];
+  if (!col) { og_free(&g); return ORC_OK; }
+  if (!val || !b) { og_free(&g); return ORC_ERR_NULL; }
+  size_t nv = (size_t)(nt ? nt : 1);
+  double *v = (double *)calloc(nv, sizeof(double));
+  osys S;
+  S.w = (double *)malloc(sizeof(double) * (size_t)(g.rp[nt] ? g.rp[nt] : 1));
+  S.ws = (double *)malloc(sizeof(double) * nv);
+  S.wt = (double *)malloc(sizeof(double) * nv);
+  S.D = (double *)malloc(sizeof(double) * nv);
+  S.b = (double *)malloc(sizeof(double) * nv);
+  if (x) for (int64_t i = 0; i < nt; i++) v[i] = x[g.orig[i]];
+  assemble(&g, &S, v, x == NULL, eps, weight_form);
+  for (int64_t i = 0; i < nt; i++) {
+    int64_t o = rowptr[i];
+    int placed = 0;
+    for (int64_t a = g.rp[i]; a < g.rp[i + 1]; a++) {
+      if (!placed && g.nb[a] > i) { col[o] = i; val[o] = S.D[i]; o++; placed = 1; }
+      col[o] = g.nb[a]; val[o] = -S.w[a]; o++;
+    }
+    if (!placed) { col[o] = i; val[o] = S.D[i]; o++; }
+    b[i] = S.b[i];
+  }
+  free(v); free(S.w); free(S.ws); free(S.wt); free(S.D); free(S.b);
+  og_free(&g);
+  return ORC_OK;
+}

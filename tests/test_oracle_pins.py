@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+Each test names the passage of the paper (or the piece of mathematics) it
+relies on.  Together they are chosen so that a plausible slip in the oracle
+(a dropped term, a wrong sign, a swapped index or operand, a wrong
+conductance form) breaks at least one of them.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import gen
+from gen import rng
+from gen.graphs import Graph
+
+
+def mk(n, s, t, edges):
+    e = np.asarray(edges, dtype=np.float64).reshape(-1, 3)
+    return Graph(n, s, t, e[:, 0].astype(np.int64), e[:, 1].astype(np.int64), e[:, 2].copy())
+
+
+def path_graph(caps):
+    """s - u1 - ... - uk - t with capacities caps[0..k]; ids: u_i = i-1, s = k, t = k+1."""
+    k = len(caps) - 1
+    s, t = k, k + 1
+    chain = [s] + list(range(k)) + [t]
+    return mk(k + 2, s, t, [(chain[j], chain[j + 1], caps[j]) for j in range(k + 1)])
+
+
+def series_potentials(cond):
+    """Series conductances g_0..g_k from s (potential 1) to t (0): potentials of the
+    k inner nodes.  The current is 1/sum(1/g); each conductor drops current/g."""
+    F = 1.0 / sum(1.0 / g for g in cond)
+    out, v = [], 1.0
+    for g in cond[:-1]:
+        v -= F / g
+        out.append(v)
+    return np.array(out)
+
+
+def exact_cut(g, in_S):
+    """Exact cut value with rational arithmetic (parallel edges summed)."""
+    tot = Fraction(0)
+    for a, b, c in zip(g.eu.tolist(), g.ev.tolist(), g.cap.tolist()):
+        if a != b and bool(in_S[a]) != bool(in_S[b]):
+            tot += Fraction(c)
+    return tot
+
+
+# ---------------------------------------------------------------------------
+# closed forms
+# ---------------------------------------------------------------------------
+def test_single_node_round0_and_limit(oracle_mod):
+    """One non-terminal u with capacities a (to s) and b (to t).
+
+    Round 0 (Section 2.1, W0 = C): u is a voltage divider, v = a/(a+b).
+    Every later round solves a 1x1 system, v' = g_s/(g_s+g_t).  With a
+    vanishing smoothing eps the conductances are c/|d| (Step 1 with the
+    reweighted Laplacian), so the odds v/(1-v) are multiplied by a/b each
+    round, and the sweep picks the cheaper edge: cut = min(a, b)."""
+    a, b = 0.7, 0.3
+    g = mk(3, 1, 2, [(1, 0, a), (0, 2, b)])
+    x, R, _ = oracle_mod.irls(g, rounds=0)
+    assert x[0] == pytest.approx(a / (a + b), rel=1e-15)
+    odds0 = x[0] / (1 - x[0])
+    for T in range(1, 6):
+        xT, _, _ = oracle_mod.irls(g, rounds=T, eps0=1e-30, eps_factor=1.0)
+        odds = xT[0] / (1 - xT[0])
+        assert odds == pytest.approx(odds0 * (a / b) ** T, rel=1e-12)
+    inS, val, k, _ = oracle_mod.sweep(g, xT)
+    assert val == b and inS[0]          # the t-edge (b < a) is cut: u stays with s
+
+
+def test_single_node_paper_form_scale(oracle_mod):
+    """Paper form (eq. define-reweight-vector + eq. reweighted-laplacian):
+    conductance c^2/sqrt((c d)^2 + eps).  Scaling every capacity by k leaves
+    the potentials unchanged when eps is scaled by k^2: the conductances all
+    scale by k.  The other form c/sqrt(d^2+eps) has the same invariance with
+    eps fixed.  A wrong power of c in either form breaks one of these."""
+    base = [(1, 0, 0.9), (0, 2, 0.4), (0, 3, 0.5), (3, 2, 1.3), (1, 3, 0.2)]
+    k = 3.0
+    g1 = mk(4, 1, 2, base)
+    g2 = mk(4, 1, 2, [(u, v, c * k) for u, v, c in base])
+    xa, _, _ = oracle_mod.irls(g1, rounds=4, weight_form=1, eps0=1e-2, eps_factor=0.5)
+    xb, _, _ = oracle_mod.irls(g2, rounds=4, weight_form=1, eps0=1e-2 * k * k, eps_factor=0.5)
+    np.testing.assert_allclose(xa, xb, rtol=1e-11, atol=1e-13)
+    ya, _, _ = oracle_mod.irls(g1, rounds=4, weight_form=0, eps0=1e-2, eps_factor=0.5)
+    yb, _, _ = oracle_mod.irls(g2, rounds=4, weight_form=0, eps0=1e-2, eps_factor=0.5)
+    np.testing.assert_allclose(ya, yb, rtol=1e-11, atol=1e-13)
+    # and the two forms really differ once capacities differ from 1
+    assert np.max(np.abs(xa - ya)) > 1e-4
+
+
+def test_path_every_round_matches_series_circuit(oracle_mod):
+    """Path s-u1-...-uk-t: each round is a series circuit (Proposition 3, the
+    WLS is an electrical flow), solved in closed form from the conductances.
+    Round 0 conductances are the capacities; later ones c/sqrt(d^2+eps_l)
+    with d taken from the oracle's previous round.  The min cut of a path is
+    its smallest capacity."""
+    caps = [0.9, 0.35, 0.8, 0.6, 0.25, 1.1, 0.7]
+    g = path_graph(caps)
+    k = len(caps) - 1
+    x0, _, _ = oracle_mod.irls(g, rounds=0, cg_rtol=1e-14)
+    np.testing.assert_allclose(x0[:k], series_potentials(caps), rtol=1e-12, atol=1e-14)
+    prev = x0
+    eps = 0.1
+    for T in range(1, 12):
+        xT, _, _ = oracle_mod.irls(g, rounds=T, cg_rtol=1e-14)
+        pot = [1.0] + list(prev[:k]) + [0.0]
+        cond = [c / np.sqrt((pot[j] - pot[j + 1]) ** 2 + eps) for j, c in enumerate(caps)]
+        np.testing.assert_allclose(xT[:k], series_potentials(cond), rtol=1e-9, atol=1e-12)
+        prev = xT
+        eps *= 0.5
+    _, val, _, _ = oracle_mod.sweep(g, prev)
+    assert val == min(caps)
+
+
+def test_uniform_grid_reduces_to_path(oracle_mod):
+    """Uniform interior capacity 1 on an nx-by-ny grid with equal terminal
+    capacity q on the left and right columns: by symmetry the round-0
+    potentials depend on the column only, giving a path whose column-to-column
+    conductance is ny and whose terminal conductances are ny*q."""
+    nx, ny, q = 12, 5, 0.8
+    g = gen.grid2d(nx, ny, seed=0)
+    g.cap[:] = 1.0
+    g.cap[g.meta["interior"]:] = q
+    x, _, _ = oracle_mod.irls(g, rounds=0, cg_rtol=1e-14)
+    cols = [ny * q] + [float(ny)] * (nx - 1) + [ny * q]
+    want = series_potentials(cols)
+    got = x[:nx * ny].reshape(ny, nx)
+    for r in range(ny):
+        np.testing.assert_allclose(got[r], want, rtol=1e-11, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# solver against a direct solve
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["grid", "gnp"])
+def test_pcg_matches_dense_solve(oracle_mod, which):
+    """Section 3.1: L~ v = b is symmetric positive definite; PCG must reach
+    the direct solution.  Also: L~ is symmetric, has a positive diagonal,
+    non-positive off-diagonals, and L~ e >= b (proof of Proposition 2)."""
+    g = gen.grid2d(20, 20, seed=5) if which == "grid" else gen.gnp(16, 0.3, seed=9)
+    nt = g.n - 2
+    for T in (0, 3):
+        x, _, _ = oracle_mod.irls(g, rounds=T, cg_rtol=1e-14)
+        xprev = None
+        if T > 0:
+            xprev, _, _ = oracle_mod.irls(g, rounds=T - 1, cg_rtol=1e-14)
+        eps = 0.0 if T == 0 else 0.1 * 0.5 ** (T - 1)
+        rp, col, val, b = oracle_mod.reduced_system(g, xprev, eps)
+        A = np.zeros((nt, nt))
+        for i in range(nt):
+            A[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+        assert np.array_equal(A, A.T)
+        assert np.all(np.diag(A) > 0)
+        off = A - np.diag(np.diag(A))
+        assert np.all(off <= 0)
+        assert np.all(A.sum(axis=1) >= b - 1e-12 * np.diag(A))
+        ids = [u for u in range(g.n) if u not in (g.s, g.t)]
+        v = np.linalg.solve(A, b)
+        np.testing.assert_allclose(x[ids], v, rtol=1e-9, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# invariants from the paper
+# ---------------------------------------------------------------------------
+def test_prop2_prop3_descent_on_grid(oracle_mod):
+    """Proposition 2: 0 <= v <= 1.  Proposition 3: the WLS solution is an
+    electrical flow whose value x^T L x equals the flow leaving s and the flow
+    entering t.  Section 2.2 (majorisation-minimisation of S_eps, Beck's
+    theorems): S at this round's x with the next round's eps never increases,
+    because eps decreases and each round minimises a majoriser."""
+    g = gen.grid2d(32, 32, seed=3)
+    _, R, _ = oracle_mod.irls(g, rounds=25, cg_rtol=1e-12)
+    tol = 1e-8
+    prev = np.inf
+    for r in R:
+        assert r["vmin"] >= -tol and r["vmax"] <= 1 + tol
+        assert r["flow_s"] == pytest.approx(r["flow"], rel=1e-7)
+        assert r["flow_t"] == pytest.approx(r["flow"], rel=1e-7)
+        assert r["s_eps"] <= prev * (1 + 1e-10)
+        prev = r["s_eps"]
+
+
+def test_cheeger_bounds_round0(oracle_mod):
+    """Section 2.3 and the appendix: with C = 2 sum c and E0 the round-0 flow
+    value, lambda_2 = 2 E0 / C and phi = mu*/C, so phi^2/2 <= lambda_2 <= 2 phi
+    reads mu*^2/(4C) <= E0 <= mu*."""
+    for seed in range(1, 21):
+        g = gen.gnp(16, 0.3, seed=seed)
+        _, R, _ = oracle_mod.irls(g, rounds=0, cg_rtol=1e-14)
+        _, mu, _ = oracle_mod.bruteforce(g)
+        Ctot = 2 * g.cap.sum()
+        E0 = R[0]["flow"]
+        assert mu * mu / (4 * Ctot) <= E0 * (1 + 1e-12)
+        assert E0 <= mu * (1 + 1e-12)
+
+
+def test_chain_invariant_random_potentials(oracle_mod):
+    """eq. l1-min: for any x in [0,1] with x_s=1, x_t=0 the threshold (coarea)
+    argument gives mu* <= sweep(x) <= ||CBx||_1 <= S_eps(x)."""
+    for seed in range(1, 11):
+        g = gen.gnp(16, 0.3, seed=seed)
+        _, mu, _ = oracle_mod.bruteforce(g)
+        x = rng.uniform(seed, 99, np.arange(g.n, dtype=np.uint64))
+        x[g.s], x[g.t] = 1.0, 0.0
+        _, sw, _, _ = oracle_mod.sweep(g, x)
+        l1 = sum(c * abs(x[a] - x[b]) for a, b, c in zip(g.eu, g.ev, g.cap))
+        seps = sum(c * np.sqrt((x[a] - x[b]) ** 2 + 1e-3) for a, b, c in zip(g.eu, g.ev, g.cap))
+        assert mu <= sw * (1 + 1e-15)
+        assert sw <= l1 * (1 + 1e-12)
+        assert l1 <= seps
+
+
+# ---------------------------------------------------------------------------
+# the sweep and exact cut values
+# ---------------------------------------------------------------------------
+def _sweep_by_definition(g, x):
+    nt_ids = [u for u in range(g.n) if u not in (g.s, g.t)]
+    order = sorted(nt_ids, key=lambda u: (-x[u], u))
+    best, bk = None, None
+    inS = np.zeros(g.n, bool)
+    inS[g.s] = True
+    for k in range(len(order) + 1):
+        if k > 0:
+            inS[order[k - 1]] = True
+        v = exact_cut(g, inS)
+        if best is None or v < best:
+            best, bk = v, k
+    return best, bk
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_sweep_equals_prefix_definition(oracle_mod, seed):
+    """The sweep recomputed from scratch for every prefix set with exact
+    rational sums must pick the same k and value (ties included: potentials
+    are rounded to a few levels so many nodes tie)."""
+    g = gen.gnp(16, 0.3, seed=seed)
+    x = np.round(rng.uniform(seed, 5, np.arange(g.n, dtype=np.uint64)) * 4) / 4
+    _, val, k, _ = oracle_mod.sweep(g, x)
+    best, bk = _sweep_by_definition(g, x)
+    assert k == bk
+    assert val == float(best)
+
+
+def test_cut_value_exact_with_parallel_edges(oracle_mod):
+    """Parallel edges add up, self loops never count (problem statement)."""
+    g = mk(5, 0, 4, [(0, 1, 0.1), (1, 0, 0.2), (1, 2, 0.3), (2, 2, 9.0), (2, 3, 1e-3),
+                     (3, 4, 0.7), (1, 4, 0.05), (0, 3, 0.4), (2, 4, 0.6)])
+    for mask in range(8):
+        inS = np.array([1, mask & 1, (mask >> 1) & 1, (mask >> 2) & 1, 0], dtype=bool)
+        assert oracle_mod.cut_value(g, inS) == float(exact_cut(g, inS))
+
+
+def test_fixed_point_extreme_scales(oracle_mod):
+    """Capacities 16 decimal orders apart are summed exactly: 1 + 1e-16 + 1e-16
+    is 1 in left-to-right double arithmetic but 1 + 2^-52 when rounded once
+    from the exact sum (the 128-bit scale keeps every capacity exact)."""
+    caps = [1.0, 1e-16, 2.5, 1e-16, 0.3, 3.0]
+    g = path_graph(caps)
+    x = np.array([0.9, 0.8, 0.7, 0.6, 0.5, 1.0, 0.0])
+    inS, val, k, _ = oracle_mod.sweep(g, x)
+    assert val == 1e-16 and k == 1     # S_1 = {s, u0}; the tie at k = 3 loses to the smaller k
+    inS2 = np.zeros(g.n, bool)
+    inS2[[g.s, 1, 2]] = True          # cuts s-u0 (1), u0-u1 (1e-16) and u2-u3 (1e-16)
+    exact = float(exact_cut(g, inS2))
+    assert exact == 1.0 + 2.0 ** -52 and (1.0 + 1e-16) + 1e-16 == 1.0
+    assert oracle_mod.cut_value(g, inS2) == exact
+
+
+# ---------------------------------------------------------------------------
+# exact solvers
+# ---------------------------------------------------------------------------
+def test_bruteforce_hand_graphs(oracle_mod):
+    # two disjoint s-t paths: min cut = sum of each path's bottleneck
+    g = mk(6, 0, 5, [(0, 1, 3.0), (1, 5, 1.0), (0, 2, 0.5), (2, 3, 2.0), (3, 4, 4.0), (4, 5, 1.5)])
+    _, v, sec = oracle_mod.bruteforce(g)
+    assert v == 1.5
+    # path 1 (caps 3, 1) and path 2 (caps 0.5, 2, 4, 1.5): the best cut takes the
+    # bottleneck of each, 1 + 0.5; the next distinct value is 1 + 1.5
+    assert sec == 2.5
+
+
+def test_maxflow_equals_bruteforce(oracle_mod):
+    """FIFO push-relabel (Section 4 names the family) against enumeration of
+    all 2^14 source sides on the 50 G(16,0.3) graphs."""
+    for seed in range(1, 51):
+        g = gen.gnp(16, 0.3, seed=seed)
+        S1, v1 = oracle_mod.maxflow(g)
+        S2, v2, sec = oracle_mod.bruteforce(g)
+        assert v1 == v2
+        assert oracle_mod.cut_value(g, S1) == v1
+        if sec > v2:
+            assert np.array_equal(S1, S2)
+
+
+def test_maxflow_random_small_graphs(oracle_mod):
+    for seed in range(100, 130):
+        n = 6 + seed % 14
+        g = gen.gnp(n, 0.35, seed=seed)
+        _, v1 = oracle_mod.maxflow(g)
+        _, v2, _ = oracle_mod.bruteforce(g)
+        assert v1 == v2
+
+
+# ---------------------------------------------------------------------------
+# quality and determinism of the whole oracle
+# ---------------------------------------------------------------------------
+def test_irls_sweep_bounded_by_exact(oracle_mod):
+    """IRLS with sweep rounding is an approximation (Section 1, delta-accurate):
+    its cut can never be below mu*.  On these well-separated small graphs it
+    finds the exact minimum in the large majority of cases."""
+    exact = 0
+    for seed in range(1, 51):
+        g = gen.gnp(16, 0.3, seed=seed)
+        x, _, _ = oracle_mod.irls(g, rounds=30, cg_rtol=1e-12)
+        _, val, _, _ = oracle_mod.sweep(g, x)
+        _, mu, _ = oracle_mod.bruteforce(g)
+        assert val >= mu
+        exact += val == mu
+    assert exact >= 45
+
+
+def test_grid64_exact(oracle_mod):
+    g = gen.grid2d(64, 64, seed=0)
+    x, R, rc = oracle_mod.irls(g, rounds=30, cg_rtol=1e-10)
+    assert rc == 0
+    _, val, _, _ = oracle_mod.sweep(g, x)
+    _, mu = oracle_mod.maxflow(g)
+    assert val == mu
+
+
+def test_thread_count_does_not_change_bits(oracle_mod):
+    g = gen.grid2d(40, 30, seed=2)
+    x1, R1, _ = oracle_mod.irls(g, rounds=8, threads=1)
+    x4, R4, _ = oracle_mod.irls(g, rounds=8, threads=4)
+    assert np.array_equal(x1, x4)
+    assert [r["cg_iters"] for r in R1] == [r["cg_iters"] for r in R4]
+
+
+def test_parallel_edges_and_self_loops_merge(oracle_mod):
+    g = gen.gnp(12, 0.4, seed=3)
+    # split every edge into two halves, reverse one, add self loops
+    half = g.cap / 2
+    g2 = Graph(g.n, g.s, g.t, np.concatenate([g.eu, g.ev, np.arange(g.n)]),
+               np.concatenate([g.ev, g.eu, np.arange(g.n)]),
+               np.concatenate([half, g.cap - half, np.ones(g.n)]))
+    x1, _, _ = oracle_mod.irls(g, rounds=5)
+    x2, _, _ = oracle_mod.irls(g2, rounds=5)
+    np.testing.assert_allclose(x1, x2, rtol=1e-12, atol=1e-14)
+    assert oracle_mod.sweep(g, x1)[1] == oracle_mod.sweep(g2, x1)[1]
+
+
+def test_error_codes(oracle_mod):
+    o = oracle_mod
+    g = gen.gnp(8, 0.5, seed=1)
+    assert o.error_code(o.irls, Graph(g.n, 0, 0, g.eu, g.ev, g.cap)) == 2
+    assert o.error_code(o.irls, Graph(g.n, 0, 99, g.eu, g.ev, g.cap)) == 2
+    bad = g.cap.copy()
+    bad[0] = -1
+    assert o.error_code(o.irls, Graph(g.n, g.s, g.t, g.eu, g.ev, bad)) == 3
+    bad[0] = np.nan
+    assert o.error_code(o.irls, Graph(g.n, g.s, g.t, g.eu, g.ev, bad)) == 3
+    dis = mk(5, 0, 4, [(0, 1, 1.0), (1, 4, 1.0), (2, 3, 1.0)])
+    assert o.error_code(o.irls, dis) == 4
+    assert o.error_code(o.irls, g, rounds=-1) == 5
+    assert o.error_code(o.irls, g, cg_rtol=0.0) == 5
+    assert o.error_code(o.irls, g, weight_form=3) == 5
+
+
+def test_degenerate_graphs(oracle_mod):
+    # only s and t: the cut is the s-t edge
+    g = mk(2, 0, 1, [(0, 1, 0.75), (1, 0, 0.25)])
+    x, R, _ = oracle_mod.irls(g, rounds=3)
+    inS, val, k, _ = oracle_mod.sweep(g, x)
+    assert val == 1.0 and k == 0 and list(inS) == [True, False]
+    # a node hanging off t only: its potential is 0, it never joins S
+    g = mk(4, 0, 1, [(0, 2, 1.0), (2, 1, 2.0), (3, 1, 0.5), (0, 1, 0.1)])
+    x, _, _ = oracle_mod.irls(g, rounds=5)
+    assert x[3] == 0.0
+    inS, val, _, _ = oracle_mod.sweep(g, x)
+    assert val == pytest.approx(1.1) and not inS[3]
