@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""IRLS s-t min-cut benchmark on one MI355X.
+
+A step is one whole pass of the hot path on one synthetic instance already
+resident in HBM: every IRLS round (reweight + Jacobi-PCG) followed by the
+sweep cut, i.e. irls_mincut_solve + irls_mincut_cut.  The default workload is
+the 128^3 6-connected segmentation grid (2,097,152 non-terminal nodes,
+6,242,304 interior edges), FP64, 40 rounds with eps halved from 0.1, CG to a
+relative residual of 1e-8.
+
+Prints one JSON line with the throughput (cuts/s), the roofline of the SpMV
+kernel (algorithmic bytes / measured launch time vs 8 TB/s) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (generator kwargs, solver options, description)
+    "seg128": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8),
+               "3-D 6-connected 128^3 segmentation grid, smooth-field capacities, FP64, "
+               "40 rounds, eps 0.1 halved per round, Jacobi-PCG to 1e-8"),
+    "grid64": (dict(kind="grid2d", nx=64, ny=64, seed=0), dict(rounds=30, cg_rtol=1e-10),
+               "2-D 4-connected 64x64 grid, FP64, 30 rounds, eps 0.1 halved, Jacobi-PCG to 1e-10"),
+    "seg256": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8),
+               "3-D 6-connected 256^3 segmentation grid, FP64 (plain), 40 rounds, CG to 1e-8"),
+    "seg256-mixed": (dict(kind="seg", N=256, seed=2),
+                     dict(rounds=40, cg_rtol=1e-8, precision=1, refine_every=20),
+                     "3-D 256^3 segmentation grid, FP32 conductances/SpMV/CG vectors, FP64 "
+                     "potentials, dots and residual replacement every 20 CG steps"),
+}
+
+
+def make_graph(spec):
+    import gen
+    spec = dict(spec)
+    kind = spec.pop("kind")
+    if kind == "seg":
+        return gen.grid3d_seg(spec["N"], seed=spec["seed"])
+    return gen.grid2d(spec["nx"], spec["ny"], seed=spec["seed"])
+
+
+def spmv_bytes(info, precision):
+    """Algorithmic bytes of one SpMV launch (each array element touched once)."""
+    nt, nnz, K = info["n_nonterminal"], info["nnz_offdiag"], info["n_diagonals"]
+    ts = 4 if precision == 1 else 8
+    if info["format"] == 2:
+        # reads D, K conductances, r, p_old; writes p_new, q
+        return nt * (ts * (K + 3) + 2 * ts)
+    # CSR: values + column indices + row pointers, D, p, q
+    return nnz * (ts + 4) + (nt + 1) * 4 + nt * 3 * ts
+
+
+def cpu_baseline(g, opts, gpu_iters_total, budget_s):
+    """Oracle time per CG iteration on the first rounds of the same instance,
+    scaled to the GPU run's total CG iterations, plus the oracle sweep."""
+    import oracle
+    rounds = 1
+    t_total, it_total = 0.0, 0
+    while True:
+        t0 = time.perf_counter()
+        x, R, _ = oracle.irls(g, rounds=rounds, eps0=0.1, eps_factor=0.5,
+                              cg_rtol=opts.get("cg_rtol", 1e-8), allow_maxit=True)
+        dt = time.perf_counter() - t0
+        t_total, it_total = dt, sum(r["cg_iters"] for r in R)
+        if dt > budget_s / 3 or rounds >= opts.get("rounds", 40):
+            break
+        rounds = min(opts.get("rounds", 40), rounds * 2)
+    t0 = time.perf_counter()
+    oracle.sweep(g, x)
+    t_sweep = time.perf_counter() - t0
+    per_it = t_total / max(it_total, 1)
+    est = per_it * gpu_iters_total + t_sweep
+    return {
+        "value": 1.0 / est, "unit": "cuts/s", "cores": oracle.max_threads(), "kind": "oracle",
+        "sample": (f"oracle IRLS rounds 0..{rounds} of the same instance ({it_total} CG iterations "
+                   f"in {t_total:.1f} s) + one oracle sweep ({t_sweep:.1f} s); time-to-cut "
+                   f"estimated as per-iteration cost x the GPU run's {gpu_iters_total} CG iterations "
+                   f"+ sweep = {est:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="seg128", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--kernel-reps", type=int, default=100)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not part of it "
+              "(see the sharding design in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1501_03105_amd as P
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    spec, opts, desc = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    g = make_graph(spec)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] workload {args.workload}: n={g.n} m={g.m} generated in {t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    mc = P.MinCut.from_graph(g, stream=stream, **opts)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    info = mc.info()
+    print(f"[bench] create {t_setup:.1f}s info {info}", file=sys.stderr, flush=True)
+
+    def step():
+        rc, st = mc.solve()
+        _, val, k = mc.cut()
+        return st, val
+
+    for i in range(args.warmup):
+        st, val = step()
+        print(f"[bench] warmup {i}: cut {val:.10g}, CG iterations {sum(r['cg_iters'] for r in st)}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st, val = step()
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(r["cg_iters"] for r in st)
+    ms_step = 1000.0 * dt / args.steps
+
+    roof = None
+    if info["solver"] == 1:
+        spmv_ms = mc.time_kernel(0, args.kernel_reps)
+        upd_ms = mc.time_kernel(1, args.kernel_reps)
+        nbytes = spmv_bytes(info, opts.get("precision", 0))
+        achieved = nbytes / (spmv_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_spmv_dia" if info["format"] == 2 else "k_spmv_csr",
+                "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5),
+                "update_kernel_ms": round(upd_ms, 5)}
+        print(f"[bench] spmv {spmv_ms*1e3:.1f} us ({achieved:.0f} GB/s), update {upd_ms*1e3:.1f} us",
+              file=sys.stderr, flush=True)
+    mc.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(g, opts, iters, args.cpu_budget)
+
+    out = {
+        "metric": "IRLS s-t min-cut time-to-cut, as cuts per second (solve + sweep, graph resident)",
+        "value": round(args.steps / dt, 5), "unit": "cuts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if opts.get("precision", 0) == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "n_nonterminal": info["n_nonterminal"],
+                   "interior_edges": info["nnz_offdiag"] // 2, "format": info["format"],
+                   "solver": info["solver"], "cg_iters_per_cut": iters, "cut_value": val,
+                   "setup_s": round(t_setup, 3)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * irls_mincut.h -- C ABI of the MI355X (gfx950) IRLS undirected s-t min-cut
+ * library (libirls_mincut.so).
+ *
+ * Method: Zhu & Gleich, "A Parallel Min-Cut Algorithm using Iteratively
+ * Reweighted Least Squares".
+ *   - problem (Section 2): G = (V, E) undirected, capacities c({u,v}) > 0,
+ *     source s, sink t, G connected; find the s-t cut of least capacity;
+ *   - IRLS (Section 2.1): round 0 solves the weighted least-squares problem
+ *     (eq. constrained-wls) with W = C; each later round recomputes the edge
+ *     conductances from the current potentials (Step 1, eq.
+ *     define-reweight-vector with eq. reweighted-laplacian) and solves the
+ *     reduced Laplacian system L~ v = b (eq. reduced-laplacian-system) on the
+ *     non-terminal nodes with x_s = 1, x_t = 0;
+ *   - solver (Section 3.1): Jacobi-preconditioned CG, warm-started from the
+ *     previous round;
+ *   - rounding (Section 3.4): sweep cut over the sorted final potentials.
+ *
+ * Every call returns an irls_status; no exception or signal crosses the ABI.
+ * Argument validation finishes before any HIP call, so error paths can be
+ * exercised without a GPU.  Handles are not thread safe; distinct handles are
+ * independent.  All device work of a handle is ordered on the HIP stream given
+ * at creation; calls that return host-visible results synchronise it.
+ */
+#ifndef IRLS_MINCUT_H
+#define IRLS_MINCUT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct irls_mincut_s *irls_mincut_t;   /* opaque, owned by the library */
+
+typedef enum {
+  IRLS_OK = 0,
+  IRLS_ERR_NULL = 1,          /* a required pointer is NULL */
+  IRLS_ERR_RANGE = 2,         /* n < 2, m < 0, an endpoint or s/t outside [0,n), s == t,
+                                 a non-finite potential, or a graph too large for 32-bit
+                                 device indices */
+  IRLS_ERR_CAPACITY = 3,      /* a capacity <= 0, NaN or infinite (Section 2: c > 0) */
+  IRLS_ERR_DISCONNECTED = 4,  /* G is not connected (Section 2; Proposition 1) */
+  IRLS_ERR_OPTIONS = 5,       /* an option out of range or struct_size mismatch */
+  IRLS_ERR_NOT_SOLVED = 6,    /* cut/potentials requested before a successful solve */
+  IRLS_ERR_CG_BREAKDOWN = 7,  /* p^T q <= 0 or a non-finite CG scalar */
+  IRLS_ERR_DEVICE = 8,        /* HIP runtime error; text in irls_mincut_last_error */
+  IRLS_ERR_OOM = 9,           /* device or host allocation failed */
+  IRLS_WARN_CG_MAXIT = 100    /* finished, but some round stopped at cg_maxit */
+} irls_status;
+
+/* Options.  Fill with irls_options_default() and change fields. */
+typedef struct {
+  int32_t struct_size;        /* must equal sizeof(irls_options) */
+  int32_t rounds;             /* T, reweighted rounds after round 0 (>= 0), default 30 */
+  double  eps0;               /* smoothing of round 1 (> 0), default 0.1 */
+  double  eps_factor;         /* eps_{l+1} = eps_l * eps_factor, in (0,1], default 0.5 */
+  int32_t weight_form;        /* 0: g = c/sqrt(d^2+eps) (default);
+                                 1: g = c^2/sqrt((c d)^2+eps), the paper's w with eps^2 -> eps */
+  int32_t init;               /* 0: round 0 solves with W = C (paper, default);
+                                 1: x = 1/2 on every non-terminal, no round-0 solve;
+                                 2: caller potentials x0 passed to irls_mincut_solve */
+  int32_t warm_start;         /* 1: CG starts from the previous round (default); 0: from 0 */
+  double  cg_rtol;            /* stop when ||r||_2 <= cg_rtol * ||b||_2, default 1e-10 */
+  int64_t cg_maxit;           /* per round, >= 1, default 100000 */
+  int32_t precision;          /* 0: FP64 everywhere (default);
+                                 1: FP32 conductances, SpMV and CG vectors, FP64 potentials,
+                                    FP64 dot products, FP64 residual replacement */
+  int32_t refine_every;       /* precision 1: true FP64 residual every this many CG steps */
+  double  fp64_weights_below_eps; /* precision 1: conductances computed in FP64 once eps is
+                                     below this value, in FP32 before (default 1e-4) */
+  int32_t format;             /* 0 auto; 1 CSR; 2 diagonal (few constant index offsets) */
+  int32_t solver;             /* 0 auto; 1 multi-workgroup kernels; 2 one resident workgroup */
+  int32_t chunk;              /* CG iterations launched between host checks, 0 = auto */
+  int32_t inputs_on_device;   /* 1: edge arrays and x0 are device pointers */
+  int32_t rows_per_wave;      /* CSR SpMV rows per 64-lane wavefront: 0 autotune, else
+                                 1,2,4,...,64 */
+} irls_options;
+
+/* Per-round record (round 0 first). */
+typedef struct {
+  double  eps;                /* smoothing of this round (0 for round 0) */
+  int64_t cg_iters;           /* CG iterations of this round */
+  double  rel_res;            /* recursive ||r||/||b|| at exit */
+  double  true_rel_res;       /* ||b - L~ v||/||b|| recomputed in FP64 at exit */
+  double  s_eps;              /* smoothed objective (eq. l1-min-smooth-version) at this
+                                 round's x, with the next round's eps */
+  double  l1;                 /* ||C B x||_1 (eq. l1-min) */
+  double  flow;               /* x^T L x, the electrical flow value (Proposition 3) */
+  double  flow_s, flow_t;     /* flow leaving s / entering t */
+  double  vmin, vmax;         /* range of the non-terminal potentials (Proposition 2) */
+  int32_t status;             /* irls_status of this round's CG */
+} irls_round_stats;
+
+void irls_options_default(irls_options *o);
+
+/* Build a handle for graph G.
+ *   n        nodes, ids 0..n-1 (n >= 2)
+ *   m        edges; edge e joins edge_u[e] and edge_v[e] with capacity cap[e] > 0.
+ *            Edges are undirected; self loops are dropped; parallel edges are merged
+ *            by summing their capacities in ascending e.  The s-t edge counts in the
+ *            cut value but not in the linear systems.
+ *   s, t     source and sink
+ *   opt      NULL = defaults; copied
+ *   hip_stream  hipStream_t to order all work on, NULL = the default stream
+ * Arrays are read during the call only (host memory, or device memory when
+ * opt->inputs_on_device); the caller keeps ownership.  On error *out = NULL and
+ * nothing is leaked. */
+irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m,
+                               const int64_t *edge_u, const int64_t *edge_v,
+                               const double *cap, int64_t s, int64_t t,
+                               const irls_options *opt, void *hip_stream);
+
+/* Run round 0 (or the chosen start) and rounds 1..T on the device.
+ *   x0      n potentials (entries of s and t ignored) when init == 2, else NULL
+ *   stats   NULL, or an array of T+1 records (host memory) filled on return
+ * Returns IRLS_OK, IRLS_WARN_CG_MAXIT or an error. */
+irls_status irls_mincut_solve(irls_mincut_t h, const double *x0, irls_round_stats *stats);
+
+/* Sweep cut of the current potentials (Section 3.4): non-terminals in
+ * descending potential, ties by ascending id; S_k = {s} + first k; the
+ * smallest k with the least cut value wins.  Cut values are exact integer
+ * sums of round-half-even(c * 2^k) at one 128-bit scale per graph; the value
+ * returned is the exact minimum rounded once to double.
+ *   in_source_side  NULL or n bytes (host): 1 for nodes in S (s included)
+ *   cut_value       NULL or 1 double (host)
+ *   k_star          NULL or 1 int64 (host): number of non-terminals in S */
+irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
+                            int64_t *k_star);
+
+/* Copy the current potentials (n doubles, host; x_s = 1, x_t = 0). */
+irls_status irls_mincut_potentials(irls_mincut_t h, double *x);
+
+/* Replace the current potentials (n doubles, host or device per
+ * inputs_on_device; s and t entries ignored) and mark the handle solved, so
+ * that irls_mincut_cut rounds them and a later solve with init == 2 may
+ * resume from them.  Non-finite entries give IRLS_ERR_RANGE. */
+irls_status irls_mincut_set_potentials(irls_mincut_t h, const double *x);
+
+/* Sizes chosen at creation: non-terminal count, stored off-diagonal entries,
+ * storage format (1 CSR, 2 diagonal), number of diagonals, solver (1 or 2),
+ * CSR rows per wavefront. */
+irls_status irls_mincut_info(irls_mincut_t h, int64_t *n_nonterminal, int64_t *nnz_offdiag,
+                             int32_t *format, int32_t *n_diagonals, int32_t *solver,
+                             int32_t *rows_per_wave);
+
+/* Time one hot kernel of the CG loop on the handle's stream with HIP events:
+ * `which` 0 = SpMV (with its fused direction update), 1 = the CG vector
+ * update.  `reps` back-to-back launches after one warm-up launch; *avg_ms is
+ * the mean duration.  Needs a prior solve; overwrites the CG work vectors
+ * (p, q; potentials untouched) -- call solve again before resuming. */
+irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps,
+                                    double *avg_ms);
+
+/* Free the handle and all its device memory (NULL is a no-op). */
+void irls_mincut_destroy(irls_mincut_t h);
+
+/* Text of the last error of h, or of the calling thread's last failed create
+ * when h == NULL.  Valid until the next call on the same handle/thread. */
+const char *irls_mincut_last_error(irls_mincut_t h);
+
+/* ----------------------------------------------------------------------------
+ * Batched form: G independent graphs solved together, one workgroup per graph
+ * running every round of its graph inside one persistent kernel launch.
+ *   node_off[G+1], edge_off[G+1]   graph g owns nodes node_off[g]..node_off[g+1]-1
+ *                                   and edges edge_off[g]..edge_off[g+1]-1
+ *   edge_u, edge_v                 LOCAL node ids (0..n_g-1) of each graph
+ *   s[G], t[G]                     local source and sink of each graph
+ * Each graph obeys the single-graph rules above. */
+irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t G, const int64_t *node_off,
+                                     const int64_t *edge_off, const int64_t *edge_u,
+                                     const int64_t *edge_v, const double *cap,
+                                     const int64_t *s, const int64_t *t,
+                                     const irls_options *opt, void *hip_stream);
+
+/* Solve every graph of a batch handle.  stats: NULL or G*(T+1) records,
+ * graph-major (host). */
+irls_status irls_mincut_solve_batch(irls_mincut_t h, irls_round_stats *stats);
+
+/* Sweep cut of every graph: in_source_side NULL or sum(n_g) bytes laid out like
+ * node_off; cut_values NULL or G doubles. */
+irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, double *cut_values);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,229 @@
+"""Python binding of libirls_mincut, the MI355X IRLS s-t min-cut library.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  The names follow the C ABI in include/irls_mincut.h.  Arrays may
+be numpy arrays (host) or torch CUDA tensors (device; the options then set
+inputs_on_device).  Importing this module raises if the HIP library has not
+been built: there is no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libirls_mincut.so")
+
+OK, ERR_NULL, ERR_RANGE, ERR_CAPACITY, ERR_DISCONNECTED, ERR_OPTIONS = 0, 1, 2, 3, 4, 5
+ERR_NOT_SOLVED, ERR_CG_BREAKDOWN, ERR_DEVICE, ERR_OOM, WARN_CG_MAXIT = 6, 7, 8, 9, 100
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("rounds", C.c_int32), ("eps0", C.c_double),
+                ("eps_factor", C.c_double), ("weight_form", C.c_int32), ("init", C.c_int32),
+                ("warm_start", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int64),
+                ("precision", C.c_int32), ("refine_every", C.c_int32),
+                ("fp64_weights_below_eps", C.c_double), ("format", C.c_int32),
+                ("solver", C.c_int32), ("chunk", C.c_int32), ("inputs_on_device", C.c_int32),
+                ("rows_per_wave", C.c_int32)]
+
+
+class RoundStats(C.Structure):
+    _fields_ = [("eps", C.c_double), ("cg_iters", C.c_int64), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double), ("s_eps", C.c_double), ("l1", C.c_double),
+                ("flow", C.c_double), ("flow_s", C.c_double), ("flow_t", C.c_double),
+                ("vmin", C.c_double), ("vmax", C.c_double), ("status", C.c_int32)]
+
+
+STAT_FIELDS = [f for f, _ in RoundStats._fields_]
+
+
+class IrlsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"irls_mincut error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libirls_mincut.so; raises if it is missing (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1501_03105_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        P64, PF64, PU8 = C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_uint8)
+        L.irls_options_default.argtypes = [C.POINTER(Options)]
+        L.irls_options_default.restype = None
+        L.irls_mincut_create.argtypes = [C.POINTER(H), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_int64, C.c_int64, C.POINTER(Options), C.c_void_p]
+        L.irls_mincut_solve.argtypes = [H, C.c_void_p, C.POINTER(RoundStats)]
+        L.irls_mincut_cut.argtypes = [H, PU8, PF64, P64]
+        L.irls_mincut_potentials.argtypes = [H, PF64]
+        L.irls_mincut_set_potentials.argtypes = [H, C.c_void_p]
+        L.irls_mincut_info.argtypes = [H, P64, P64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.irls_mincut_time_kernel.argtypes = [H, C.c_int32, C.c_int32, PF64]
+        L.irls_mincut_destroy.argtypes = [H]
+        L.irls_mincut_destroy.restype = None
+        L.irls_mincut_last_error.argtypes = [H]
+        L.irls_mincut_last_error.restype = C.c_char_p
+        L.irls_mincut_create_batch.argtypes = [C.POINTER(H), C.c_int32, P64, P64, P64, P64, PF64,
+                                               P64, P64, C.POINTER(Options), C.c_void_p]
+        L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
+        L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
+        for f in ("create", "solve", "cut", "potentials", "set_potentials", "info", "time_kernel",
+                  "create_batch", "solve_batch", "cut_batch"):
+            getattr(L, "irls_mincut_" + f).restype = C.c_int
+        o = Options()
+        L.irls_options_default(C.byref(o))
+        if o.struct_size != C.sizeof(Options):
+            raise ImportError("irls_options layout mismatch between binding and library")
+        _lib = L
+    return _lib
+
+
+def options(**kw):
+    o = Options()
+    lib().irls_options_default(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, dtype):
+    """Device/host address of a contiguous array; returns (ptr, keepalive, on_device)."""
+    if a is None:
+        return None, None, False
+    if _is_torch(a):
+        import torch
+        tdt = {np.int64: torch.int64, np.float64: torch.float64}[dtype]
+        t = a.to(tdt).contiguous()
+        return t.data_ptr(), t, t.is_cuda
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, arr, False
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream        # torch.cuda.Stream
+
+
+def _stats_list(arr):
+    return [{f: getattr(r, f) for f in STAT_FIELDS} for r in arr]
+
+
+class MinCut:
+    """One graph on the GPU: irls_mincut_create / _solve / _cut / ... / _destroy."""
+
+    def __init__(self, n, eu, ev, cap, s, t, stream=None, **opts):
+        L = lib()
+        pu, ku, du = _ptr(eu, np.int64)
+        pv, kv, dv = _ptr(ev, np.int64)
+        pc, kc, dc = _ptr(cap, np.float64)
+        if opts.get("inputs_on_device") is None and (du or dv or dc):
+            opts["inputs_on_device"] = 1
+        self.opt = options(**opts)
+        self.n, self.s, self.t = int(n), int(s), int(t)
+        m = 0 if ku is None else int(ku.shape[0] if hasattr(ku, "shape") else len(ku))
+        h = C.c_void_p()
+        rc = L.irls_mincut_create(C.byref(h), self.n, m, pu, pv, pc, self.s, self.t,
+                                  C.byref(self.opt), _stream_ptr(stream))
+        if rc != OK:
+            raise IrlsError(rc, L.irls_mincut_last_error(None).decode())
+        self.h = h
+
+    @classmethod
+    def from_graph(cls, g, **kw):
+        return cls(g.n, g.eu, g.ev, g.cap, g.s, g.t, **kw)
+
+    def _err(self, rc):
+        return IrlsError(rc, lib().irls_mincut_last_error(self.h).decode())
+
+    def solve(self, x0=None, allow_maxit=True):
+        """Run all rounds. Returns (status, per-round stats list)."""
+        st = (RoundStats * (self.opt.rounds + 1))()
+        px, keep, _ = _ptr(x0, np.float64)
+        rc = lib().irls_mincut_solve(self.h, px, st)
+        if rc not in (OK, WARN_CG_MAXIT) or (rc == WARN_CG_MAXIT and not allow_maxit):
+            raise self._err(rc)
+        return rc, _stats_list(st)
+
+    def cut(self):
+        """Sweep cut. Returns (in_S bool [n], value, k_star)."""
+        mask = np.zeros(self.n, np.uint8)
+        val = C.c_double(0)
+        ks = C.c_int64(0)
+        rc = lib().irls_mincut_cut(self.h, mask.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(val),
+                                   C.byref(ks))
+        if rc != OK:
+            raise self._err(rc)
+        return mask.astype(bool), val.value, ks.value
+
+    def potentials(self):
+        x = np.zeros(self.n)
+        rc = lib().irls_mincut_potentials(self.h, x.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc != OK:
+            raise self._err(rc)
+        return x
+
+    def set_potentials(self, x):
+        px, keep, _ = _ptr(x, np.float64)
+        rc = lib().irls_mincut_set_potentials(self.h, px)
+        if rc != OK:
+            raise self._err(rc)
+
+    def info(self):
+        nt, nnz = C.c_int64(), C.c_int64()
+        fmt, K, sol, rpw = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        rc = lib().irls_mincut_info(self.h, C.byref(nt), C.byref(nnz), C.byref(fmt), C.byref(K),
+                                    C.byref(sol), C.byref(rpw))
+        if rc != OK:
+            raise self._err(rc)
+        return dict(n_nonterminal=nt.value, nnz_offdiag=nnz.value, format=fmt.value,
+                    n_diagonals=K.value, solver=sol.value, rows_per_wave=rpw.value)
+
+    def time_kernel(self, which=0, reps=50):
+        ms = C.c_double(0)
+        rc = lib().irls_mincut_time_kernel(self.h, which, reps, C.byref(ms))
+        if rc != OK:
+            raise self._err(rc)
+        return ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().irls_mincut_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def create_error(n, eu, ev, cap, s, t, **opts):
+    """Status code irls_mincut_create returns for these arguments (0 = success)."""
+    try:
+        MinCut(n, eu, ev, cap, s, t, **opts).close()
+        return OK
+    except IrlsError as e:
+        return e.code

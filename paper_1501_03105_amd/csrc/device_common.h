@@ -1,0 +1,104 @@
+// Device helpers shared by the gfx950 kernels of libirls_mincut.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace irls {
+
+// Conductance of an edge of capacity c whose end potentials differ by d.
+// Step 1 of the IRLS round (eq. define-reweight-vector) combined with the
+// reweighted Laplacian (eq. reweighted-laplacian): the Laplacian weight of an
+// edge is c^2 / w with w = sqrt((c d)^2 + eps^2) (form 1, eps standing for the
+// squared smoothing); form 0 divides out one factor of c inside the root.
+template <typename F>
+__device__ __forceinline__ F conductance(F c, F d, F eps, int form) {
+  if (form == 0) return c / sqrt(d * d + eps);
+  F cd = c * d;
+  return (c * c) / sqrt(cd * cd + eps);
+}
+
+// Sum (or max, for the slots set in MAXMASK) of NQ values over the whole
+// workgroup.  Fixed butterfly inside each wavefront, then the per-wave
+// results in wave order: the result does not depend on timing.  On return
+// thread 0 holds the totals.  lds must hold NQ * (blockDim.x / 64) doubles.
+template <int NQ, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void block_reduce(double (&x)[NQ], double *lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    double v = x[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      double u = __shfl_xor(v, o, 64);
+      v = ((MAXMASK >> q) & 1u) ? fmax(v, u) : v + u;
+    }
+    x[q] = v;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) lds[q * nw + wid] = x[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+      double acc = lds[q * nw];
+      for (int w = 1; w < nw; w++)
+        acc = ((MAXMASK >> q) & 1u) ? fmax(acc, lds[q * nw + w]) : acc + lds[q * nw + w];
+      x[q] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NQ, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void block_allreduce(double (&x)[NQ], double *lds, double *bc) {
+  block_reduce<NQ, MAXMASK>(x, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) bc[q] = x[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; q++) x[q] = bc[q];
+}
+
+__device__ __forceinline__ double *pslot(double *partials, int slot, int q) {
+  return partials + ((size_t)slot * kNumPartial + q) * kMaxGrid;
+}
+
+// This workgroup's share of NQ grid-wide sums: stored at [slot][q][blockIdx].
+template <int NQ, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void write_partials(double (&x)[NQ], double *partials, int slot, double *lds) {
+  block_reduce<NQ, MAXMASK>(x, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; q++) pslot(partials, slot, q)[blockIdx.x] = x[q];
+  }
+}
+
+// Totals of the partial sums a previous kernel of `nblocks` workgroups left in
+// `slot`.  Every workgroup adds them in the same fixed order, so all get the
+// same bits; no atomics and no fences are needed (kernel boundaries order the
+// memory traffic).
+template <int NQ, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void read_totals(const double *partials, int slot, int nblocks,
+                                            double (&tot)[NQ], double *lds, double *bc) {
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const double *P = partials + ((size_t)slot * kNumPartial + q) * kMaxGrid;
+    double acc = ((MAXMASK >> q) & 1u) ? -INFINITY : 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+      acc = ((MAXMASK >> q) & 1u) ? fmax(acc, P[b]) : acc + P[b];
+    tot[q] = acc;
+  }
+  block_allreduce<NQ, MAXMASK>(tot, lds, bc);
+}
+
+// Grid-stride row loop helper: first row and stride of this thread.
+__device__ __forceinline__ int64_t row_begin() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int64_t row_stride() { return (int64_t)gridDim.x * blockDim.x; }
+
+}  // namespace irls

@@ -1,0 +1,927 @@
+// Host side of libirls_mincut: the C ABI, argument validation, graph set-up
+// (merging, connectivity, storage format), the IRLS round driver and the
+// sweep-cut driver.  All arithmetic of the method runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace irls;
+typedef __int128 i128;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+// ----------------------------------------------------------------------------
+// exact fixed point for cut values (host side of the sweep)
+// ----------------------------------------------------------------------------
+int fx_scale_of(double cmax, int64_t merged_edges) {
+  int e2 = 0;
+  if (cmax > 0.0) std::frexp(cmax, &e2);       // cmax = f 2^e2, f in [0.5, 1)
+  int L = 0;
+  while (L < 62 && ((int64_t)1 << L) < merged_edges + 1) L++;
+  return 125 - e2 - L;                          // sum of all capacities < 2^125
+}
+
+i128 fx_round_host(double c, int k) {
+  if (!(c > 0.0)) return 0;
+  uint64_t bits;
+  std::memcpy(&bits, &c, 8);
+  int ef = (int)((bits >> 52) & 0x7FF);
+  uint64_t mant = bits & ((1ull << 52) - 1);
+  int e2;
+  if (ef == 0) { e2 = -1074; } else { mant |= 1ull << 52; e2 = ef - 1075; }
+  int sh = e2 + k;
+  if (sh >= 0) return ((i128)mant) << sh;
+  int r = -sh;
+  if (r >= 64) return 0;
+  uint64_t q = mant >> r, rem = mant & ((1ull << r) - 1), half = 1ull << (r - 1);
+  if (rem > half || (rem == half && (q & 1ull))) q++;
+  return (i128)q;
+}
+
+// round-to-nearest-even conversion of a 128-bit integer, then scaling by 2^-k
+double fx_to_double(i128 v, int k) {
+  bool neg = v < 0;
+  unsigned __int128 a = neg ? (unsigned __int128)(-(v + 1)) + 1u : (unsigned __int128)v;
+  if (a == 0) return 0.0;
+  int msb = 127;
+  while (!((a >> msb) & 1u)) msb--;
+  double r;
+  if (msb <= 52) {
+    r = (double)(uint64_t)a;
+  } else {
+    int sh = msb - 52;
+    unsigned __int128 mant = a >> sh;
+    unsigned __int128 rem = a & ((((unsigned __int128)1) << sh) - 1u);
+    unsigned __int128 half = ((unsigned __int128)1) << (sh - 1);
+    if (rem > half || (rem == half && (mant & 1u))) mant++;
+    if (mant >> 53) { mant >>= 1; sh++; }
+    r = std::ldexp((double)(uint64_t)mant, sh);
+  }
+  r = std::ldexp(r, -k);
+  return neg ? -r : r;
+}
+
+// ----------------------------------------------------------------------------
+// host graph
+// ----------------------------------------------------------------------------
+struct HostGraph {
+  int64_t n = 0, s = 0, t = 0, nt = 0;
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> ccap, cs, ct, dcap;
+  double cst = 0.0, cmax = 0.0;
+  int64_t merged = 0, interior = 0;
+  int32_t K = 0;
+  int32_t off[kMaxDiag] = {0};
+  bool dia_ok = false;
+  int32_t fx_k = 0;
+  i128 D0 = 0;
+  bool no_source_edges = true;
+};
+
+inline int64_t nid_of(int64_t u, int64_t s, int64_t t) { return u - (u > s) - (u > t); }
+inline int64_t orig_of(int64_t i, int64_t s, int64_t t) {
+  int64_t lo = std::min(s, t), hi = std::max(s, t);
+  if (i >= lo) i++;
+  if (i >= hi) i++;
+  return i;
+}
+
+struct UnionFind {
+  std::vector<int64_t> p;
+  explicit UnionFind(int64_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+  int64_t find(int64_t x) {
+    while (p[x] != x) { p[x] = p[p[x]]; x = p[x]; }
+    return x;
+  }
+  void unite(int64_t a, int64_t b) {
+    a = find(a); b = find(b);
+    if (a != b) p[std::max(a, b)] = std::min(a, b);
+  }
+};
+
+irls_status build_host_graph(HostGraph &g, int64_t n, int64_t m, const int64_t *eu,
+                             const int64_t *ev, const double *cap, int64_t s, int64_t t,
+                             std::string &err) {
+  if (m > 0 && (!eu || !ev || !cap)) { err = "edge arrays must not be NULL"; return IRLS_ERR_NULL; }
+  if (n < 2 || m < 0 || s < 0 || s >= n || t < 0 || t >= n || s == t) {
+    err = "need n >= 2, m >= 0, s and t distinct nodes in [0,n)";
+    return IRLS_ERR_RANGE;
+  }
+  if (n - 2 >= (int64_t)INT32_MAX) { err = "too many nodes for 32-bit device indices"; return IRLS_ERR_RANGE; }
+  g.n = n; g.s = s; g.t = t; g.nt = n - 2;
+  const int64_t nt = g.nt;
+  for (int64_t e = 0; e < m; e++) {
+    if (eu[e] < 0 || eu[e] >= n || ev[e] < 0 || ev[e] >= n) {
+      err = "edge " + std::to_string(e) + " has an endpoint outside [0,n)";
+      return IRLS_ERR_RANGE;
+    }
+    if (!(cap[e] > 0.0) || !std::isfinite(cap[e])) {
+      err = "edge " + std::to_string(e) + " has a capacity that is not finite and positive";
+      return IRLS_ERR_CAPACITY;
+    }
+  }
+  g.cs.assign(nt, 0.0);
+  g.ct.assign(nt, 0.0);
+  // terminal edges are merged per node by a left-to-right sum in input order;
+  // interior edges are collected as (row a, row b), a < b
+  std::vector<int32_t> ia, ib;
+  std::vector<double> ic;
+  ia.reserve(m); ib.reserve(m); ic.reserve(m);
+  bool sorted = true;
+  uint64_t last = 0;
+  for (int64_t e = 0; e < m; e++) {
+    int64_t u = eu[e], v = ev[e];
+    if (u == v) continue;
+    double c = cap[e];
+    bool us = (u == s) || (v == s), ut = (u == t) || (v == t);
+    if (us && ut) { g.cst += c; continue; }
+    if (us) { g.cs[nid_of(u == s ? v : u, s, t)] += c; continue; }
+    if (ut) { g.ct[nid_of(u == t ? v : u, s, t)] += c; continue; }
+    int32_t a = (int32_t)nid_of(std::min(u, v), s, t), b = (int32_t)nid_of(std::max(u, v), s, t);
+    uint64_t key = ((uint64_t)a << 32) | (uint32_t)b;
+    if (!ia.empty() && key <= last) sorted = false;
+    last = key;
+    ia.push_back(a); ib.push_back(b); ic.push_back(c);
+  }
+  // merge parallel interior edges (stable by input order inside a key)
+  if (!sorted) {
+    std::vector<int64_t> idx(ia.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+      return ia[x] != ia[y] ? ia[x] < ia[y] : ib[x] < ib[y];
+    });
+    std::vector<int32_t> na, nb;
+    std::vector<double> nc;
+    na.reserve(idx.size()); nb.reserve(idx.size()); nc.reserve(idx.size());
+    for (int64_t j : idx) {
+      if (!na.empty() && na.back() == ia[j] && nb.back() == ib[j]) { nc.back() += ic[j]; continue; }
+      na.push_back(ia[j]); nb.push_back(ib[j]); nc.push_back(ic[j]);
+    }
+    ia.swap(na); ib.swap(nb); ic.swap(nc);
+  }
+  const int64_t mi = (int64_t)ia.size();
+  g.interior = mi;
+  if (2 * mi >= (int64_t)INT32_MAX) { err = "too many edges for 32-bit device indices"; return IRLS_ERR_RANGE; }
+
+  // connectivity (Proposition 1 needs G connected)
+  {
+    UnionFind uf(n);
+    for (int64_t i = 0; i < nt; i++) {
+      if (g.cs[i] > 0.0) uf.unite(orig_of(i, s, t), s);
+      if (g.ct[i] > 0.0) uf.unite(orig_of(i, s, t), t);
+    }
+    if (g.cst > 0.0) uf.unite(s, t);
+    for (int64_t e = 0; e < mi; e++) uf.unite(orig_of(ia[e], s, t), orig_of(ib[e], s, t));
+    int64_t root = uf.find(s);
+    for (int64_t u = 0; u < n; u++)
+      if (uf.find(u) != root) { err = "graph is not connected"; return IRLS_ERR_DISCONNECTED; }
+  }
+
+  // CSR over non-terminal rows, columns ascending
+  g.rowptr.assign(nt + 1, 0);
+  for (int64_t e = 0; e < mi; e++) { g.rowptr[ia[e] + 1]++; g.rowptr[ib[e] + 1]++; }
+  for (int64_t i = 0; i < nt; i++) g.rowptr[i + 1] += g.rowptr[i];
+  g.col.resize(2 * mi);
+  g.ccap.resize(2 * mi);
+  {
+    std::vector<int32_t> pos(g.rowptr.begin(), g.rowptr.end() - 1);
+    for (int64_t e = 0; e < mi; e++) { int32_t r = ib[e]; g.col[pos[r]] = ia[e]; g.ccap[pos[r]++] = ic[e]; }
+    for (int64_t e = 0; e < mi; e++) { int32_t r = ia[e]; g.col[pos[r]] = ib[e]; g.ccap[pos[r]++] = ic[e]; }
+  }
+
+  // diagonal format: few distinct offsets b - a and at least half of the slots used
+  {
+    int32_t offs[kMaxDiag + 1];
+    int K = 0;
+    bool ok = true;
+    for (int64_t e = 0; e < mi && ok; e++) {
+      int32_t d = ib[e] - ia[e];
+      int k = 0;
+      while (k < K && offs[k] != d) k++;
+      if (k == K) {
+        if (K == kMaxDiag) ok = false;
+        else offs[K++] = d;
+      }
+    }
+    if (ok && K > 0 && 2 * mi >= (int64_t)K * nt) {
+      std::sort(offs, offs + K);
+      g.K = K;
+      for (int k = 0; k < K; k++) g.off[k] = offs[k];
+      g.dia_ok = true;
+    }
+  }
+  if (g.dia_ok) {
+    g.dcap.assign((size_t)g.K * nt, 0.0);
+    for (int64_t e = 0; e < mi; e++) {
+      int32_t d = ib[e] - ia[e];
+      int k = 0;
+      while (g.off[k] != d) k++;
+      g.dcap[(size_t)k * nt + ia[e]] = ic[e];
+    }
+  }
+
+  // fixed-point scale of exact cut values and the cut of S_0 = {s}
+  double cmax = g.cst;
+  int64_t merged = mi + (g.cst > 0.0);
+  for (int64_t e = 0; e < mi; e++) cmax = std::max(cmax, ic[e]);
+  for (int64_t i = 0; i < nt; i++) {
+    if (g.cs[i] > 0.0) { merged++; cmax = std::max(cmax, g.cs[i]); g.no_source_edges = false; }
+    if (g.ct[i] > 0.0) { merged++; cmax = std::max(cmax, g.ct[i]); }
+  }
+  g.cmax = cmax;
+  g.merged = merged;
+  g.fx_k = fx_scale_of(cmax, merged);
+  g.D0 = fx_round_host(g.cst, g.fx_k);
+  for (int64_t i = 0; i < nt; i++) g.D0 += fx_round_host(g.cs[i], g.fx_k);
+  return IRLS_OK;
+}
+
+irls_status check_options(const irls_options &o, std::string &err) {
+  if (o.struct_size != (int32_t)sizeof(irls_options)) { err = "irls_options.struct_size mismatch"; return IRLS_ERR_OPTIONS; }
+  if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
+      !(o.cg_rtol > 0.0) || o.cg_maxit < 1 || (o.rounds > 0 && !(o.eps0 > 0.0)) ||
+      !(o.eps_factor > 0.0) || o.eps_factor > 1.0 || o.precision < 0 || o.precision > 1 ||
+      o.refine_every < 0 || o.format < 0 || o.format > 2 || o.solver < 0 || o.solver > 2 ||
+      o.chunk < 0 || (o.warm_start != 0 && o.warm_start != 1) ||
+      (o.inputs_on_device != 0 && o.inputs_on_device != 1) || o.rows_per_wave < 0 ||
+      o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0) {
+    err = "an option is out of range";
+    return IRLS_ERR_OPTIONS;
+  }
+  if (o.precision == 1 && o.solver == 2) { err = "the resident solver runs in FP64 only"; return IRLS_ERR_OPTIONS; }
+  return IRLS_OK;
+}
+
+int grid_for(int64_t rows) {
+  int64_t g = (rows + kBlock - 1) / kBlock;
+  if (g > kMaxGrid) g = kMaxGrid;
+  return g < 1 ? 1 : (int)g;
+}
+
+constexpr int64_t kResidentMaxRows = 32768;
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// handle
+// ----------------------------------------------------------------------------
+struct irls_mincut_s {
+  irls_options opt;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool solved = false;
+  bool batch = false;
+  GraphDev g;
+  i128 D0 = 0;
+  int solver = 1;
+  int rpw = 8;
+  int grid = 1;
+  // FP64 state (both precisions)
+  double *v = nullptr, *b = nullptr, *gt = nullptr;
+  double *w64 = nullptr, *D64 = nullptr;
+  // working-precision state (double for precision 0, float for 1)
+  void *w = nullptr, *D = nullptr, *r = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
+  double *partials = nullptr;
+  double *vsave = nullptr;         // potentials saved across kernel timing
+  Scalars *sc = nullptr, *sc_bench = nullptr;
+  irls_round_stats *dstats = nullptr;
+  Scalars *pinned = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // resident solver
+  ResidentGraph *rgraphs = nullptr;
+  int32_t *rorder = nullptr;
+  unsigned *rnext = nullptr;
+  SweepBufs sw;
+  std::vector<void *> allocs;
+
+  template <typename T>
+  hipError_t dalloc(T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    *p = (T *)q;
+    return hipSuccess;
+  }
+  void release() {
+    for (void *p : allocs) (void)hipFree(p);
+    allocs.clear();
+    if (pinned) (void)hipHostFree(pinned);
+    pinned = nullptr;
+    for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+irls_status dev_fail(irls_mincut_t h, hipError_t e, const char *what) {
+  h->err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? IRLS_ERR_OOM : IRLS_ERR_DEVICE;
+}
+
+#define HIPCHK(h, expr, what)                          \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return dev_fail(h, e_, what); \
+  } while (0)
+
+template <typename T>
+CGArgs<T> make_args(irls_mincut_t h) {
+  CGArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.nt = h->g.nt;
+  a.rowptr = h->g.rowptr;
+  a.col = h->g.col;
+  a.ccap = h->g.ccap;
+  a.K = h->g.format == 2 ? h->g.K : 0;
+  for (int k = 0; k < kMaxDiag; k++) a.off[k] = h->g.off[k];
+  a.dcap = h->g.dcap;
+  a.cs = h->g.cs;
+  a.ct = h->g.ct;
+  a.w = (T *)h->w;
+  a.D = (T *)h->D;
+  a.w64 = h->w64;
+  a.D64 = h->D64;
+  a.b = h->b;
+  a.gt = h->gt;
+  a.v = h->v;
+  a.r = (T *)h->r;
+  a.q = (T *)h->q;
+  a.p0 = (T *)h->p0;
+  a.p1 = (T *)h->p1;
+  a.partials = h->partials;
+  a.sc = h->sc;
+  a.form = h->opt.weight_form;
+  a.cst = h->g.cst;
+  a.rtol = h->opt.cg_rtol;
+  a.weights_fp64 = 1;
+  return a;
+}
+
+template <typename T>
+hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a, int64_t count) {
+  hipError_t e = hipSuccess;
+  for (int64_t i = 0; i < count && e == hipSuccess; i++) {
+    if (a.K == 0) e = launch_direction(a, h->grid, h->stream);
+    if (e == hipSuccess) e = launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream);
+    if (e == hipSuccess) e = launch_update(a, h->grid, h->stream);
+    if (e == hipSuccess && h->opt.precision == 1) e = launch_replace_residual(a, h->grid, h->stream);
+  }
+  return e;
+}
+
+// Run CG iterations in chunks until the device reports done.  The next chunk
+// is queued before the previous chunk's state is read back, so the GPU never
+// waits for the host; iterations queued after convergence return at once.
+template <typename T>
+irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *iters, int *status) {
+  // the stopping test of iteration i runs at the start of iteration i + 1, so
+  // cg_maxit iterations need cg_maxit + 1 direction launches
+  const int64_t maxit = h->opt.cg_maxit + 1;
+  int64_t first = pred > 0 ? std::max<int64_t>(16, pred * 7 / 8) : 64;
+  int64_t next = pred > 0 ? std::max<int64_t>(16, pred / 8) : 64;
+  if (h->opt.chunk > 0) first = next = h->opt.chunk;
+  first = std::min(first, maxit);
+  HIPCHK(h, launch_iterations(h, a, first), "CG launch");
+  HIPCHK(h, hipMemcpyAsync(&h->pinned[0], h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream), "readback");
+  HIPCHK(h, hipEventRecord(h->ev[0], h->stream), "event");
+  int64_t launched = first;
+  int slot = 0;
+  for (;;) {
+    bool queued = false;
+    if (launched < maxit) {
+      int64_t c = std::min(next, maxit - launched);
+      HIPCHK(h, launch_iterations(h, a, c), "CG launch");
+      HIPCHK(h, hipMemcpyAsync(&h->pinned[1 - slot], h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream), "readback");
+      HIPCHK(h, hipEventRecord(h->ev[1 - slot], h->stream), "event");
+      launched += c;
+      queued = true;
+      next = std::min<int64_t>(next * 2, 4096);
+    }
+    HIPCHK(h, hipEventSynchronize(h->ev[slot]), "sync");
+    if (h->pinned[slot].done) break;
+    if (!queued) {
+      HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+      slot = 1 - slot;
+      if (!h->pinned[slot].done) { h->err = "CG did not stop at cg_maxit"; return IRLS_ERR_DEVICE; }
+      break;
+    }
+    slot = 1 - slot;
+  }
+  *iters = h->pinned[slot].iter_b;
+  *status = h->pinned[slot].status;
+  return IRLS_OK;
+}
+
+irls_status load_x0(irls_mincut_t h, const double *x0) {
+  const int64_t n = h->g.n, nt = h->g.nt;
+  std::vector<double> xh;
+  const double *src = x0;
+  if (h->opt.inputs_on_device) {
+    xh.resize(n);
+    HIPCHK(h, hipMemcpy(xh.data(), x0, n * sizeof(double), hipMemcpyDeviceToHost), "x0 copy");
+    src = xh.data();
+  }
+  std::vector<double> vn(nt);
+  for (int64_t i = 0; i < nt; i++) {
+    vn[i] = src[orig_of(i, h->g.s, h->g.t)];
+    if (!std::isfinite(vn[i])) { h->err = "x0 has a non-finite entry"; return IRLS_ERR_RANGE; }
+  }
+  if (nt > 0)
+    HIPCHK(h, hipMemcpyAsync(h->v, vn.data(), nt * sizeof(double), hipMemcpyHostToDevice, h->stream), "x0 upload");
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  return IRLS_OK;
+}
+
+template <typename T>
+irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
+  const irls_options &o = h->opt;
+  const int64_t nt = h->g.nt;
+  CGArgs<T> a = make_args<T>(h);
+  const bool fp64 = sizeof(T) == 8;
+  int64_t pred = 0;
+  double eps = o.eps0;
+  irls_status result = IRLS_OK;
+  for (int l = 0; l <= o.rounds; l++) {
+    a.round0 = l == 0;
+    a.eps = l == 0 ? 0.0 : eps;
+    a.eps_next = l == 0 ? o.eps0 : eps * o.eps_factor;
+    a.warm = (l > 0 && o.warm_start) ? 1 : 0;
+    a.weights_fp64 = (fp64 || a.eps < o.fp64_weights_below_eps) ? 1 : 0;
+    a.stat = h->dstats + l;
+    const int32_t refine = o.refine_every > 0 ? o.refine_every : INT32_MAX;
+    HIPCHK(h, launch_scalars_reset(h->sc, o.cg_maxit, fp64 ? 0 : refine, h->stream), "reset");
+    if (nt > 0) HIPCHK(h, launch_assemble(a, h->grid, h->stream), "assemble");
+    bool solve = !(l == 0 && o.init != 0) && nt > 0;
+    if (solve && h->g.no_source_edges) {
+      HIPCHK(h, launch_fill(h->v, nt, 0.0, h->stream), "fill");
+      solve = false;
+    }
+    if (solve) {
+      HIPCHK(h, launch_cginit(a, h->grid, h->stream), "cg init");
+      int64_t it = 0;
+      int st = IRLS_OK;
+      irls_status rc = run_cg(h, a, pred, &it, &st);
+      if (rc != IRLS_OK) return rc;
+      pred = it;
+      if (st == IRLS_ERR_CG_BREAKDOWN) {
+        h->err = "CG breakdown in round " + std::to_string(l);
+        result = IRLS_ERR_CG_BREAKDOWN;
+      } else if (st == IRLS_WARN_CG_MAXIT && result == IRLS_OK) {
+        result = IRLS_WARN_CG_MAXIT;
+      }
+    }
+    if (nt > 0) HIPCHK(h, launch_stats(a, h->grid, h->stream), "stats");
+    if (result == IRLS_ERR_CG_BREAKDOWN) break;
+    if (l >= 1) eps *= o.eps_factor;
+  }
+  if (stats)
+    HIPCHK(h, hipMemcpyAsync(stats, h->dstats, (o.rounds + 1) * sizeof(irls_round_stats),
+                             hipMemcpyDeviceToHost, h->stream), "stats copy");
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  return result;
+}
+
+irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
+  const irls_options &o = h->opt;
+  ResidentArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.G = 1;
+  a.graphs = h->rgraphs;
+  a.rowptr = h->g.rowptr;
+  a.col = h->g.col;
+  a.ccap = h->g.ccap;
+  a.cs = h->g.cs;
+  a.ct = h->g.ct;
+  a.w = (double *)h->w;
+  a.D = (double *)h->D;
+  a.b = h->b;
+  a.gt = h->gt;
+  a.v = h->v;
+  a.r = (double *)h->r;
+  a.p = (double *)h->p0;
+  a.q = (double *)h->q;
+  a.stats = h->dstats;
+  a.next_graph = h->rnext;
+  a.order = h->rorder;
+  a.rounds = o.rounds;
+  a.eps0 = o.eps0;
+  a.eps_factor = o.eps_factor;
+  a.form = o.weight_form;
+  a.init = o.init;
+  a.warm = o.warm_start;
+  a.rtol = o.cg_rtol;
+  a.maxit = o.cg_maxit;
+  HIPCHK(h, hipMemsetAsync(h->rnext, 0, sizeof(unsigned), h->stream), "queue reset");
+  HIPCHK(h, hipMemsetAsync(h->dstats, 0, (o.rounds + 1) * sizeof(irls_round_stats), h->stream), "stats reset");
+  HIPCHK(h, launch_resident(a, 1, 1024, h->stream), "resident solve");
+  std::vector<irls_round_stats> hs(o.rounds + 1);
+  HIPCHK(h, hipMemcpyAsync(hs.data(), h->dstats, hs.size() * sizeof(irls_round_stats),
+                           hipMemcpyDeviceToHost, h->stream), "stats copy");
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  if (stats) std::memcpy(stats, hs.data(), hs.size() * sizeof(irls_round_stats));
+  irls_status result = IRLS_OK;
+  for (int l = 0; l <= o.rounds; l++) {
+    if (hs[l].status == IRLS_ERR_CG_BREAKDOWN) { h->err = "CG breakdown in round " + std::to_string(l); return IRLS_ERR_CG_BREAKDOWN; }
+    if (hs[l].status == IRLS_WARN_CG_MAXIT) result = IRLS_WARN_CG_MAXIT;
+  }
+  return result;
+}
+
+irls_status alloc_state(irls_mincut_t h) {
+  const int64_t nt = h->g.nt;
+  const bool f32 = h->opt.precision == 1;
+  const size_t ts = f32 ? sizeof(float) : sizeof(double);
+  const int64_t nw = h->g.format == 2 ? (int64_t)h->g.K * nt : h->g.nnz;
+  auto rawalloc = [&](void **p, size_t bytes) -> hipError_t {
+    char *q = nullptr;
+    hipError_t e = h->dalloc(&q, bytes);
+    *p = q;
+    return e;
+  };
+  HIPCHK(h, h->dalloc(&h->v, nt), "alloc");
+  HIPCHK(h, h->dalloc(&h->b, nt), "alloc");
+  HIPCHK(h, h->dalloc(&h->gt, nt), "alloc");
+  HIPCHK(h, rawalloc(&h->w, nw * ts), "alloc");
+  HIPCHK(h, rawalloc(&h->D, nt * ts), "alloc");
+  HIPCHK(h, rawalloc(&h->r, nt * ts), "alloc");
+  HIPCHK(h, rawalloc(&h->q, nt * ts), "alloc");
+  HIPCHK(h, rawalloc(&h->p0, nt * ts), "alloc");
+  if (h->g.format == 2) HIPCHK(h, rawalloc(&h->p1, nt * ts), "alloc");
+  if (f32) {
+    HIPCHK(h, h->dalloc(&h->w64, nw), "alloc");
+    HIPCHK(h, h->dalloc(&h->D64, nt), "alloc");
+  }
+  HIPCHK(h, h->dalloc(&h->partials, (size_t)kNumPSlots * kNumPartial * kMaxGrid), "alloc");
+  HIPCHK(h, hipMemset(h->partials, 0, (size_t)kNumPSlots * kNumPartial * kMaxGrid * sizeof(double)), "memset");
+  HIPCHK(h, h->dalloc(&h->sc, 1), "alloc");
+  HIPCHK(h, h->dalloc(&h->sc_bench, 1), "alloc");
+  HIPCHK(h, h->dalloc(&h->dstats, h->opt.rounds + 1), "alloc");
+  HIPCHK(h, hipMemset(h->v, 0, std::max<int64_t>(nt, 1) * sizeof(double)), "memset");
+  HIPCHK(h, hipHostMalloc((void **)&h->pinned, 2 * sizeof(Scalars), hipHostMallocDefault), "pinned alloc");
+  std::memset(h->pinned, 0, 2 * sizeof(Scalars));
+  HIPCHK(h, hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming), "event");
+  HIPCHK(h, hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming), "event");
+  if (h->solver == 2) {
+    HIPCHK(h, h->dalloc(&h->rgraphs, 1), "alloc");
+    HIPCHK(h, h->dalloc(&h->rorder, 1), "alloc");
+    HIPCHK(h, h->dalloc(&h->rnext, 1), "alloc");
+    ResidentGraph rg;
+    std::memset(&rg, 0, sizeof(rg));
+    rg.node0 = 0;
+    rg.nt = nt;
+    rg.nnz0 = 0;
+    rg.cst = h->g.cst;
+    rg.no_source_edges = h->g.no_source_edges ? 1 : 0;
+    int32_t zero = 0;
+    HIPCHK(h, hipMemcpy(h->rgraphs, &rg, sizeof(rg), hipMemcpyHostToDevice), "upload");
+    HIPCHK(h, hipMemcpy(h->rorder, &zero, sizeof(zero), hipMemcpyHostToDevice), "upload");
+  }
+  return IRLS_OK;
+}
+
+template <typename T>
+irls_status upload(irls_mincut_t h, T **dst, const std::vector<T> &src) {
+  HIPCHK(h, h->dalloc(dst, src.size()), "alloc");
+  if (!src.empty()) HIPCHK(h, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return IRLS_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+void irls_options_default(irls_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(irls_options);
+  o->rounds = 30;
+  o->eps0 = 0.1;
+  o->eps_factor = 0.5;
+  o->weight_form = 0;
+  o->init = 0;
+  o->warm_start = 1;
+  o->cg_rtol = 1e-10;
+  o->cg_maxit = 100000;
+  o->precision = 0;
+  o->refine_every = 20;
+  o->fp64_weights_below_eps = 1e-4;
+  o->format = 0;
+  o->solver = 0;
+  o->chunk = 0;
+  o->inputs_on_device = 0;
+  o->rows_per_wave = 0;
+}
+
+irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const int64_t *edge_u,
+                               const int64_t *edge_v, const double *cap, int64_t s, int64_t t,
+                               const irls_options *opt, void *hip_stream) {
+  if (!out) { g_thread_error = "out must not be NULL"; return IRLS_ERR_NULL; }
+  *out = nullptr;
+  irls_mincut_t h = nullptr;
+  try {
+    irls_options o;
+    if (opt) o = *opt; else irls_options_default(&o);
+    std::string err;
+    irls_status rc = check_options(o, err);
+    if (rc != IRLS_OK) { g_thread_error = err; return rc; }
+    if (m > 0 && (!edge_u || !edge_v || !cap)) { g_thread_error = "edge arrays must not be NULL"; return IRLS_ERR_NULL; }
+    // device-resident inputs are staged to the host for set-up
+    std::vector<int64_t> hu, hv;
+    std::vector<double> hc;
+    if (o.inputs_on_device && m > 0) {
+      if (n < 2 || m < 0) { g_thread_error = "need n >= 2 and m >= 0"; return IRLS_ERR_RANGE; }
+      hu.resize(m); hv.resize(m); hc.resize(m);
+      if (hipMemcpy(hu.data(), edge_u, m * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hv.data(), edge_v, m * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hc.data(), cap, m * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+        g_thread_error = "cannot read the device edge arrays";
+        return IRLS_ERR_DEVICE;
+      }
+      edge_u = hu.data(); edge_v = hv.data(); cap = hc.data();
+    }
+    HostGraph hg;
+    rc = build_host_graph(hg, n, m, edge_u, edge_v, cap, s, t, err);
+    if (rc != IRLS_OK) { g_thread_error = err; return rc; }
+    hu.clear(); hv.clear(); hc.clear();
+    if (o.format == 2 && !hg.dia_ok) {
+      g_thread_error = "graph does not fit the diagonal format";
+      return IRLS_ERR_OPTIONS;
+    }
+    h = new irls_mincut_s();
+    h->opt = o;
+    h->stream = (hipStream_t)hip_stream;
+    GraphDev &g = h->g;
+    g.n = n; g.s = s; g.t = t; g.nt = hg.nt;
+    g.nnz = (int64_t)hg.col.size();
+    g.cst = hg.cst;
+    g.fx_k = hg.fx_k;
+    g.cmax = hg.cmax;
+    g.no_source_edges = hg.no_source_edges;
+    h->D0 = hg.D0;
+    h->solver = o.solver ? o.solver : ((o.precision == 0 && hg.nt <= kResidentMaxRows) ? 2 : 1);
+    if (h->solver == 2 && o.format == 2) {
+      g_thread_error = "the resident solver stores the graph in CSR form";
+      delete h;
+      return IRLS_ERR_OPTIONS;
+    }
+    // the resident solver keeps one conductance per CSR entry
+    const bool use_dia = hg.dia_ok && o.format != 1 && h->solver == 1;
+    g.format = use_dia ? 2 : 1;
+    g.K = use_dia ? hg.K : 0;
+    for (int k = 0; k < kMaxDiag; k++) g.off[k] = hg.off[k];
+    h->grid = grid_for(hg.nt);
+    {
+      double avg = hg.nt > 0 ? (double)hg.col.size() / (double)hg.nt : 1.0;
+      int L = 1;
+      while (L < 64 && L < avg) L <<= 1;
+      h->rpw = o.rows_per_wave ? o.rows_per_wave : 64 / L;
+    }
+    if ((rc = upload(h, &g.rowptr, hg.rowptr)) != IRLS_OK ||
+        (rc = upload(h, &g.col, hg.col)) != IRLS_OK ||
+        (rc = upload(h, &g.ccap, hg.ccap)) != IRLS_OK ||
+        (rc = upload(h, &g.cs, hg.cs)) != IRLS_OK ||
+        (rc = upload(h, &g.ct, hg.ct)) != IRLS_OK ||
+        (use_dia && (rc = upload(h, &g.dcap, hg.dcap)) != IRLS_OK) ||
+        (rc = alloc_state(h)) != IRLS_OK) {
+      g_thread_error = h->err;
+      h->release();
+      delete h;
+      return rc;
+    }
+    *out = h;
+    return IRLS_OK;
+  } catch (const std::bad_alloc &) {
+    if (h) { h->release(); delete h; }
+    g_thread_error = "host allocation failed";
+    return IRLS_ERR_OOM;
+  } catch (...) {
+    if (h) { h->release(); delete h; }
+    g_thread_error = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_solve(irls_mincut_t h, const double *x0, irls_round_stats *stats) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "use irls_mincut_solve_batch for a batch handle"; return IRLS_ERR_OPTIONS; }
+  try {
+    h->solved = false;
+    const irls_options &o = h->opt;
+    if (o.init == 2) {
+      if (!x0) { h->err = "init == 2 needs x0"; return IRLS_ERR_NULL; }
+      irls_status rc = load_x0(h, x0);
+      if (rc != IRLS_OK) return rc;
+    } else if (o.init == 1 && h->g.nt > 0) {
+      HIPCHK(h, launch_fill(h->v, h->g.nt, 0.5, h->stream), "fill");
+    }
+    irls_status rc;
+    if (h->solver == 2) rc = solve_resident(h, stats);
+    else if (o.precision == 1) rc = solve_multi<float>(h, stats);
+    else rc = solve_multi<double>(h, stats);
+    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) h->solved = true;
+    return rc;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value, int64_t *k_star) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "use irls_mincut_cut_batch for a batch handle"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "no potentials yet: call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
+  try {
+    GraphDev &g = h->g;
+    i128 best = 0;
+    int64_t ks = 0;
+    if (g.nt > 0) {
+      SweepBufs &b = h->sw;
+      if (!b.keyA) {
+        const size_t nb = sweep_sort_blocks(g.nt), sb = sweep_scan_blocks(g.nt);
+        HIPCHK(h, h->dalloc(&b.keyA, g.nt), "alloc");
+        HIPCHK(h, h->dalloc(&b.keyB, g.nt), "alloc");
+        HIPCHK(h, h->dalloc(&b.idA, g.nt), "alloc");
+        HIPCHK(h, h->dalloc(&b.idB, g.nt), "alloc");
+        HIPCHK(h, h->dalloc(&b.rank, g.nt), "alloc");
+        HIPCHK(h, h->dalloc(&b.delta, g.nt), "alloc");
+        HIPCHK(h, h->dalloc(&b.hist, 256 * nb), "alloc");
+        HIPCHK(h, h->dalloc(&b.bsum, sb), "alloc");
+        HIPCHK(h, h->dalloc(&b.bmin, sb), "alloc");
+        HIPCHK(h, h->dalloc(&b.barg, sb), "alloc");
+        HIPCHK(h, h->dalloc(&b.best, 2), "alloc");
+        HIPCHK(h, h->dalloc(&b.kstar, 1), "alloc");
+        HIPCHK(h, h->dalloc(&b.mask, g.n), "alloc");
+      }
+      SweepArgs a;
+      a.nt = g.nt; a.n = g.n; a.s = g.s; a.t = g.t;
+      a.v = h->v;
+      a.rowptr = g.rowptr; a.col = g.col; a.ccap = g.ccap; a.cs = g.cs; a.ct = g.ct;
+      a.cst = g.cst;
+      a.fx_k = g.fx_k;
+      HIPCHK(h, sweep_run(a, b, h->stream), "sweep");
+      HIPCHK(h, hipMemcpyAsync(&best, b.best, sizeof(i128), hipMemcpyDeviceToHost, h->stream), "readback");
+      HIPCHK(h, hipMemcpyAsync(&ks, b.kstar, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream), "readback");
+      if (in_source_side)
+        HIPCHK(h, hipMemcpyAsync(in_source_side, b.mask, g.n, hipMemcpyDeviceToHost, h->stream), "readback");
+      HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+    } else if (in_source_side) {
+      in_source_side[g.s] = 1;
+      in_source_side[g.t] = 0;
+    }
+    if (cut_value) *cut_value = fx_to_double(h->D0 + best, g.fx_k);
+    if (k_star) *k_star = ks;
+    return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_potentials(irls_mincut_t h, double *x) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!x) { h->err = "x must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "not available for a batch handle"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "no potentials yet"; return IRLS_ERR_NOT_SOLVED; }
+  try {
+    const int64_t nt = h->g.nt;
+    std::vector<double> vn(nt);
+    if (nt > 0) HIPCHK(h, hipMemcpyAsync(vn.data(), h->v, nt * sizeof(double), hipMemcpyDeviceToHost, h->stream), "readback");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+    for (int64_t i = 0; i < nt; i++) x[orig_of(i, h->g.s, h->g.t)] = vn[i];
+    x[h->g.s] = 1.0;
+    x[h->g.t] = 0.0;
+    return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_set_potentials(irls_mincut_t h, const double *x) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!x) { h->err = "x must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "not available for a batch handle"; return IRLS_ERR_OPTIONS; }
+  try {
+    irls_status rc = load_x0(h, x);
+    if (rc != IRLS_OK) return rc;
+    h->solved = true;
+    return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_info(irls_mincut_t h, int64_t *n_nonterminal, int64_t *nnz_offdiag,
+                             int32_t *format, int32_t *n_diagonals, int32_t *solver,
+                             int32_t *rows_per_wave) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (n_nonterminal) *n_nonterminal = h->g.nt;
+  if (nnz_offdiag) *nnz_offdiag = h->g.nnz;
+  if (format) *format = h->g.format;
+  if (n_diagonals) *n_diagonals = h->g.K;
+  if (solver) *solver = h->solver;
+  if (rows_per_wave) *rows_per_wave = h->rpw;
+  return IRLS_OK;
+}
+
+irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps, double *avg_ms) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!avg_ms) { h->err = "avg_ms must not be NULL"; return IRLS_ERR_NULL; }
+  if (which < 0 || which > 1 || reps < 1) { h->err = "which must be 0 or 1, reps >= 1"; return IRLS_ERR_OPTIONS; }
+  if (h->batch || h->solver != 1) { h->err = "kernel timing needs the multi-workgroup solver"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
+  try {
+    // a private scalar block: beta = 0 and alpha = 0 make every launch
+    // idempotent (p = z, q = L~ z; v and r unchanged), done = 0 keeps it running
+    // The launches run on the live system of the last round with a private
+    // scalar block (iteration 1, done = 0, no stopping); the potentials are
+    // saved first and restored afterwards.
+    Scalars s;
+    std::memset(&s, 0, sizeof(s));
+    s.rho[0] = s.rho[1] = 1.0;
+    s.iter_a = s.iter_b = 1;
+    s.maxit = std::numeric_limits<int64_t>::max();
+    HIPCHK(h, hipMemcpy(h->sc_bench, &s, sizeof(s), hipMemcpyHostToDevice), "upload");
+    if (!h->vsave) HIPCHK(h, h->dalloc(&h->vsave, h->g.nt), "alloc");
+    HIPCHK(h, hipMemcpyAsync(h->vsave, h->v, h->g.nt * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "save");
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0), "event");
+    HIPCHK(h, hipEventCreate(&e1), "event");
+    auto one = [&](void) -> hipError_t {
+      if (h->opt.precision == 1) {
+        CGArgs<float> a = make_args<float>(h);
+        a.sc = h->sc_bench;
+        return which == 0 ? launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream) : launch_update(a, h->grid, h->stream);
+      }
+      CGArgs<double> a = make_args<double>(h);
+      a.sc = h->sc_bench;
+      return which == 0 ? launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream) : launch_update(a, h->grid, h->stream);
+    };
+    hipError_t e = one();
+    if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+    for (int i = 0; i < reps && e == hipSuccess; i++) e = one();
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_fail(h, e, "kernel timing");
+    HIPCHK(h, hipMemcpyAsync(h->v, h->vsave, h->g.nt * sizeof(double), hipMemcpyDeviceToDevice, h->stream), "restore");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+    *avg_ms = (double)ms / reps;
+    return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+void irls_mincut_destroy(irls_mincut_t h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  h->release();
+  delete h;
+}
+
+const char *irls_mincut_last_error(irls_mincut_t h) {
+  return h ? h->err.c_str() : g_thread_error.c_str();
+}
+
+irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t, const int64_t *, const int64_t *,
+                                     const int64_t *, const int64_t *, const double *,
+                                     const int64_t *, const int64_t *, const irls_options *, void *) {
+  if (out) *out = nullptr;
+  g_thread_error = "batched form not available in this build";
+  return IRLS_ERR_OPTIONS;
+}
+
+irls_status irls_mincut_solve_batch(irls_mincut_t h, irls_round_stats *) {
+  if (!h) return IRLS_ERR_NULL;
+  h->err = "not a batch handle";
+  return IRLS_ERR_OPTIONS;
+}
+
+irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *, double *) {
+  if (!h) return IRLS_ERR_NULL;
+  h->err = "not a batch handle";
+  return IRLS_ERR_OPTIONS;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Internal declarations of libirls_mincut (host driver <-> HIP kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/irls_mincut.h"
+
+namespace irls {
+
+constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
+constexpr int kMaxGrid = 1024;       // workgroups of the streaming kernels (grid-stride)
+constexpr int kMaxDiag = 8;          // most index offsets the diagonal format stores
+constexpr int kNumPartial = 8;       // reduction slots per workgroup
+
+// CG state shared between consecutive kernels of one solve, in device memory.
+// Only workgroup 0 of a kernel writes it, and never a field that the same
+// kernel reads: every kernel first reduces the per-workgroup partial sums of
+// its predecessor itself (fixed order, so every workgroup gets the same bits)
+// and derives alpha, beta and the stopping test from them.
+struct Scalars {
+  double rho[2];     // r^T z, by iteration parity
+  double bb;         // ||b||^2
+  double rr;         // ||r||^2 of the last stopping test
+  double alpha, beta, pq;
+  int64_t iter_a;    // index of the last SpMV started (written by the SpMV)
+  int64_t iter_b;    // CG iterations completed (written by the update)
+  int64_t maxit;
+  int32_t done;      // 1 once converged, at maxit, or broken down
+  int32_t status;    // IRLS_OK, IRLS_WARN_CG_MAXIT or IRLS_ERR_CG_BREAKDOWN
+  int32_t refine_every;  // precision 1: FP64 residual replacement period
+  int32_t pad;
+};
+
+// partial-sum slots (each kNumPartial x kMaxGrid doubles)
+enum { kPInit = 0, kPSpmv = 1, kPUpd = 2, kPRep = 3, kPStats = 4, kNumPSlots = 5 };
+
+// Everything a CG-phase kernel needs; passed by value.
+template <typename T>
+struct CGArgs {
+  int64_t nt;                     // non-terminal rows
+  // pattern (one of the two)
+  const int32_t *rowptr;          // CSR: [nt+1]
+  const int32_t *col;             // CSR: [nnz] neighbour rows, ascending
+  const double *ccap;             // CSR: [nnz] capacity of each entry's edge
+  int32_t K;                      // diagonal format: number of offsets
+  int32_t off[kMaxDiag];          // diagonal format: positive row offsets
+  const double *dcap;             // diagonal format: [K*nt] capacity of edge (u, u+off[k])
+  const double *cs, *ct;          // [nt] capacity to s / to t (0 = no edge)
+  // this round's system
+  T *w;                           // conductances: CSR [nnz] or diagonal [K*nt]
+  T *D;                           // diagonal of L~
+  double *w64, *D64;              // precision 1: FP64 copies for residual replacement
+  double *b;                      // [nt] b = conductance to s (FP64)
+  double *gt;                     // [nt] conductance to t (FP64)
+  // CG vectors
+  double *v;                      // potentials (FP64 always)
+  T *r, *q;
+  T *p0, *p1;                     // direction, double-buffered for the fused diagonal kernel
+  // reductions
+  double *partials;               // [kNumPSlots][kNumPartial][kMaxGrid]
+  Scalars *sc;
+  irls_round_stats *stat;         // this round's record
+  double eps, eps_next;
+  int32_t form;
+  int32_t round0;                 // conductance = capacity
+  int32_t warm;
+  int32_t weights_fp64;           // precision 1: compute conductances in FP64
+  double cst;                     // s-t capacity
+  double rtol;                    // CG stopping tolerance relative to ||b||
+};
+
+// Device arrays of one graph.
+struct GraphDev {
+  int64_t n = 0, s = 0, t = 0, nt = 0;
+  int64_t nnz = 0;                // stored off-diagonal CSR entries (2 per interior edge)
+  int32_t *rowptr = nullptr, *col = nullptr;
+  double *ccap = nullptr, *cs = nullptr, *ct = nullptr;
+  double cst = 0.0;
+  int32_t format = 1, K = 0;
+  int32_t off[kMaxDiag] = {0};
+  double *dcap = nullptr;
+  int32_t fx_k = 0;               // fixed-point scale of cut values
+  double cmax = 0.0;
+  bool no_source_edges = false;
+};
+
+struct SweepBufs {
+  uint64_t *keyA = nullptr, *keyB = nullptr;
+  uint32_t *idA = nullptr, *idB = nullptr;
+  uint32_t *rank = nullptr;
+  __int128 *delta = nullptr;      // per rank position
+  uint32_t *hist = nullptr;       // [256 * blocks]
+  __int128 *bsum = nullptr;       // per scan block
+  __int128 *bmin = nullptr;
+  int64_t *barg = nullptr;
+  __int128 *best = nullptr;       // [2]: best prefix, D0
+  int64_t *kstar = nullptr;
+  uint8_t *mask = nullptr;        // [n]
+  int sort_blocks = 0, scan_blocks = 0;
+};
+
+// ----------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ----------------------------------------------------------------------------
+template <typename T> hipError_t launch_assemble(const CGArgs<T> &a, int grid, hipStream_t st);
+template <typename T> hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st);
+template <typename T> hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave,
+                                             bool fused_dia, hipStream_t st);
+template <typename T> hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st);
+template <typename T> hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st);
+template <typename T> hipError_t launch_replace_residual(const CGArgs<T> &a, int grid,
+                                                         hipStream_t st);
+template <typename T> hipError_t launch_stats(const CGArgs<T> &a, int grid, hipStream_t st);
+hipError_t launch_fill(double *x, int64_t n, double value, hipStream_t st);
+hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every,
+                                hipStream_t st);
+
+// single-workgroup resident solver (one workgroup per graph of a batch)
+struct ResidentGraph {            // per graph, device array of these
+  int64_t node0;                  // first row in the concatenated non-terminal arrays
+  int64_t nt;
+  int64_t nnz0;                   // first CSR entry
+  double cst;
+  int32_t no_source_edges;
+  int32_t pad;
+};
+struct ResidentArgs {
+  int32_t G;
+  const ResidentGraph *graphs;
+  const int32_t *rowptr;          // per graph local row pointers, concatenated ([nt_g+1] each,
+                                  // at node0 + g)
+  const int32_t *col;             // local neighbour rows
+  const double *ccap;
+  const double *cs, *ct;
+  double *w, *D, *b, *gt, *v, *r, *p, *q;
+  irls_round_stats *stats;        // [G * (T+1)]
+  unsigned *next_graph;           // work-queue counter
+  const int32_t *order;           // graph processing order (largest first)
+  int32_t rounds;
+  double eps0, eps_factor;
+  int32_t form, init, warm;
+  double rtol;
+  int64_t maxit;
+};
+hipError_t launch_resident(const ResidentArgs &a, int grid, int block, hipStream_t st);
+
+// sweep
+struct SweepArgs {
+  int64_t nt, n, s, t;
+  const double *v;
+  const int32_t *rowptr, *col;
+  const double *ccap, *cs, *ct;
+  double cst;
+  int32_t fx_k;
+};
+hipError_t sweep_run(const SweepArgs &a, SweepBufs &b, hipStream_t st);
+size_t sweep_scan_blocks(int64_t nt);
+size_t sweep_sort_blocks(int64_t nt);
+
+}  // namespace irls

@@ -1,0 +1,320 @@
+// Sweep cut on the GPU (Section 3.4): order the non-terminal nodes by their
+// final potential (descending, ties by ascending id), evaluate every prefix
+// set S_k = {s} + first k nodes exactly, take the smallest k of least cut.
+//
+//   1. keys:    potential -> 64-bit key whose ascending order is descending x
+//   2. sort:    stable LSD radix sort, 8 passes of 8-bit digits; per pass a
+//               per-workgroup digit histogram, one exclusive scan over
+//               (digit, workgroup), and a stable scatter ranked with
+//               wavefront ballots
+//   3. rank:    rank[id] = position + 1
+//   4. delta:   cut(S_k) - cut(S_{k-1}) for the node entering at step k, in
+//               128-bit fixed point round(c 2^k): edges to nodes already in S
+//               leave the cut, edges to later nodes and to t enter it
+//   5. scan:    prefix sums of the deltas per workgroup, exclusive scan of the
+//               workgroup sums, then per-workgroup minimum and its first index
+//   6. mask:    source-side flag of every node
+#include "device_common.h"
+
+namespace irls {
+
+typedef __int128 i128;
+
+constexpr int kSortItems = 16;                       // keys per thread per sort tile
+constexpr int kSortTile = kBlock * kSortItems;       // 4096
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+size_t sweep_sort_blocks(int64_t nt) { return (size_t)((nt + kSortTile - 1) / kSortTile); }
+size_t sweep_scan_blocks(int64_t nt) { return (size_t)((nt + kScanTile - 1) / kScanTile); }
+
+// round-half-even(c * 2^k) for c >= 0, exact for every c >= 2^(52-k)
+__device__ __forceinline__ i128 fx_round(double c, int k) {
+  if (!(c > 0.0)) return 0;
+  uint64_t bits = (uint64_t)__double_as_longlong(c);
+  int ef = (int)((bits >> 52) & 0x7FF);
+  uint64_t mant = bits & ((1ull << 52) - 1);
+  int e2;
+  if (ef == 0) { e2 = -1074; } else { mant |= 1ull << 52; e2 = ef - 1075; }   // c = mant 2^e2
+  int sh = e2 + k;
+  if (sh >= 0) return ((i128)mant) << sh;
+  int r = -sh;
+  if (r >= 64) return 0;
+  uint64_t q = mant >> r, rem = mant & ((1ull << r) - 1), half = 1ull << (r - 1);
+  if (rem > half || (rem == half && (q & 1ull))) q++;
+  return (i128)q;
+}
+
+__device__ __forceinline__ int64_t orig_id(int64_t i, int64_t lo, int64_t hi) {
+  // non-terminal index -> node id (ids in ascending order skipping s and t)
+  if (i >= lo) i++;
+  if (i >= hi) i++;
+  return i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys(const double *v, int64_t nt, uint64_t *key, uint32_t *id) {
+  for (int64_t i = row_begin(); i < nt; i += row_stride()) {
+    double x = v[i];
+    uint64_t b = x == 0.0 ? 0ull : (uint64_t)__double_as_longlong(x);   // -0 -> +0
+    uint64_t asc = (b >> 63) ? ~b : (b | (1ull << 63));
+    key[i] = ~asc;
+    id[i] = (uint32_t)i;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hist(const uint64_t *key, int64_t nt, int shift, uint32_t *hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int it = 0; it < kSortItems; it++) {
+    int64_t i = base + (int64_t)it * kBlock + threadIdx.x;
+    if (i < nt) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of hist[256 * nb] (digit-major) in place, one workgroup
+__global__ __launch_bounds__(1024) void k_scan_hist(uint32_t *hist, int64_t total) {
+  __shared__ uint32_t part[1024];
+  const int64_t per = (total + 1023) / 1024;
+  const int64_t lo = (int64_t)threadIdx.x * per;
+  const int64_t hi = lo + per < total ? lo + per : total;
+  uint32_t s = 0;
+  for (int64_t i = lo; i < hi; i++) s += hist[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    uint32_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int64_t i = lo; i < hi; i++) {
+    uint32_t c = hist[i];
+    hist[i] = run;
+    run += c;
+  }
+}
+
+// stable scatter: sub-tiles of kBlock keys in order; within a sub-tile the
+// rank of a key among equal digits follows lane order inside a wavefront and
+// wavefront order inside the workgroup
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint64_t *kin, const uint32_t *iin,
+                                                     uint64_t *kout, uint32_t *iout, int64_t nt,
+                                                     int shift, const uint32_t *hist) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t cnt[kBlock / 64][256];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  base[threadIdx.x] = hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  for (int it = 0; it < kSortItems; it++) {
+    for (int w = 0; w < kBlock / 64; w++) cnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = tile + (int64_t)it * kBlock + threadIdx.x;
+    const bool valid = i < nt;
+    uint64_t k = valid ? kin[i] : 0ull;
+    uint32_t idv = valid ? iin[i] : 0u;
+    uint32_t d = (uint32_t)((k >> shift) & 255u);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; bit++) {
+      uint64_t bset = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? bset : ~bset;
+    }
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    if (valid && before == 0) cnt[wid][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + before;
+      for (int w = 0; w < wid; w++) pos += cnt[w][d];
+      kout[pos] = k;
+      iout[pos] = idv;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kBlock / 64; w++) add += cnt[w][threadIdx.x];
+    base[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank(const uint32_t *id, int64_t nt, uint32_t *rank) {
+  for (int64_t i = row_begin(); i < nt; i += row_stride()) rank[id[i]] = (uint32_t)(i + 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_delta(SweepArgs a, const uint32_t *rank, i128 *delta) {
+  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
+    const uint32_t ru = rank[u];
+    i128 d = fx_round(a.ct[u], a.fx_k) - fx_round(a.cs[u], a.fx_k);
+    for (int32_t e = a.rowptr[u]; e < a.rowptr[u + 1]; e++) {
+      i128 q = fx_round(a.ccap[e], a.fx_k);
+      d += rank[a.col[e]] > ru ? q : -q;
+    }
+    delta[ru - 1] = d;
+  }
+}
+
+// block sums of the deltas
+__global__ __launch_bounds__(kBlock) void k_bsum(const i128 *delta, int64_t nt, i128 *bsum) {
+  __shared__ i128 sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  i128 s = 0;
+  for (int j = 0; j < kScanItems; j++)
+    if (base + j < nt) s += delta[base + j];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of the nb block sums in place (one workgroup)
+__global__ __launch_bounds__(kBlock) void k_bscan(i128 *bsum, int64_t nb) {
+  __shared__ i128 part[kBlock];
+  const int64_t per = (nb + kBlock - 1) / kBlock;
+  const int64_t lo = (int64_t)threadIdx.x * per;
+  const int64_t hi = lo + per < nb ? lo + per : nb;
+  i128 s = 0;
+  for (int64_t i = lo; i < hi; i++) s += bsum[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    i128 add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : (i128)0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  i128 run = threadIdx.x ? part[threadIdx.x - 1] : (i128)0;
+  for (int64_t i = lo; i < hi; i++) {
+    i128 c = bsum[i];
+    bsum[i] = run;
+    run += c;
+  }
+}
+
+// per block: inclusive prefix values P_k (k = global position + 1), minimum
+// and the smallest k attaining it
+__global__ __launch_bounds__(kBlock) void k_bmin(const i128 *delta, int64_t nt, const i128 *boff,
+                                                 i128 *bmin, int64_t *barg) {
+  __shared__ i128 part[kBlock];
+  __shared__ i128 mv[kBlock];
+  __shared__ int64_t mk[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  i128 s = 0;
+  for (int j = 0; j < kScanItems; j++)
+    if (base + j < nt) s += delta[base + j];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    i128 add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : (i128)0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  i128 run = boff[blockIdx.x] + (threadIdx.x ? part[threadIdx.x - 1] : (i128)0);
+  i128 best = 0;
+  int64_t bk = -1;
+  for (int j = 0; j < kScanItems; j++) {
+    if (base + j >= nt) break;
+    run += delta[base + j];
+    if (bk < 0 || run < best) { best = run; bk = base + j + 1; }
+  }
+  mv[threadIdx.x] = best;
+  mk[threadIdx.x] = bk;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      int64_t k2 = mk[threadIdx.x + o];
+      if (k2 >= 0) {
+        int64_t k1 = mk[threadIdx.x];
+        i128 v2 = mv[threadIdx.x + o], v1 = mv[threadIdx.x];
+        if (k1 < 0 || v2 < v1 || (v2 == v1 && k2 < k1)) { mv[threadIdx.x] = v2; mk[threadIdx.x] = k2; }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { bmin[blockIdx.x] = mv[0]; barg[blockIdx.x] = mk[0]; }
+}
+
+// global minimum over blocks, including the empty prefix (k = 0, P_0 = 0)
+__global__ __launch_bounds__(kBlock) void k_final(const i128 *bmin, const int64_t *barg, int64_t nb,
+                                                  i128 *best, int64_t *kstar) {
+  __shared__ i128 mv[kBlock];
+  __shared__ int64_t mk[kBlock];
+  i128 b = 0;
+  int64_t k = 0;                                  // S_0 = {s}
+  for (int64_t i = threadIdx.x; i < nb; i += kBlock) {
+    int64_t k2 = barg[i];
+    if (k2 < 0) continue;
+    i128 v2 = bmin[i];
+    if (v2 < b || (v2 == b && k2 < k)) { b = v2; k = k2; }
+  }
+  mv[threadIdx.x] = b;
+  mk[threadIdx.x] = k;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      i128 v2 = mv[threadIdx.x + o], v1 = mv[threadIdx.x];
+      int64_t k2 = mk[threadIdx.x + o], k1 = mk[threadIdx.x];
+      if (v2 < v1 || (v2 == v1 && k2 < k1)) { mv[threadIdx.x] = v2; mk[threadIdx.x] = k2; }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { best[0] = mv[0]; kstar[0] = mk[0]; }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mask(SweepArgs a, const uint32_t *rank, const int64_t *kstar,
+                                                 uint8_t *mask) {
+  const int64_t ks = *kstar;
+  const int64_t lo = a.s < a.t ? a.s : a.t, hi = a.s < a.t ? a.t : a.s;
+  for (int64_t u = row_begin(); u < a.nt; u += row_stride())
+    mask[orig_id(u, lo, hi)] = (int64_t)rank[u] <= ks ? 1 : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) { mask[a.s] = 1; mask[a.t] = 0; }
+}
+
+static int grid_for(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > kMaxGrid) g = kMaxGrid;
+  return g < 1 ? 1 : (int)g;
+}
+
+hipError_t sweep_run(const SweepArgs &a, SweepBufs &b, hipStream_t st) {
+  const int64_t nt = a.nt;
+  if (nt > 0) {
+    const int gs = grid_for(nt);
+    const int nb = (int)sweep_sort_blocks(nt);
+    hipLaunchKernelGGL(k_keys, dim3(gs), dim3(kBlock), 0, st, a.v, nt, b.keyA, b.idA);
+    uint64_t *kin = b.keyA, *kout = b.keyB;
+    uint32_t *iin = b.idA, *iout = b.idB;
+    for (int pass = 0; pass < 8; pass++) {
+      const int shift = 8 * pass;
+      hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kBlock), 0, st, kin, nt, shift, b.hist);
+      hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, st, b.hist, (int64_t)256 * nb);
+      hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, kin, iin, kout, iout, nt, shift,
+                         (const uint32_t *)b.hist);
+      uint64_t *tk = kin; kin = kout; kout = tk;
+      uint32_t *ti = iin; iin = iout; iout = ti;
+    }
+    // eight passes: the sorted ids are back in idA
+    hipLaunchKernelGGL(k_rank, dim3(gs), dim3(kBlock), 0, st, (const uint32_t *)iin, nt, b.rank);
+    hipLaunchKernelGGL(k_delta, dim3(gs), dim3(kBlock), 0, st, a, (const uint32_t *)b.rank, b.delta);
+    const int sb = (int)sweep_scan_blocks(nt);
+    hipLaunchKernelGGL(k_bsum, dim3(sb), dim3(kBlock), 0, st, (const i128 *)b.delta, nt, b.bsum);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kBlock), 0, st, b.bsum, (int64_t)sb);
+    hipLaunchKernelGGL(k_bmin, dim3(sb), dim3(kBlock), 0, st, (const i128 *)b.delta, nt,
+                       (const i128 *)b.bsum, b.bmin, b.barg);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, st, (const i128 *)b.bmin,
+                       (const int64_t *)b.barg, (int64_t)sb, b.best, b.kstar);
+    hipLaunchKernelGGL(k_mask, dim3(gs), dim3(kBlock), 0, st, a, (const uint32_t *)b.rank,
+                       (const int64_t *)b.kstar, b.mask);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace irls
