@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run 5 plain device copies of MIB MiB (reference for byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -158,6 +160,17 @@ def main():
         print(f"[bench] spmv {spmv_ms*1e3:.1f} us ({achieved:.0f} GB/s), update {upd_ms*1e3:.1f} us",
               file=sys.stderr, flush=True)
     mc.close()
+
+    if args.calibrate_copy > 0:
+        nel = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copies: 5 x {args.calibrate_copy} MiB read + written",
+              file=sys.stderr, flush=True)
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

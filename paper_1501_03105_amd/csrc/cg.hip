@@ -47,7 +47,7 @@ __device__ __forceinline__ double edge_g(const CGArgs<T> &a, double c, double d)
 // ----------------------------------------------------------------------------
 template <typename T, bool DIA>
 __global__ __launch_bounds__(kBlock) void k_assemble(CGArgs<T> a) {
-  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
+  FOR_ROWS(u, a.nt) {
     const double vu = a.v[u];
     double diag = 0.0;
     if constexpr (DIA) {
@@ -115,7 +115,7 @@ template <typename T, bool DIA>
 __global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   double x[3] = {0.0, 0.0, 0.0};   // rho, bb, rr
-  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
+  FOR_ROWS(u, a.nt) {
     double bu = a.b[u];
     double ru;
     if (a.warm) {
@@ -125,8 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
       ru = bu;
     }
     T rt = (T)ru;
-    a.r[u] = rt;
-    double zu = (double)(rt / a.D[u]);
+    T zt = rt / a.D[u];
+    a.z[u] = zt;                               // z = M^-1 r is what CG keeps
+    double zu = (double)zt;
     x[0] += (double)rt * zu;
     x[1] += bu * bu;
     x[2] += (double)rt * (double)rt;
@@ -210,16 +211,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia(CGArgs<T> a) {
   const bool first = it == 0;
   const T *__restrict__ pin = (it & 1) ? a.p1 : a.p0;
   T *__restrict__ pout = (it & 1) ? a.p0 : a.p1;
-  const T *__restrict__ r = a.r;
+  const T *__restrict__ z = a.z;
   const T *__restrict__ D = a.D;
   const T *__restrict__ w = a.w;
   const int64_t nt = a.nt;
-  auto dir = [&](int64_t j) -> T {
-    T z = r[j] / D[j];
-    return first ? z : z + beta * pin[j];
-  };
+  auto dir = [&](int64_t j) -> T { return first ? z[j] : z[j] + beta * pin[j]; };
   double x[1] = {0.0};
-  for (int64_t u = row_begin(); u < nt; u += row_stride()) {
+  FOR_ROWS(u, nt) {
     const T pu = dir(u);
     T acc = D[u] * pu;
 #pragma unroll
@@ -235,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia(CGArgs<T> a) {
   write_partials<1>(x, a.partials, kPSpmv, lds);
 }
 
-// direction update for CSR: p = z + beta p (p = z on the first iteration)
+// direction update for CSR: p = z + beta p (p = z on the first iteration);
+// the CG kernels keep z = r / D in place of r
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_direction(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
@@ -245,9 +244,9 @@ __global__ __launch_bounds__(kBlock) void k_direction(CGArgs<T> a) {
   if (!cg_iteration_start(a, lds, bc, it, beta64)) return;
   const bool first = it == 0;
   const T beta = (T)beta64;
-  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
-    T z = a.r[u] / a.D[u];
-    a.p0[u] = first ? z : z + beta * a.p0[u];
+  FOR_ROWS(u, a.nt) {
+    const T zu = a.z[u];
+    a.p0[u] = first ? zu : zu + beta * a.p0[u];
   }
 }
 
@@ -305,12 +304,13 @@ __global__ __launch_bounds__(kBlock) void k_update(CGArgs<T> a) {
   const double alpha = sc->rho[it & 1] / pq;
   const T *__restrict__ p = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;   // fused diagonal kernel's output
   double x[2] = {0.0, 0.0};
-  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
+  FOR_ROWS(u, a.nt) {
     const T pu = p[u];
     a.v[u] += alpha * (double)pu;
-    T ru = (T)((double)a.r[u] - alpha * (double)a.q[u]);
-    a.r[u] = ru;
-    T zu = ru / a.D[u];
+    const T Du = a.D[u];
+    T ru = (T)((double)Du * (double)a.z[u] - alpha * (double)a.q[u]);   // r = D z - alpha q
+    T zu = ru / Du;
+    a.z[u] = zu;
     x[0] += (double)ru * (double)zu;
     x[1] += (double)ru * (double)ru;
   }
@@ -337,11 +337,11 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
   const bool conv_rec = sqrt(t2[1]) <= a.rtol * sqrt(sc->bb);
   if (!(conv_rec || i % sc->refine_every == 0)) return;
   double x[2] = {0.0, 0.0};
-  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
+  FOR_ROWS(u, a.nt) {
     double ru64 = a.b[u] - row_apply64<DIA>(a, u, a.v);
     T ru = (T)ru64;
-    a.r[u] = ru;
     T zu = ru / a.D[u];
+    a.z[u] = zu;
     x[0] += (double)ru * (double)zu;
     x[1] += (double)ru * (double)ru;
   }
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_stats(CGArgs<T> a) {
   const double *w = a.w64 ? a.w64 : (const double *)a.w;
   // slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v)
   double x[8] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY};
-  for (int64_t u = row_begin(); u < a.nt; u += row_stride()) {
+  FOR_ROWS(u, a.nt) {
     const double vu = a.v[u];
     for_each_nb<DIA>(a, u, [&](int64_t j, double c, int64_t wi) {
       if (j <= u) return;                       // each interior edge once

@@ -101,4 +101,29 @@ __device__ __forceinline__ void read_totals(const double *partials, int slot, in
 __device__ __forceinline__ int64_t row_begin() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int64_t row_stride() { return (int64_t)gridDim.x * blockDim.x; }
 
+// XCD-aware row ranges.  Workgroups are dispatched round-robin over the 8
+// XCDs, each with its own L2; workgroup b runs on XCD b % 8.  Giving each XCD
+// one contiguous slab of rows keeps the stencil neighbours of a row (offsets
+// 1, nx, nx*ny) in the same L2 except at slab boundaries.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void slab_rows(int64_t n, int64_t &begin, int64_t &end, int64_t &step) {
+  if (gridDim.x < kXcds || gridDim.x % kXcds != 0) {
+    begin = row_begin();
+    end = n;
+    step = row_stride();
+    return;
+  }
+  const int64_t x = blockIdx.x % kXcds, lb = blockIdx.x / kXcds, nb = gridDim.x / kXcds;
+  const int64_t slab = (n + kXcds - 1) / kXcds;
+  const int64_t lo = x * slab;
+  end = lo + slab < n ? lo + slab : n;
+  begin = lo + lb * blockDim.x + threadIdx.x;
+  step = nb * blockDim.x;
+}
+
+#define FOR_ROWS(u, n)                                   \
+  int64_t u##_b_, u##_e_, u##_s_;                        \
+  slab_rows((n), u##_b_, u##_e_, u##_s_);                \
+  for (int64_t u = u##_b_; u < u##_e_; u += u##_s_)
+
 }  // namespace irls

@@ -263,10 +263,12 @@ irls_status check_options(const irls_options &o, std::string &err) {
   return IRLS_OK;
 }
 
+// workgroups of the streaming kernels: a multiple of the 8 XCDs (see slab_rows)
 int grid_for(int64_t rows) {
   int64_t g = (rows + kBlock - 1) / kBlock;
+  g = (g + 7) / 8 * 8;
   if (g > kMaxGrid) g = kMaxGrid;
-  return g < 1 ? 1 : (int)g;
+  return g < 8 ? 8 : (int)g;
 }
 
 constexpr int64_t kResidentMaxRows = 32768;
@@ -356,7 +358,7 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.b = h->b;
   a.gt = h->gt;
   a.v = h->v;
-  a.r = (T *)h->r;
+  a.z = (T *)h->r;
   a.q = (T *)h->q;
   a.p0 = (T *)h->p0;
   a.p1 = (T *)h->p1;
@@ -389,8 +391,10 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
   // the stopping test of iteration i runs at the start of iteration i + 1, so
   // cg_maxit iterations need cg_maxit + 1 direction launches
   const int64_t maxit = h->opt.cg_maxit + 1;
-  int64_t first = pred > 0 ? std::max<int64_t>(16, pred * 7 / 8) : 64;
-  int64_t next = pred > 0 ? std::max<int64_t>(16, pred / 8) : 64;
+  // first chunk: the previous round's count (counts rarely fall between
+  // rounds); then small chunks, so at most two chunks run past convergence
+  int64_t first = pred > 0 ? std::max<int64_t>(16, pred) : 32;
+  int64_t next = pred > 0 ? 16 : 32;
   if (h->opt.chunk > 0) first = next = h->opt.chunk;
   first = std::min(first, maxit);
   HIPCHK(h, launch_iterations(h, a, first), "CG launch");
@@ -407,7 +411,6 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
       HIPCHK(h, hipEventRecord(h->ev[1 - slot], h->stream), "event");
       launched += c;
       queued = true;
-      next = std::min<int64_t>(next * 2, 4096);
     }
     HIPCHK(h, hipEventSynchronize(h->ev[slot]), "sync");
     if (h->pinned[slot].done) break;

@@ -57,7 +57,7 @@ struct CGArgs {
   double *gt;                     // [nt] conductance to t (FP64)
   // CG vectors
   double *v;                      // potentials (FP64 always)
-  T *r, *q;
+  T *z, *q;                       // z = M^-1 r (Jacobi), q = L~ p
   T *p0, *p1;                     // direction, double-buffered for the fused diagonal kernel
   // reductions
   double *partials;               // [kNumPSlots][kNumPartial][kMaxGrid]
