@@ -60,6 +60,25 @@ def spmv_bytes(info, precision):
     return nnz * (ts + 4) + (nt + 1) * 4 + nt * 3 * ts
 
 
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 summary, if the kernel
+    source is still the one that was profiled (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1501_03105_amd", "csrc", "cg.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("source_sha256_prefix") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(g, opts, gpu_iters_total, budget_s):
     """Oracle time per CG iteration on the first rounds of the same instance,
     scaled to the GPU run's total CG iterations, plus the oracle sweep."""
@@ -152,9 +171,10 @@ def main():
         upd_ms = mc.time_kernel(1, args.kernel_reps)
         nbytes = spmv_bytes(info, opts.get("precision", 0))
         achieved = nbytes / (spmv_ms * 1e-3) / 1e9
+        kname = "k_spmv_dia" if info["format"] == 2 else "k_spmv_csr"
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_spmv_dia" if info["format"] == 2 else "k_spmv_csr",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": profiled_traffic(kname, args.workload), "kernel": kname,
                 "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5),
                 "update_kernel_ms": round(upd_ms, 5)}
         print(f"[bench] spmv {spmv_ms*1e3:.1f} us ({achieved:.0f} GB/s), update {upd_ms*1e3:.1f} us",
