@@ -1,0 +1,83 @@
+"""The 128^3 segmentation workload at full size, in the launch configuration the
+benchmark times (multi-workgroup solver, diagonal format, FP64, 40 rounds,
+CG to 1e-8).  The oracle cannot run all 40 rounds here in test time, so the
+checks are ones it can compute at this size: the exact sweep of the GPU's
+potentials, the invariants of every round, and for sampled rounds the residual
+of the GPU's potentials in the oracle's own assembly of that round's system."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import gen
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+OPTS = dict(rounds=40, cg_rtol=1e-8, solver=1)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1501_03105_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def seg128():
+    return gen.grid3d_seg(128, seed=1)
+
+
+def test_fullsize_sweep_and_invariants(P, oracle_mod, seg128):
+    g = seg128
+    with P.MinCut.from_graph(g, **OPTS) as mc:
+        assert mc.info()["format"] == 2
+        rc, st = mc.solve()
+        x = mc.potentials()
+        inS, val, k = mc.cut()
+    assert rc == P.OK
+    So, vo, ko, _ = oracle_mod.sweep(g, x)
+    say(f"128^3: cut {val!r} k {k}; oracle sweep of the same x {vo!r} k {ko}")
+    assert val == vo and k == ko and np.array_equal(inS, So)
+    prev = np.inf
+    for l, r in enumerate(st):
+        assert r["true_rel_res"] <= 1.5e-8, l
+        assert r["vmin"] >= -1e-6 and r["vmax"] <= 1 + 1e-6, l          # Proposition 2
+        # Proposition 3 holds for exact solves; with the CG residual r the flows
+        # differ by v^T r and e^T r (checked exactly on sampled rounds below)
+        assert r["flow_s"] == pytest.approx(r["flow"], rel=1e-3), l
+        assert r["flow_t"] == pytest.approx(r["flow"], rel=1e-3), l
+        assert r["s_eps"] <= prev * (1 + 1e-9), l                        # MM descent
+        prev = r["s_eps"]
+    # chain: the sweep value is at most ||CBx||_1 of the same potentials
+    assert val <= st[-1]["l1"] * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("l", [1, 25])
+def test_fullsize_round_solves_oracle_system(P, oracle_mod, seg128, l):
+    """x(l) from the GPU solves the system the oracle assembles from the GPU's
+    x(l-1) to the CG tolerance (relative residual in FP64)."""
+    g = seg128
+    opts = dict(OPTS)
+    xs = []
+    for T in (l - 1, l):
+        opts["rounds"] = T
+        with P.MinCut.from_graph(g, **opts) as mc:
+            _, st = mc.solve()
+            xs.append(mc.potentials())
+    eps = 0.1 * 0.5 ** (l - 1)
+    rp, col, val, b = oracle_mod.reduced_system(g, xs[0], eps)
+    nt = g.n - 2
+    A = sp.csr_matrix((val, col, rp), shape=(nt, nt))
+    v = xs[1][:nt]                      # non-terminals are ids 0..nt-1 (s, t last)
+    r = b - A @ v
+    res = np.linalg.norm(r) / np.linalg.norm(b)
+    say(f"round {l}: relative residual of the GPU potentials in the oracle system {res:.2e}")
+    assert res <= 1.5e-8
+    # Proposition 3 with an inexact solve: x^T L x = flow_s - v^T r and
+    # flow_s - flow_t = e^T r (L annihilates constants)
+    R = st[l]
+    assert R["flow_s"] - R["flow"] == pytest.approx(v @ r, rel=1e-3, abs=1e-9 * R["flow"])
+    assert R["flow_s"] - R["flow_t"] == pytest.approx(r.sum(), rel=1e-3, abs=1e-9 * R["flow"])
