@@ -33,6 +33,9 @@ WORKLOADS = {
                "2-D 4-connected 64x64 grid, FP64, 30 rounds, eps 0.1 halved, Jacobi-PCG to 1e-10"),
     "seg256": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8),
                "3-D 6-connected 256^3 segmentation grid, FP64 (plain), 40 rounds, CG to 1e-8"),
+    "rmat512": (dict(kind="rmat", count=512, seed=1000), dict(rounds=30, cg_rtol=1e-8),
+                "512 R-MAT FlowImprove-style instances (2^10..2^17 nodes drawn, isolated nodes "
+                "dropped, average degree ~13), FP64, 30 rounds, CG to 1e-8, one persistent launch"),
     "seg256-mixed": (dict(kind="seg", N=256, seed=2),
                      dict(rounds=40, cg_rtol=1e-8, precision=1, refine_every=20),
                      "3-D 256^3 segmentation grid, FP32 conductances/SpMV/CG vectors, FP64 "
@@ -44,6 +47,8 @@ def make_graph(spec):
     import gen
     spec = dict(spec)
     kind = spec.pop("kind")
+    if kind == "rmat":
+        return gen.rmat_batch(spec["count"], first_seed=spec["seed"])
     if kind == "seg":
         return gen.grid3d_seg(spec["N"], seed=spec["seed"])
     return gen.grid2d(spec["nx"], spec["ny"], seed=spec["seed"])
@@ -108,6 +113,55 @@ def cpu_baseline(g, opts, gpu_iters_total, budget_s):
     }
 
 
+def bench_batch(args, spec, opts, desc):
+    """Batched form: cuts/s over the whole batch (solve + sweep of every graph)."""
+    import numpy as np
+    import torch
+
+    import paper_1501_03105_amd as P
+    t0 = time.perf_counter()
+    gs = make_graph(spec)
+    print(f"[bench] {len(gs)} graphs, {sum(g.n for g in gs)} nodes, generated in "
+          f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    mb = P.MinCutBatch(gs, stream=torch.cuda.current_stream(), **opts)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+
+    def step():
+        rc, st = mb.solve()
+        _, vals = mb.cut()
+        return st, vals
+
+    for i in range(args.warmup):
+        st, vals = step()
+        print(f"[bench] warmup {i}: CG iterations {sum(r['cg_iters'] for s in st for r in s)}",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        st, vals = step()
+        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = [sum(r["cg_iters"] for r in s) for s in st]
+    mb.close()
+    out = {
+        "metric": "IRLS s-t min-cut throughput of the batched form (cuts per second)",
+        "value": round(len(gs) * args.steps / dt, 3), "unit": "cuts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "graphs": len(gs),
+                   "nodes": int(sum(g.n for g in gs)),
+                   "interior_edges": int(sum(g.meta["interior"] for g in gs)),
+                   "cg_iters_total": int(sum(iters)), "cg_iters_max_graph": int(max(iters)),
+                   "setup_s": round(t_setup, 3)},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +187,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     spec, opts, desc = WORKLOADS[args.workload]
+    if spec["kind"] == "rmat":
+        return bench_batch(args, spec, opts, desc)
     t0 = time.perf_counter()
     g = make_graph(spec)
     t_gen = time.perf_counter() - t0

@@ -18,6 +18,7 @@ Edge order: interior edges first (per node in id order, +x, +y, +z), then
 source edges, then sink edges.  Every graph is returned as plain arrays;
 nothing here computes any part of the min-cut method.
 """
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -236,7 +237,7 @@ def rmat_flowimprove(seed, log2_lo=10.0, log2_hi=17.0, avg_degree=8, ball_frac=0
     keys = np.empty(0, np.int64)
     start = 0
     while True:
-        cnt = max(4 * want, 1024)
+        cnt = max(2 * want, 1024)
         a, b = _rmat_candidates(seed, scale, start, cnt)
         start += cnt
         ok = (a < n) & (b < n) & (a != b)
@@ -294,8 +295,22 @@ def rmat_flowimprove(seed, log2_lo=10.0, log2_hi=17.0, avg_degree=8, ball_frac=0
                            components=int(ncomp)))
 
 
-def rmat_batch(count=512, first_seed=1000, **kw):
-    return [rmat_flowimprove(first_seed + i, **kw) for i in range(count)]
+def _rmat_one(args):
+    seed, kw = args
+    return rmat_flowimprove(seed, **kw)
+
+
+def rmat_batch(count=512, first_seed=1000, workers=None, **kw):
+    """Instances first_seed .. first_seed+count-1 (each a pure function of its
+    seed), generated in parallel worker processes."""
+    seeds = [(first_seed + i, kw) for i in range(count)]
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or count < 4:
+        return [_rmat_one(a) for a in seeds]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_rmat_one, seeds, chunksize=1)
 
 
 # ----------------------------------------------------------------------------

@@ -127,7 +127,8 @@ irls_status irls_mincut_solve(irls_mincut_t h, const double *x0, irls_round_stat
 irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
                             int64_t *k_star);
 
-/* Copy the current potentials (n doubles, host; x_s = 1, x_t = 0). */
+/* Copy the current potentials (host; x_s = 1, x_t = 0): n doubles, or for a
+ * batch handle sum(n_g) doubles laid out like node_off. */
 irls_status irls_mincut_potentials(irls_mincut_t h, double *x);
 
 /* Replace the current potentials (n doubles, host or device per
@@ -159,8 +160,13 @@ void irls_mincut_destroy(irls_mincut_t h);
 const char *irls_mincut_last_error(irls_mincut_t h);
 
 /* ----------------------------------------------------------------------------
- * Batched form: G independent graphs solved together, one workgroup per graph
- * running every round of its graph inside one persistent kernel launch.
+ * Batched form (the paper's setting of many related min-cut problems, Section
+ * 6, run as independent instances): G graphs solved together in FP64, one
+ * 1024-thread workgroup per graph running every round of its graph inside one
+ * persistent kernel launch; workgroups take graphs from a queue, largest
+ * first.  Each solve replays a HIP graph captured at the first solve (queue
+ * reset + the persistent launch).  Options: precision 0, solver 0 or 2, init
+ * 0 or 1.  G <= 65536; node ids local to each graph.
  *   node_off[G+1], edge_off[G+1]   graph g owns nodes node_off[g]..node_off[g+1]-1
  *                                   and edges edge_off[g]..edge_off[g+1]-1
  *   edge_u, edge_v                 LOCAL node ids (0..n_g-1) of each graph

@@ -220,6 +220,85 @@ class MinCut:
         self.close()
 
 
+class MinCutBatch:
+    """Many independent graphs solved together: irls_mincut_create_batch /
+    _solve_batch / _cut_batch.  `graphs` are objects with n, eu, ev, cap, s, t
+    (local node ids)."""
+
+    def __init__(self, graphs, stream=None, **opts):
+        L = lib()
+        self.G = len(graphs)
+        self.opt = options(**opts)
+        ns = [int(g.n) for g in graphs]
+        ms = [int(len(g.eu)) for g in graphs]
+        self.node_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+        self.edge_off = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+        cat = lambda f, dt: (np.ascontiguousarray(np.concatenate([np.asarray(getattr(g, f)) for g in graphs]), dtype=dt)
+                             if self.edge_off[-1] > 0 else np.zeros(1, dt))
+        self._eu, self._ev, self._cap = cat("eu", np.int64), cat("ev", np.int64), cat("cap", np.float64)
+        self._s = np.array([g.s for g in graphs], np.int64)
+        self._t = np.array([g.t for g in graphs], np.int64)
+        P64 = C.POINTER(C.c_int64)
+        h = C.c_void_p()
+        rc = L.irls_mincut_create_batch(C.byref(h), self.G, self.node_off.ctypes.data_as(P64),
+                                        self.edge_off.ctypes.data_as(P64), self._eu.ctypes.data_as(P64),
+                                        self._ev.ctypes.data_as(P64),
+                                        self._cap.ctypes.data_as(C.POINTER(C.c_double)),
+                                        self._s.ctypes.data_as(P64), self._t.ctypes.data_as(P64),
+                                        C.byref(self.opt), _stream_ptr(stream))
+        if rc != OK:
+            raise IrlsError(rc, L.irls_mincut_last_error(None).decode())
+        self.h = h
+
+    def _err(self, rc):
+        return IrlsError(rc, lib().irls_mincut_last_error(self.h).decode())
+
+    def solve(self):
+        """Returns (status, stats[g][round])."""
+        T1 = self.opt.rounds + 1
+        st = (RoundStats * (self.G * T1))()
+        rc = lib().irls_mincut_solve_batch(self.h, st)
+        if rc not in (OK, WARN_CG_MAXIT):
+            raise self._err(rc)
+        flat = _stats_list(st)
+        return rc, [flat[g * T1:(g + 1) * T1] for g in range(self.G)]
+
+    def cut(self):
+        """Returns (list of source-side masks, array of cut values)."""
+        mask = np.zeros(int(self.node_off[-1]), np.uint8)
+        vals = np.zeros(self.G)
+        rc = lib().irls_mincut_cut_batch(self.h, mask.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                         vals.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc != OK:
+            raise self._err(rc)
+        m = mask.astype(bool)
+        return [m[self.node_off[g]:self.node_off[g + 1]] for g in range(self.G)], vals
+
+    def potentials(self):
+        x = np.zeros(int(self.node_off[-1]))
+        rc = lib().irls_mincut_potentials(self.h, x.ctypes.data_as(C.POINTER(C.c_double)))
+        if rc != OK:
+            raise self._err(rc)
+        return [x[self.node_off[g]:self.node_off[g + 1]] for g in range(self.G)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().irls_mincut_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def create_error(n, eu, ev, cap, s, t, **opts):
     """Status code irls_mincut_create returns for these arguments (0 = success)."""
     try:

@@ -273,6 +273,14 @@ int grid_for(int64_t rows) {
 
 constexpr int64_t kResidentMaxRows = 32768;
 
+// SpMV lanes per row: the power of two at or above the mean row length
+int lanes_for(int64_t rows, int64_t nnz) {
+  double avg = rows > 0 ? (double)nnz / (double)rows : 1.0;
+  int L = 1;
+  while (L < 64 && L < avg) L <<= 1;
+  return L;
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -300,10 +308,20 @@ struct irls_mincut_s {
   irls_round_stats *dstats = nullptr;
   Scalars *pinned = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  // resident solver
-  ResidentGraph *rgraphs = nullptr;
+  // resident solver (one graph, or every graph of a batch)
+  int32_t G = 1;
+  BatchGraph *rgraphs = nullptr;
   int32_t *rorder = nullptr;
   unsigned *rnext = nullptr;
+  int grid_res = 1;
+  // batch
+  std::vector<BatchGraph> hgraphs;
+  std::vector<i128> D0s;
+  uint32_t *gid = nullptr;
+  int64_t nodes_total = 0;
+  SweepBatchBufs swb;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
   SweepBufs sw;
   std::vector<void *> allocs;
 
@@ -322,6 +340,10 @@ struct irls_mincut_s {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    gexec = nullptr;
+    cap_stream = nullptr;
   }
 };
 
@@ -500,7 +522,7 @@ irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
   const irls_options &o = h->opt;
   ResidentArgs a;
   std::memset(&a, 0, sizeof(a));
-  a.G = 1;
+  a.G = h->G;
   a.graphs = h->rgraphs;
   a.rowptr = h->g.rowptr;
   a.col = h->g.col;
@@ -526,18 +548,42 @@ irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
   a.warm = o.warm_start;
   a.rtol = o.cg_rtol;
   a.maxit = o.cg_maxit;
-  HIPCHK(h, hipMemsetAsync(h->rnext, 0, sizeof(unsigned), h->stream), "queue reset");
-  HIPCHK(h, hipMemsetAsync(h->dstats, 0, (o.rounds + 1) * sizeof(irls_round_stats), h->stream), "stats reset");
-  HIPCHK(h, launch_resident(a, 1, 1024, h->stream), "resident solve");
-  std::vector<irls_round_stats> hs(o.rounds + 1);
+  const int64_t nrec = (int64_t)h->G * (o.rounds + 1);
+  if (h->batch) {
+    // the whole batched solve (queue reset + one persistent launch running
+    // every round of every graph) is captured once and replayed
+    if (!h->gexec) {
+      hipGraph_t graph = nullptr;
+      HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal), "capture");
+      hipError_t e1 = launch_resident_reset(h->rnext, h->dstats, nrec, h->cap_stream);
+      hipError_t e2 = launch_resident(a, h->grid_res, 1024, h->cap_stream);
+      hipError_t e3 = hipStreamEndCapture(h->cap_stream, &graph);
+      if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return dev_fail(h, e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "graph capture");
+      }
+      hipError_t e4 = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e4 != hipSuccess) { h->gexec = nullptr; return dev_fail(h, e4, "graph instantiate"); }
+    }
+    HIPCHK(h, hipGraphLaunch(h->gexec, h->stream), "graph launch");
+  } else {
+    HIPCHK(h, launch_resident_reset(h->rnext, h->dstats, nrec, h->stream), "reset");
+    HIPCHK(h, launch_resident(a, h->grid_res, 1024, h->stream), "resident solve");
+  }
+  std::vector<irls_round_stats> hs(nrec);
   HIPCHK(h, hipMemcpyAsync(hs.data(), h->dstats, hs.size() * sizeof(irls_round_stats),
                            hipMemcpyDeviceToHost, h->stream), "stats copy");
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
   if (stats) std::memcpy(stats, hs.data(), hs.size() * sizeof(irls_round_stats));
   irls_status result = IRLS_OK;
-  for (int l = 0; l <= o.rounds; l++) {
-    if (hs[l].status == IRLS_ERR_CG_BREAKDOWN) { h->err = "CG breakdown in round " + std::to_string(l); return IRLS_ERR_CG_BREAKDOWN; }
-    if (hs[l].status == IRLS_WARN_CG_MAXIT) result = IRLS_WARN_CG_MAXIT;
+  for (int64_t i = 0; i < nrec; i++) {
+    if (hs[i].status == IRLS_ERR_CG_BREAKDOWN) {
+      h->err = "CG breakdown in graph " + std::to_string(i / (o.rounds + 1)) + " round " +
+               std::to_string(i % (o.rounds + 1));
+      return IRLS_ERR_CG_BREAKDOWN;
+    }
+    if (hs[i].status == IRLS_WARN_CG_MAXIT) result = IRLS_WARN_CG_MAXIT;
   }
   return result;
 }
@@ -570,26 +616,29 @@ irls_status alloc_state(irls_mincut_t h) {
   HIPCHK(h, hipMemset(h->partials, 0, (size_t)kNumPSlots * kNumPartial * kMaxGrid * sizeof(double)), "memset");
   HIPCHK(h, h->dalloc(&h->sc, 1), "alloc");
   HIPCHK(h, h->dalloc(&h->sc_bench, 1), "alloc");
-  HIPCHK(h, h->dalloc(&h->dstats, h->opt.rounds + 1), "alloc");
+  HIPCHK(h, h->dalloc(&h->dstats, (int64_t)h->G * (h->opt.rounds + 1)), "alloc");
   HIPCHK(h, hipMemset(h->v, 0, std::max<int64_t>(nt, 1) * sizeof(double)), "memset");
   HIPCHK(h, hipHostMalloc((void **)&h->pinned, 2 * sizeof(Scalars), hipHostMallocDefault), "pinned alloc");
   std::memset(h->pinned, 0, 2 * sizeof(Scalars));
   HIPCHK(h, hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming), "event");
   HIPCHK(h, hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming), "event");
-  if (h->solver == 2) {
+  if (h->solver == 2 && !h->batch) {
     HIPCHK(h, h->dalloc(&h->rgraphs, 1), "alloc");
     HIPCHK(h, h->dalloc(&h->rorder, 1), "alloc");
     HIPCHK(h, h->dalloc(&h->rnext, 1), "alloc");
-    ResidentGraph rg;
+    BatchGraph rg;
     std::memset(&rg, 0, sizeof(rg));
-    rg.node0 = 0;
     rg.nt = nt;
-    rg.nnz0 = 0;
+    rg.s = h->g.s;
+    rg.t = h->g.t;
     rg.cst = h->g.cst;
+    rg.fx_k = h->g.fx_k;
+    rg.lanes = lanes_for(nt, h->g.nnz);
     rg.no_source_edges = h->g.no_source_edges ? 1 : 0;
     int32_t zero = 0;
     HIPCHK(h, hipMemcpy(h->rgraphs, &rg, sizeof(rg), hipMemcpyHostToDevice), "upload");
     HIPCHK(h, hipMemcpy(h->rorder, &zero, sizeof(zero), hipMemcpyHostToDevice), "upload");
+    h->rpw = 64 / rg.lanes;
   }
   return IRLS_OK;
 }
@@ -798,13 +847,20 @@ irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cu
 irls_status irls_mincut_potentials(irls_mincut_t h, double *x) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (!x) { h->err = "x must not be NULL"; return IRLS_ERR_NULL; }
-  if (h->batch) { h->err = "not available for a batch handle"; return IRLS_ERR_OPTIONS; }
   if (!h->solved) { h->err = "no potentials yet"; return IRLS_ERR_NOT_SOLVED; }
   try {
     const int64_t nt = h->g.nt;
     std::vector<double> vn(nt);
     if (nt > 0) HIPCHK(h, hipMemcpyAsync(vn.data(), h->v, nt * sizeof(double), hipMemcpyDeviceToHost, h->stream), "readback");
     HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+    if (h->batch) {                 // every graph, laid out like node_off
+      for (const BatchGraph &B : h->hgraphs) {
+        for (int64_t i = 0; i < B.nt; i++) x[B.node_off + orig_of(i, B.s, B.t)] = vn[B.node0 + i];
+        x[B.node_off + B.s] = 1.0;
+        x[B.node_off + B.t] = 0.0;
+      }
+      return IRLS_OK;
+    }
     for (int64_t i = 0; i < nt; i++) x[orig_of(i, h->g.s, h->g.t)] = vn[i];
     x[h->g.s] = 1.0;
     x[h->g.t] = 0.0;
@@ -907,24 +963,209 @@ const char *irls_mincut_last_error(irls_mincut_t h) {
   return h ? h->err.c_str() : g_thread_error.c_str();
 }
 
-irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t, const int64_t *, const int64_t *,
-                                     const int64_t *, const int64_t *, const double *,
-                                     const int64_t *, const int64_t *, const irls_options *, void *) {
-  if (out) *out = nullptr;
-  g_thread_error = "batched form not available in this build";
-  return IRLS_ERR_OPTIONS;
+irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t G, const int64_t *node_off,
+                                     const int64_t *edge_off, const int64_t *edge_u,
+                                     const int64_t *edge_v, const double *cap, const int64_t *s,
+                                     const int64_t *t, const irls_options *opt, void *hip_stream) {
+  if (!out) { g_thread_error = "out must not be NULL"; return IRLS_ERR_NULL; }
+  *out = nullptr;
+  irls_mincut_t h = nullptr;
+  try {
+    irls_options o;
+    if (opt) o = *opt; else irls_options_default(&o);
+    std::string err;
+    irls_status rc = check_options(o, err);
+    if (rc != IRLS_OK) { g_thread_error = err; return rc; }
+    if (o.precision != 0 || o.solver == 1 || o.init == 2) {
+      g_thread_error = "the batched form runs the FP64 resident solver and starts from W = C or x = 1/2";
+      return IRLS_ERR_OPTIONS;
+    }
+    if (G < 1 || G > 65536) { g_thread_error = "need 1 <= G <= 65536 graphs"; return IRLS_ERR_RANGE; }
+    if (!node_off || !edge_off || !s || !t) { g_thread_error = "offset and terminal arrays must not be NULL"; return IRLS_ERR_NULL; }
+    std::vector<int64_t> hno, heo, hs, ht, hu, hv;
+    std::vector<double> hc;
+    if (o.inputs_on_device) {
+      hno.resize(G + 1); heo.resize(G + 1); hs.resize(G); ht.resize(G);
+      if (hipMemcpy(hno.data(), node_off, (G + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(heo.data(), edge_off, (G + 1) * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hs.data(), s, G * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(ht.data(), t, G * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+        g_thread_error = "cannot read the device arrays";
+        return IRLS_ERR_DEVICE;
+      }
+      node_off = hno.data(); edge_off = heo.data(); s = hs.data(); t = ht.data();
+    }
+    if (node_off[0] != 0 || edge_off[0] != 0) { g_thread_error = "offsets must start at 0"; return IRLS_ERR_RANGE; }
+    for (int32_t g = 0; g < G; g++)
+      if (node_off[g + 1] < node_off[g] || edge_off[g + 1] < edge_off[g]) {
+        g_thread_error = "offsets must not decrease";
+        return IRLS_ERR_RANGE;
+      }
+    const int64_t M = edge_off[G];
+    if (M > 0 && (!edge_u || !edge_v || !cap)) { g_thread_error = "edge arrays must not be NULL"; return IRLS_ERR_NULL; }
+    if (o.inputs_on_device && M > 0) {
+      hu.resize(M); hv.resize(M); hc.resize(M);
+      if (hipMemcpy(hu.data(), edge_u, M * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hv.data(), edge_v, M * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hc.data(), cap, M * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+        g_thread_error = "cannot read the device edge arrays";
+        return IRLS_ERR_DEVICE;
+      }
+      edge_u = hu.data(); edge_v = hv.data(); cap = hc.data();
+    }
+    // per-graph set-up, concatenated rows and CSR entries
+    std::vector<int32_t> rowptr, col;
+    std::vector<double> ccap, cs, ct;
+    std::vector<BatchGraph> graphs(G);
+    std::vector<uint32_t> gid;
+    std::vector<i128> D0s(G);
+    int64_t rows = 0, nnz = 0;
+    for (int32_t g = 0; g < G; g++) {
+      HostGraph hg;
+      const int64_t e0 = edge_off[g];
+      rc = build_host_graph(hg, node_off[g + 1] - node_off[g], edge_off[g + 1] - e0, edge_u + e0,
+                            edge_v + e0, cap + e0, s[g], t[g], err);
+      if (rc != IRLS_OK) { g_thread_error = "graph " + std::to_string(g) + ": " + err; return rc; }
+      BatchGraph &B = graphs[g];
+      std::memset(&B, 0, sizeof(B));
+      B.node0 = rows;
+      B.nt = hg.nt;
+      B.nnz0 = nnz;
+      B.node_off = node_off[g];
+      B.s = s[g];
+      B.t = t[g];
+      B.cst = hg.cst;
+      B.fx_k = hg.fx_k;
+      B.lanes = lanes_for(hg.nt, (int64_t)hg.col.size());
+      B.no_source_edges = hg.no_source_edges ? 1 : 0;
+      D0s[g] = hg.D0;
+      rowptr.insert(rowptr.end(), hg.rowptr.begin(), hg.rowptr.end());
+      col.insert(col.end(), hg.col.begin(), hg.col.end());
+      ccap.insert(ccap.end(), hg.ccap.begin(), hg.ccap.end());
+      cs.insert(cs.end(), hg.cs.begin(), hg.cs.end());
+      ct.insert(ct.end(), hg.ct.begin(), hg.ct.end());
+      gid.insert(gid.end(), (size_t)hg.nt, (uint32_t)g);
+      rows += hg.nt;
+      nnz += (int64_t)hg.col.size();
+    }
+    if (rows >= (int64_t)INT32_MAX) { g_thread_error = "too many rows in the batch"; return IRLS_ERR_RANGE; }
+    // largest graphs first, so the longest solves start first
+    std::vector<int32_t> order(G);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      int64_t wx = graphs[x].nt + (int64_t)(x + 1 < G ? graphs[x + 1].nnz0 : nnz) - graphs[x].nnz0;
+      int64_t wy = graphs[y].nt + (int64_t)(y + 1 < G ? graphs[y + 1].nnz0 : nnz) - graphs[y].nnz0;
+      return wx > wy;
+    });
+    h = new irls_mincut_s();
+    h->opt = o;
+    h->stream = (hipStream_t)hip_stream;
+    h->batch = true;
+    h->G = G;
+    h->solver = 2;
+    h->hgraphs = graphs;
+    h->D0s = D0s;
+    h->nodes_total = node_off[G];
+    GraphDev &gd = h->g;
+    gd.n = node_off[G];
+    gd.nt = rows;
+    gd.nnz = nnz;
+    gd.format = 1;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+    h->grid_res = std::max(1, std::min(G, 2 * cus));
+    h->grid = grid_for(rows);
+    if ((rc = upload(h, &gd.rowptr, rowptr)) != IRLS_OK || (rc = upload(h, &gd.col, col)) != IRLS_OK ||
+        (rc = upload(h, &gd.ccap, ccap)) != IRLS_OK || (rc = upload(h, &gd.cs, cs)) != IRLS_OK ||
+        (rc = upload(h, &gd.ct, ct)) != IRLS_OK || (rc = upload(h, &h->rgraphs, graphs)) != IRLS_OK ||
+        (rc = upload(h, &h->rorder, order)) != IRLS_OK || (rc = upload(h, &h->gid, gid)) != IRLS_OK ||
+        (rc = alloc_state(h)) != IRLS_OK) {
+      g_thread_error = h->err;
+      h->release();
+      delete h;
+      return rc;
+    }
+    hipError_t e = h->dalloc(&h->rnext, 1);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      g_thread_error = std::string("batch set-up: ") + hipGetErrorString(e);
+      h->release();
+      delete h;
+      return e == hipErrorOutOfMemory ? IRLS_ERR_OOM : IRLS_ERR_DEVICE;
+    }
+    *out = h;
+    return IRLS_OK;
+  } catch (const std::bad_alloc &) {
+    if (h) { h->release(); delete h; }
+    g_thread_error = "host allocation failed";
+    return IRLS_ERR_OOM;
+  } catch (...) {
+    if (h) { h->release(); delete h; }
+    g_thread_error = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
 }
 
-irls_status irls_mincut_solve_batch(irls_mincut_t h, irls_round_stats *) {
-  if (!h) return IRLS_ERR_NULL;
-  h->err = "not a batch handle";
-  return IRLS_ERR_OPTIONS;
+irls_status irls_mincut_solve_batch(irls_mincut_t h, irls_round_stats *stats) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!h->batch) { h->err = "not a batch handle"; return IRLS_ERR_OPTIONS; }
+  try {
+    h->solved = false;
+    if (h->opt.init == 1 && h->g.nt > 0) HIPCHK(h, launch_fill(h->v, h->g.nt, 0.5, h->stream), "fill");
+    irls_status rc = solve_resident(h, stats);
+    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) h->solved = true;
+    return rc;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
 }
 
-irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *, double *) {
-  if (!h) return IRLS_ERR_NULL;
-  h->err = "not a batch handle";
-  return IRLS_ERR_OPTIONS;
+irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, double *cut_values) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!h->batch) { h->err = "not a batch handle"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "no potentials yet: call irls_mincut_solve_batch first"; return IRLS_ERR_NOT_SOLVED; }
+  try {
+    const int64_t rows = h->g.nt;
+    SweepBufs &b = h->sw;
+    if (!h->swb.kstar) {
+      const size_t nb = sweep_sort_blocks(rows), sb = sweep_scan_blocks(rows);
+      HIPCHK(h, h->dalloc(&b.keyA, rows), "alloc");
+      HIPCHK(h, h->dalloc(&b.keyB, rows), "alloc");
+      HIPCHK(h, h->dalloc(&b.idA, rows), "alloc");
+      HIPCHK(h, h->dalloc(&b.idB, rows), "alloc");
+      HIPCHK(h, h->dalloc(&b.rank, rows), "alloc");
+      HIPCHK(h, h->dalloc(&b.delta, rows), "alloc");
+      HIPCHK(h, h->dalloc(&b.hist, 256 * nb), "alloc");
+      HIPCHK(h, h->dalloc(&b.bsum, sb), "alloc");
+      HIPCHK(h, h->dalloc(&h->swb.best, h->G), "alloc");
+      HIPCHK(h, h->dalloc(&h->swb.mask, h->nodes_total), "alloc");
+      HIPCHK(h, h->dalloc(&h->swb.kstar, h->G), "alloc");
+    }
+    SweepBatchArgs a;
+    a.G = h->G;
+    a.rows = rows;
+    a.graphs = h->rgraphs;
+    a.gid = h->gid;
+    a.v = h->v;
+    a.rowptr = h->g.rowptr;
+    a.col = h->g.col;
+    a.ccap = h->g.ccap;
+    a.cs = h->g.cs;
+    a.ct = h->g.ct;
+    HIPCHK(h, sweep_batch_run(a, b, h->swb, h->stream), "batched sweep");
+    std::vector<i128> best(h->G);
+    HIPCHK(h, hipMemcpyAsync(best.data(), h->swb.best, h->G * sizeof(i128), hipMemcpyDeviceToHost, h->stream), "readback");
+    if (in_source_side)
+      HIPCHK(h, hipMemcpyAsync(in_source_side, h->swb.mask, h->nodes_total, hipMemcpyDeviceToHost, h->stream), "readback");
+    HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+    if (cut_values)
+      for (int32_t g = 0; g < h->G; g++) cut_values[g] = fx_to_double(h->D0s[g] + best[g], h->hgraphs[g].fx_k);
+    return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
 }
 
 }  // extern "C"

@@ -118,18 +118,23 @@ hipError_t launch_fill(double *x, int64_t n, double value, hipStream_t st);
 hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every,
                                 hipStream_t st);
 
-// single-workgroup resident solver (one workgroup per graph of a batch)
-struct ResidentGraph {            // per graph, device array of these
+// One graph of a batch (the single-graph resident solver uses one of these).
+// Rows of all graphs are concatenated; each graph keeps local CSR indices.
+struct BatchGraph {
   int64_t node0;                  // first row in the concatenated non-terminal arrays
-  int64_t nt;
-  int64_t nnz0;                   // first CSR entry
-  double cst;
+  int64_t nt;                     // rows of this graph
+  int64_t nnz0;                   // first CSR entry of this graph
+  int64_t node_off;               // first node id of this graph in the caller's arrays
+  int64_t s, t;                   // local source and sink
+  double cst;                     // s-t capacity
+  int32_t fx_k;                   // fixed-point scale of its cut values
+  int32_t lanes;                  // SpMV lanes per row (64 / rows per wavefront)
   int32_t no_source_edges;
   int32_t pad;
 };
 struct ResidentArgs {
   int32_t G;
-  const ResidentGraph *graphs;
+  const BatchGraph *graphs;
   const int32_t *rowptr;          // per graph local row pointers, concatenated ([nt_g+1] each,
                                   // at node0 + g)
   const int32_t *col;             // local neighbour rows
@@ -146,6 +151,7 @@ struct ResidentArgs {
   int64_t maxit;
 };
 hipError_t launch_resident(const ResidentArgs &a, int grid, int block, hipStream_t st);
+hipError_t launch_resident_reset(unsigned *next_graph, irls_round_stats *st, int64_t nrec, hipStream_t s);
 
 // sweep
 struct SweepArgs {
@@ -157,6 +163,23 @@ struct SweepArgs {
   int32_t fx_k;
 };
 hipError_t sweep_run(const SweepArgs &a, SweepBufs &b, hipStream_t st);
+
+// batched sweep: all graphs sorted at once by (graph, potential, id)
+struct SweepBatchArgs {
+  int32_t G;
+  int64_t rows;                   // total non-terminal rows
+  const BatchGraph *graphs;
+  const uint32_t *gid;            // [rows] graph of each row
+  const double *v;
+  const int32_t *rowptr, *col;
+  const double *ccap, *cs, *ct;
+};
+struct SweepBatchBufs {
+  int64_t *kstar = nullptr;       // [G]
+  __int128 *best = nullptr;       // [G] least prefix value of each graph
+  uint8_t *mask = nullptr;        // [total nodes]
+};
+hipError_t sweep_batch_run(const SweepBatchArgs &a, SweepBufs &b, SweepBatchBufs &bb, hipStream_t st);
 size_t sweep_scan_blocks(int64_t nt);
 size_t sweep_sort_blocks(int64_t nt);
 

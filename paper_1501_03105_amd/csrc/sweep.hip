@@ -278,6 +278,104 @@ __global__ __launch_bounds__(kBlock) void k_mask(SweepArgs a, const uint32_t *ra
   if (blockIdx.x == 0 && threadIdx.x == 0) { mask[a.s] = 1; mask[a.t] = 0; }
 }
 
+// ----------------------------------------------------------------------------
+// batched sweep
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_gidkey(const uint32_t *id, const uint32_t *gid, int64_t n,
+                                                   uint64_t *key) {
+  for (int64_t i = row_begin(); i < n; i += row_stride()) key[i] = gid[id[i]];
+}
+
+// sorted by (graph, potential desc, id): rank inside the graph
+__global__ __launch_bounds__(kBlock) void k_rank_batch(const uint32_t *id, const uint32_t *gid,
+                                                       const BatchGraph *gs, int64_t n, uint32_t *rank) {
+  for (int64_t i = row_begin(); i < n; i += row_stride()) {
+    const uint32_t u = id[i];
+    rank[u] = (uint32_t)(i - gs[gid[u]].node0 + 1);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_delta_batch(SweepBatchArgs a, const uint32_t *rank, i128 *delta) {
+  for (int64_t u = row_begin(); u < a.rows; u += row_stride()) {
+    const BatchGraph G = a.graphs[a.gid[u]];
+    const int64_t lu = u - G.node0;
+    const int32_t *rp = a.rowptr + G.node0 + a.gid[u];
+    const uint32_t ru = rank[u];
+    i128 d = fx_round(a.ct[u], G.fx_k) - fx_round(a.cs[u], G.fx_k);
+    for (int32_t e = rp[lu]; e < rp[lu + 1]; e++) {
+      const int64_t j = G.node0 + a.col[G.nnz0 + e];
+      const i128 q = fx_round(a.ccap[G.nnz0 + e], G.fx_k);
+      d += rank[j] > ru ? q : -q;
+    }
+    delta[G.node0 + ru - 1] = d;
+  }
+}
+
+// in-place inclusive prefix sums of the deltas (tile offsets from k_bscan)
+__global__ __launch_bounds__(kBlock) void k_prefix(i128 *delta, int64_t nt, const i128 *boff) {
+  __shared__ i128 part[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  i128 s = 0;
+  for (int j = 0; j < kScanItems; j++)
+    if (base + j < nt) s += delta[base + j];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    i128 add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : (i128)0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  i128 run = boff[blockIdx.x] + (threadIdx.x ? part[threadIdx.x - 1] : (i128)0);
+  for (int j = 0; j < kScanItems; j++) {
+    if (base + j >= nt) break;
+    run += delta[base + j];
+    delta[base + j] = run;
+  }
+}
+
+// one workgroup per graph: least prefix (k = 0 included) and its smallest k
+__global__ __launch_bounds__(kBlock) void k_segmin(const i128 *P, const BatchGraph *gs, i128 *best,
+                                                   int64_t *kstar, uint8_t *mask) {
+  __shared__ i128 mv[kBlock];
+  __shared__ int64_t mk[kBlock];
+  const BatchGraph G = gs[blockIdx.x];
+  const i128 base = G.node0 > 0 ? P[G.node0 - 1] : (i128)0;
+  i128 b = 0;
+  int64_t k = 0;
+  for (int64_t i = threadIdx.x; i < G.nt; i += kBlock) {
+    const i128 v = P[G.node0 + i] - base;
+    if (v < b) { b = v; k = i + 1; }               // ascending i: first minimum kept
+  }
+  mv[threadIdx.x] = b;
+  mk[threadIdx.x] = k;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      i128 v2 = mv[threadIdx.x + o], v1 = mv[threadIdx.x];
+      int64_t k2 = mk[threadIdx.x + o], k1 = mk[threadIdx.x];
+      if (v2 < v1 || (v2 == v1 && k2 < k1)) { mv[threadIdx.x] = v2; mk[threadIdx.x] = k2; }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    best[blockIdx.x] = mv[0];
+    kstar[blockIdx.x] = mk[0];
+    mask[G.node_off + G.s] = 1;
+    mask[G.node_off + G.t] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mask_batch(SweepBatchArgs a, const uint32_t *rank,
+                                                       const int64_t *kstar, uint8_t *mask) {
+  for (int64_t u = row_begin(); u < a.rows; u += row_stride()) {
+    const uint32_t g = a.gid[u];
+    const BatchGraph G = a.graphs[g];
+    const int64_t lo = G.s < G.t ? G.s : G.t, hi = G.s < G.t ? G.t : G.s;
+    mask[G.node_off + orig_id(u - G.node0, lo, hi)] = (int64_t)rank[u] <= kstar[g] ? 1 : 0;
+  }
+}
+
 static int grid_for(int64_t n) {
   int64_t g = (n + kBlock - 1) / kBlock;
   if (g > kMaxGrid) g = kMaxGrid;
@@ -314,6 +412,41 @@ hipError_t sweep_run(const SweepArgs &a, SweepBufs &b, hipStream_t st) {
     hipLaunchKernelGGL(k_mask, dim3(gs), dim3(kBlock), 0, st, a, (const uint32_t *)b.rank,
                        (const int64_t *)b.kstar, b.mask);
   }
+  return hipGetLastError();
+}
+
+hipError_t sweep_batch_run(const SweepBatchArgs &a, SweepBufs &b, SweepBatchBufs &bb, hipStream_t st) {
+  const int64_t n = a.rows;
+  if (n > 0) {
+    const int gs = grid_for(n);
+    const int nb = (int)sweep_sort_blocks(n);
+    hipLaunchKernelGGL(k_keys, dim3(gs), dim3(kBlock), 0, st, a.v, n, b.keyA, b.idA);
+    uint64_t *kin = b.keyA, *kout = b.keyB;
+    uint32_t *iin = b.idA, *iout = b.idB;
+    for (int pass = 0; pass < 10; pass++) {
+      if (pass == 8)       // then by graph: stable, so potential order survives inside a graph
+        hipLaunchKernelGGL(k_gidkey, dim3(gs), dim3(kBlock), 0, st, (const uint32_t *)iin, a.gid, n, kin);
+      const int shift = pass < 8 ? 8 * pass : 8 * (pass - 8);
+      hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kBlock), 0, st, kin, n, shift, b.hist);
+      hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, st, b.hist, (int64_t)256 * nb);
+      hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, kin, iin, kout, iout, n, shift,
+                         (const uint32_t *)b.hist);
+      uint64_t *tk = kin; kin = kout; kout = tk;
+      uint32_t *ti = iin; iin = iout; iout = ti;
+    }
+    hipLaunchKernelGGL(k_rank_batch, dim3(gs), dim3(kBlock), 0, st, (const uint32_t *)iin, a.gid,
+                       a.graphs, n, b.rank);
+    hipLaunchKernelGGL(k_delta_batch, dim3(gs), dim3(kBlock), 0, st, a, (const uint32_t *)b.rank, b.delta);
+    const int sb = (int)sweep_scan_blocks(n);
+    hipLaunchKernelGGL(k_bsum, dim3(sb), dim3(kBlock), 0, st, (const i128 *)b.delta, n, b.bsum);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(kBlock), 0, st, b.bsum, (int64_t)sb);
+    hipLaunchKernelGGL(k_prefix, dim3(sb), dim3(kBlock), 0, st, b.delta, n, (const i128 *)b.bsum);
+  }
+  hipLaunchKernelGGL(k_segmin, dim3(a.G), dim3(kBlock), 0, st, (const i128 *)b.delta, a.graphs, bb.best,
+                     bb.kstar, bb.mask);
+  if (n > 0)
+    hipLaunchKernelGGL(k_mask_batch, dim3(grid_for(n)), dim3(kBlock), 0, st, a, (const uint32_t *)b.rank,
+                       (const int64_t *)bb.kstar, bb.mask);
   return hipGetLastError();
 }
 
