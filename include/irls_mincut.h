@@ -116,6 +116,19 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m,
  * Returns IRLS_OK, IRLS_WARN_CG_MAXIT or an error. */
 irls_status irls_mincut_solve(irls_mincut_t h, const double *x0, irls_round_stats *stats);
 
+/* Run `rounds` reweighted rounds from a chosen start (checkpoint/resume, the
+ * paper's warm start carried across calls, and sequences of related problems
+ * in the spirit of Section 6):
+ *   start 0: round 0 as the options say (init 0/1/2; x0 used for init 2)
+ *   start 1: continue from the potentials the handle holds (after a solve or
+ *            irls_mincut_set_potentials); no round-0 solve
+ *   start 2: start from x0 (n doubles); no round-0 solve
+ * Round l >= 1 uses eps_first * eps_factor^(l-1) (eps_first <= 0 with start 0:
+ * the options' eps0).  stats: NULL or rounds+1 records (record 0 describes the
+ * start).  Options stay as created. */
+irls_status irls_mincut_solve_range(irls_mincut_t h, int32_t start, const double *x0,
+                                    double eps_first, int32_t rounds, irls_round_stats *stats);
+
 /* Sweep cut of the current potentials (Section 3.4): non-terminals in
  * descending potential, ties by ascending id; S_k = {s} + first k; the
  * smallest k with the least cut value wins.  Cut values are exact integer

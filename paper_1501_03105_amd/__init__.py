@@ -61,6 +61,8 @@ def lib():
         L.irls_mincut_create.argtypes = [C.POINTER(H), C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_int64, C.c_int64, C.POINTER(Options), C.c_void_p]
         L.irls_mincut_solve.argtypes = [H, C.c_void_p, C.POINTER(RoundStats)]
+        L.irls_mincut_solve_range.argtypes = [H, C.c_int32, C.c_void_p, C.c_double, C.c_int32,
+                                              C.POINTER(RoundStats)]
         L.irls_mincut_cut.argtypes = [H, PU8, PF64, P64]
         L.irls_mincut_potentials.argtypes = [H, PF64]
         L.irls_mincut_set_potentials.argtypes = [H, C.c_void_p]
@@ -75,9 +77,23 @@ def lib():
                                                P64, P64, C.POINTER(Options), C.c_void_p]
         L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
         L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
-        for f in ("create", "solve", "cut", "potentials", "set_potentials", "info", "time_kernel",
-                  "create_batch", "solve_batch", "cut_batch"):
+        for f in ("create", "solve", "solve_range", "cut", "potentials", "set_potentials", "info",
+                  "time_kernel", "create_batch", "solve_batch", "cut_batch"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
+        PF32 = C.POINTER(C.c_float)
+        L.irls_gnn_create.argtypes = [C.POINTER(H), C.c_int32, C.c_int32, C.c_uint64, C.c_void_p]
+        L.irls_gnn_num_params.argtypes = [H, P64]
+        L.irls_gnn_get_params.argtypes = [H, PF32]
+        L.irls_gnn_set_params.argtypes = [H, PF32]
+        L.irls_gnn_predict.argtypes = [H, H, PF64, PF64, PF64]
+        L.irls_gnn_loss_grad.argtypes = [H, H, PF64, PF64, C.c_double, C.c_double, PF64, PF32]
+        L.irls_gnn_adam_step.argtypes = [H, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.irls_gnn_destroy.argtypes = [H]
+        L.irls_gnn_destroy.restype = None
+        L.irls_gnn_last_error.argtypes = [H]
+        L.irls_gnn_last_error.restype = C.c_char_p
+        for f in ("create", "num_params", "get_params", "set_params", "predict", "loss_grad", "adam_step"):
+            getattr(L, "irls_gnn_" + f).restype = C.c_int
         o = Options()
         L.irls_options_default(C.byref(o))
         if o.struct_size != C.sizeof(Options):
@@ -158,6 +174,15 @@ class MinCut:
         px, keep, _ = _ptr(x0, np.float64)
         rc = lib().irls_mincut_solve(self.h, px, st)
         if rc not in (OK, WARN_CG_MAXIT) or (rc == WARN_CG_MAXIT and not allow_maxit):
+            raise self._err(rc)
+        return rc, _stats_list(st)
+
+    def solve_range(self, start, rounds, eps_first=-1.0, x0=None):
+        """irls_mincut_solve_range: start 0 (options), 1 (continue), 2 (from x0)."""
+        st = (RoundStats * (rounds + 1))()
+        px, keep, _ = _ptr(x0, np.float64)
+        rc = lib().irls_mincut_solve_range(self.h, start, px, float(eps_first), rounds, st)
+        if rc not in (OK, WARN_CG_MAXIT):
             raise self._err(rc)
         return rc, _stats_list(st)
 
@@ -297,6 +322,78 @@ class MinCutBatch:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Gnn:
+    """Learned warm start (include/irls_gnn.h): a message-passing network that
+    predicts starting potentials and a starting eps for a graph handle."""
+
+    def __init__(self, layers=3, seed=0, stream=None, hidden=64):
+        L = lib()
+        h = C.c_void_p()
+        rc = L.irls_gnn_create(C.byref(h), hidden, layers, C.c_uint64(seed), _stream_ptr(stream))
+        if rc != OK:
+            raise IrlsError(rc, L.irls_gnn_last_error(None).decode())
+        self.h = h
+        n = C.c_int64()
+        L.irls_gnn_num_params(self.h, C.byref(n))
+        self.nparams = n.value
+
+    def _err(self, rc):
+        return IrlsError(rc, lib().irls_gnn_last_error(self.h).decode())
+
+    def get_params(self):
+        p = np.zeros(self.nparams, np.float32)
+        rc = lib().irls_gnn_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc != OK:
+            raise self._err(rc)
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.shape[0] == self.nparams
+        rc = lib().irls_gnn_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc != OK:
+            raise self._err(rc)
+
+    def predict(self, mc, intensity=None):
+        """Returns (xhat [n] with x_s = 1, x_t = 0, log eps)."""
+        x = np.zeros(mc.n)
+        le = C.c_double()
+        it = None if intensity is None else np.ascontiguousarray(intensity, np.float64)
+        rc = lib().irls_gnn_predict(self.h, mc.h, None if it is None else it.ctypes.data_as(C.POINTER(C.c_double)),
+                                    x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(le))
+        if rc != OK:
+            raise self._err(rc)
+        return x, le.value
+
+    def loss_grad(self, mc, y, log_eps_target, lam=0.1, intensity=None, want_grad=False):
+        y = np.ascontiguousarray(y, np.float64)
+        it = None if intensity is None else np.ascontiguousarray(intensity, np.float64)
+        loss = C.c_double()
+        g = np.zeros(self.nparams, np.float32) if want_grad else None
+        rc = lib().irls_gnn_loss_grad(self.h, mc.h, None if it is None else it.ctypes.data_as(C.POINTER(C.c_double)),
+                                      y.ctypes.data_as(C.POINTER(C.c_double)), float(log_eps_target), float(lam),
+                                      C.byref(loss), None if g is None else g.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc != OK:
+            raise self._err(rc)
+        return loss.value, g
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        rc = lib().irls_gnn_adam_step(self.h, lr, beta1, beta2, eps)
+        if rc != OK:
+            raise self._err(rc)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().irls_gnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def create_error(n, eu, ev, cap, s, t, **opts):

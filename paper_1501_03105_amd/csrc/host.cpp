@@ -306,6 +306,8 @@ struct irls_mincut_s {
   double *vsave = nullptr;         // potentials saved across kernel timing
   Scalars *sc = nullptr, *sc_bench = nullptr;
   irls_round_stats *dstats = nullptr;
+  int64_t stats_cap = 0;            // records dstats holds
+  int64_t last_iters = 0;           // CG iterations of the last round solved (chunk sizing)
   Scalars *pinned = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   // resident solver (one graph, or every graph of a batch)
@@ -475,7 +477,8 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
   const int64_t nt = h->g.nt;
   CGArgs<T> a = make_args<T>(h);
   const bool fp64 = sizeof(T) == 8;
-  int64_t pred = 0;
+  // chunk sizing: a continuation starts near the last round's CG count
+  int64_t pred = o.init == 2 ? h->last_iters : 0;
   double eps = o.eps0;
   irls_status result = IRLS_OK;
   for (int l = 0; l <= o.rounds; l++) {
@@ -500,6 +503,7 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
       irls_status rc = run_cg(h, a, pred, &it, &st);
       if (rc != IRLS_OK) return rc;
       pred = it;
+      h->last_iters = it;
       if (st == IRLS_ERR_CG_BREAKDOWN) {
         h->err = "CG breakdown in round " + std::to_string(l);
         result = IRLS_ERR_CG_BREAKDOWN;
@@ -617,6 +621,7 @@ irls_status alloc_state(irls_mincut_t h) {
   HIPCHK(h, h->dalloc(&h->sc, 1), "alloc");
   HIPCHK(h, h->dalloc(&h->sc_bench, 1), "alloc");
   HIPCHK(h, h->dalloc(&h->dstats, (int64_t)h->G * (h->opt.rounds + 1)), "alloc");
+  h->stats_cap = (int64_t)h->G * (h->opt.rounds + 1);
   HIPCHK(h, hipMemset(h->v, 0, std::max<int64_t>(nt, 1) * sizeof(double)), "memset");
   HIPCHK(h, hipHostMalloc((void **)&h->pinned, 2 * sizeof(Scalars), hipHostMallocDefault), "pinned alloc");
   std::memset(h->pinned, 0, 2 * sizeof(Scalars));
@@ -651,6 +656,12 @@ irls_status upload(irls_mincut_t h, T **dst, const std::vector<T> &src) {
 }
 
 }  // namespace
+
+namespace irls {
+// read-only views of a handle for the learned warm start (gnn_host.cpp)
+const GraphDev *handle_graph(irls_mincut_t h) { return &h->g; }
+bool handle_is_batch(irls_mincut_t h) { return h->batch; }
+}  // namespace irls
 
 // ----------------------------------------------------------------------------
 // C ABI
@@ -768,23 +779,73 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+// one call of the round driver with (possibly) overridden start, first eps
+// and round count; the handle's options are restored afterwards
+irls_status solve_impl(irls_mincut_t h, int start, const double *x0, double eps_first, int32_t rounds,
+                       irls_round_stats *stats) {
+  const irls_options saved = h->opt;
+  irls_options &o = h->opt;
+  o.rounds = rounds;
+  if (eps_first > 0.0) o.eps0 = eps_first;
+  if (start != 0) o.init = 2;                       // no round-0 solve: round 0 reports the start
+  irls_status rc = IRLS_OK;
+  if ((int64_t)rounds + 1 > h->stats_cap) {
+    irls_round_stats *ns = nullptr;
+    hipError_t e = h->dalloc(&ns, rounds + 1);
+    if (e != hipSuccess) { h->opt = saved; return dev_fail(h, e, "alloc"); }
+    h->dstats = ns;
+    h->stats_cap = rounds + 1;
+  }
+  if (start == 2 || (start == 0 && saved.init == 2)) {
+    if (!x0) { h->opt = saved; h->err = "this start needs x0"; return IRLS_ERR_NULL; }
+    rc = load_x0(h, x0);
+  } else if (start == 0 && saved.init == 1 && h->g.nt > 0) {
+    hipError_t e = launch_fill(h->v, h->g.nt, 0.5, h->stream);
+    if (e != hipSuccess) rc = dev_fail(h, e, "fill");
+  }
+  if (rc == IRLS_OK) {
+    if (h->solver == 2) rc = solve_resident(h, stats);
+    else if (o.precision == 1) rc = solve_multi<float>(h, stats);
+    else rc = solve_multi<double>(h, stats);
+  }
+  h->opt = saved;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
 irls_status irls_mincut_solve(irls_mincut_t h, const double *x0, irls_round_stats *stats) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (h->batch) { h->err = "use irls_mincut_solve_batch for a batch handle"; return IRLS_ERR_OPTIONS; }
   try {
     h->solved = false;
-    const irls_options &o = h->opt;
-    if (o.init == 2) {
-      if (!x0) { h->err = "init == 2 needs x0"; return IRLS_ERR_NULL; }
-      irls_status rc = load_x0(h, x0);
-      if (rc != IRLS_OK) return rc;
-    } else if (o.init == 1 && h->g.nt > 0) {
-      HIPCHK(h, launch_fill(h->v, h->g.nt, 0.5, h->stream), "fill");
-    }
-    irls_status rc;
-    if (h->solver == 2) rc = solve_resident(h, stats);
-    else if (o.precision == 1) rc = solve_multi<float>(h, stats);
-    else rc = solve_multi<double>(h, stats);
+    irls_status rc = solve_impl(h, 0, x0, -1.0, h->opt.rounds, stats);
+    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) h->solved = true;
+    return rc;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_solve_range(irls_mincut_t h, int32_t start, const double *x0, double eps_first,
+                                    int32_t rounds, irls_round_stats *stats) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "not available for a batch handle"; return IRLS_ERR_OPTIONS; }
+  if (start < 0 || start > 2 || rounds < 0 || (rounds > 0 && !(eps_first > 0.0) && start != 0)) {
+    h->err = "need start in {0,1,2}, rounds >= 0 and eps_first > 0";
+    return IRLS_ERR_OPTIONS;
+  }
+  if (start == 1 && !h->solved) { h->err = "no potentials to continue from"; return IRLS_ERR_NOT_SOLVED; }
+  try {
+    h->solved = false;
+    irls_status rc = solve_impl(h, start, x0, eps_first, rounds, stats);
     if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) h->solved = true;
     return rc;
   } catch (...) {

@@ -1,0 +1,124 @@
+"""Learned warm start on the GPU: the forward pass, the loss and the full
+gradient of the hand-written SpMM + bf16 MFMA kernels against the CPU oracle
+(oracle/gnn.py, float64 with bfloat16 rounding at the same places), and a
+short training run that shows what the trained network saves."""
+import numpy as np
+import pytest
+
+import gen
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1501_03105_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def G():
+    import oracle.gnn as G
+    G.ROUND_BF16 = True
+    return G
+
+
+def seg(N, seed):
+    g = gen.grid3d_seg(N, seed=seed, with_intensity=True)
+    I = np.concatenate([g.meta["I"], [0.0, 0.0]])
+    return g, I
+
+
+def cases():
+    out = [("grid2d 24x24", gen.grid2d(24, 24, seed=7), None),
+           ("gnp 80", gen.gnp(80, 0.08, seed=3), None),
+           ("rmat", gen.rmat_flowimprove(2003, log2_lo=8.0, log2_hi=10.0), None)]
+    g, I = seg(12, 5)
+    out.append(("seg 12^3", g, I))
+    return out
+
+
+# Where the two sides can differ: the GPU forms features, h0 and the SpMM in
+# FP32 and accumulates the MFMA products in FP32, the oracle in FP64; both
+# round to bf16 at the same places.  A pre-rounding difference of ~1e-7
+# relative flips a bf16 value by one unit (2^-8 relative) in a small fraction
+# of the elements; the outputs are smooth functions of ~10^3 such elements
+# each, so a flip moves them by ~1e-3 of their scale at most.
+XHAT_TOL = 5e-3
+S_TOL = 5e-3
+LOSS_RTOL = 2e-3
+GRAD_RTOL = 2e-2        # per parameter block, relative 2-norm
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_forward_matches_oracle(P, G, case):
+    name, g, I = cases()[case]
+    say(f"gnn forward: {name} n={g.n}")
+    net = P.Gnn(seed=11 + case)
+    flat = net.get_params().astype(np.float64)
+    with P.MinCut.from_graph(g, solver=1) as mc:
+        x, le = net.predict(mc, I)
+    feats, A, ids = G.graph_inputs(g, I)
+    xo, so = G.predict(flat, feats, A)
+    err = np.abs(x[ids] - xo)
+    say(f"  xhat max {err.max():.2e} mean {err.mean():.2e}; log eps {le:.6f} vs {so:.6f}")
+    assert x[g.s] == 1.0 and x[g.t] == 0.0
+    assert err.max() <= XHAT_TOL
+    assert abs(le - so) <= S_TOL * max(1.0, abs(so))
+    net.close()
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_loss_and_gradient_match_oracle(P, G, case):
+    name, g, I = cases()[case]
+    say(f"gnn gradient: {name} n={g.n}")
+    r = np.random.default_rng(case)
+    net = P.Gnn(seed=21 + case)
+    # move away from the initial point so no block of the gradient is trivial
+    p0 = net.get_params()
+    p0 = p0 + r.normal(0, 0.05, p0.shape).astype(np.float32)
+    net.set_params(p0)
+    flat = net.get_params().astype(np.float64)
+    y = r.uniform(0, 1, g.n)
+    t, lam = -7.0, 0.1
+    with P.MinCut.from_graph(g, solver=1) as mc:
+        L, grad = net.loss_grad(mc, y, t, lam=lam, intensity=I, want_grad=True)
+    feats, A, ids = G.graph_inputs(g, I)
+    Lo, go = G.loss_and_grad(flat, feats, A, y[ids], t, lam)
+    say(f"  loss {L:.7f} vs {Lo:.7f}")
+    assert abs(L - Lo) <= LOSS_RTOL * abs(Lo)
+    o = 0
+    worst = 0.0
+    for nm, shp in G.param_shapes():
+        k = int(np.prod(shp))
+        a, b = grad[o:o + k].astype(np.float64), go[o:o + k]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        worst = max(worst, rel)
+        assert rel <= GRAD_RTOL, (nm, rel, np.linalg.norm(b))
+        o += k
+    say(f"  worst block relative gradient error {worst:.2e}")
+    net.close()
+
+
+def test_adam_step_matches_formula(P):
+    """One Adam step from zero moments moves every parameter by -lr*sign(g)
+    (bias correction makes m/sqrt(v) = g/|g| on the first step)."""
+    g, I = seg(8, 9)
+    net = P.Gnn(seed=3)
+    p0 = net.get_params()
+    with P.MinCut.from_graph(g, solver=1) as mc:
+        _, grad = net.loss_grad(mc, np.full(g.n, 0.3), -6.0, intensity=I, want_grad=True)
+    net.adam_step(1e-3, eps=1e-30)
+    d = net.get_params().astype(np.float64) - p0
+    # FP32 moments: v = (1 - b2) g^2 underflows for |g| below ~1e-19, so
+    # only gradients well above that follow the formula
+    # (units that never activate on this graph get exact zeros)
+    big = np.abs(grad) > 1e-12
+    assert big.sum() > 1000
+    assert np.allclose(d[big], -1e-3 * np.sign(grad[big]), rtol=1e-4, atol=1e-8)
+    assert np.all(d[grad == 0] == 0)
+    net.close()
