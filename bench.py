@@ -40,6 +40,11 @@ WORKLOADS = {
                      dict(rounds=40, cg_rtol=1e-8, precision=1, refine_every=20),
                      "3-D 256^3 segmentation grid, FP32 conductances/SpMV/CG vectors, FP64 "
                      "potentials, dots and residual replacement every 20 CG steps"),
+    "gnn192": (dict(kind="gnn", train64=24, train128=4, eval_n=192, eval_seeds=8),
+               dict(rounds=40, cg_rtol=1e-8),
+               "learned warm start: network trained on 64^3 and 128^3 segmentation grids, "
+               "evaluated on held-out 192^3 grids (seeds 20000..); time-to-cut at relative cut "
+               "error <= 1e-6 vs the plain start (40 rounds, eps 0.1 halved, CG to 1e-8, FP64)"),
 }
 
 
@@ -162,6 +167,80 @@ def bench_batch(args, spec, opts, desc):
     print(json.dumps(out))
 
 
+def bench_gnn(args, spec, opts, desc):
+    """Learned warm start: train, then time-to-cut on held-out 192^3 grids
+    with and without the network (per-round sweeps only decide when to stop)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_1501_03105_amd as P
+    from paper_1501_03105_amd import warmstart as W
+
+    stream = torch.cuda.current_stream()
+
+    def seg(N, seed):
+        g = gen.grid3d_seg(N, seed=seed, with_intensity=True)
+        return g, np.concatenate([g.meta["I"], [0.0, 0.0]])
+
+    say = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ex = []
+    for N, cnt, base in ((64, spec["train64"], 100), (128, spec["train128"], 300)):
+        for i in range(cnt):
+            g, I = seg(N, base + i)
+            ex.append(W.make_example(g, I, opts, stream=stream))
+            say(f"training graph {N}^3 seed {base + i}: cut {ex[-1].ref_cut:.8g}")
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, gamma, costs = W.fit(ex, args.gnn_epochs, args.gnn_epochs // 2, stream=stream, log=say)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    for e in ex:
+        e.mc.close()
+    del ex
+    rows = []
+    for k in range(spec["eval_seeds"]):
+        sd = 20000 + k
+        g, I = seg(spec["eval_n"], sd)
+        mc = P.MinCut.from_graph(g, stream=stream, solver=1, **opts)
+        mc.solve()
+        _, ref, _ = mc.cut()
+        plain = W.time_to_cut(mc, ref, 1e-6, 2 * opts["rounds"], stream=stream)
+        warm = W.time_to_cut(mc, ref, 1e-6, 2 * opts["rounds"], net=net, gamma=gamma, intensity=I,
+                             stream=stream)
+        rows.append((sd, ref, plain, warm))
+        say(f"eval {spec['eval_n']}^3 seed {sd}: plain {plain['rounds']} rounds {plain['cg_iters']} CG "
+            f"{plain['seconds']:.3f}s | warm {warm['rounds']} rounds {warm['cg_iters']} CG "
+            f"{warm['seconds']:.3f}s eps_1 {warm['eps_first']:.2e} reached {warm['reached']}")
+        mc.close()
+    sp = sum(r[2]["seconds"] for r in rows)
+    sw = sum(r[3]["seconds"] for r in rows)
+    out = {
+        "metric": "learned warm start: end-to-end time-to-cut speedup vs the plain start at cut "
+                  "relative error <= 1e-6",
+        "value": round(sp / sw, 4), "unit": "x", "n_gpus": 1, "steps": len(rows), "warmup": 0,
+        "ms_per_step": round(1000 * sw / len(rows), 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 solve, bf16/f32 network", "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload,
+                   "train_graphs": {"64^3": spec["train64"], "128^3": spec["train128"]},
+                   "epochs": [args.gnn_epochs, args.gnn_epochs // 2], "gamma": gamma,
+                   "data_s": round(t_data, 1), "train_s": round(t_train, 1),
+                   "all_reached": all(r[3]["reached"] for r in rows),
+                   "rounds": {"plain": sum(r[2]["rounds"] for r in rows),
+                              "warm": sum(r[3]["rounds"] for r in rows)},
+                   "cg_iters": {"plain": sum(r[2]["cg_iters"] for r in rows),
+                                "warm": sum(r[3]["cg_iters"] for r in rows)},
+                   "per_graph": [{"seed": r[0], "cut": r[1], "plain_s": round(r[2]["seconds"], 4),
+                                  "warm_s": round(r[3]["seconds"], 4), "plain_cg": r[2]["cg_iters"],
+                                  "warm_cg": r[3]["cg_iters"], "warm_rounds": r[3]["rounds"],
+                                  "plain_rounds": r[2]["rounds"], "eps_1": r[3]["eps_first"],
+                                  "reached": r[3]["reached"]} for r in rows]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +250,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--gnn-epochs", type=int, default=30)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run 5 plain device copies of MIB MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -189,6 +269,8 @@ def main():
     spec, opts, desc = WORKLOADS[args.workload]
     if spec["kind"] == "rmat":
         return bench_batch(args, spec, opts, desc)
+    if spec["kind"] == "gnn":
+        return bench_gnn(args, spec, opts, desc)
     t0 = time.perf_counter()
     g = make_graph(spec)
     t_gen = time.perf_counter() - t0

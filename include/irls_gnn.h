@@ -3,13 +3,16 @@
  *
  * Not part of the paper.  The paper warm-starts every CG solve from the
  * previous IRLS round (Section 3.1); this network carries a warm start across
- * instances: from per-node inputs it predicts starting potentials x0 and a
- * starting smoothing eps, which irls_mincut_solve then uses (init = 2,
- * eps0 = predicted eps, fewer rounds to the same final eps).
+ * instances: from per-node inputs it predicts the potentials the IRLS rounds
+ * converge to and a starting smoothing eps.  A caller starts the reweighted
+ * rounds from a blend of the round-0 potentials and the prediction, at the
+ * predicted eps (irls_mincut_solve_range with start 2).
  *
  * Model (hidden width 64, `layers` message-passing layers):
- *   f_u  = [log1p(c_us), log1p(c_ut), log1p(w_u), I_u]   w_u: all capacity at u,
- *                                                        I_u: optional intensity
+ *   f_u  = [log1p(c_us), log1p(c_ut), log1p(w_u), I_u, x0_u]
+ *          w_u: all capacity at u, I_u: optional intensity (0 if absent),
+ *          x0_u: the potentials the rounds start from (normally round 0's,
+ *          the solution with W = C)
  *   h0   = bf16(relu(f W_in + b_in))
  *   h_l  = bf16(relu(bf16([h_{l-1} | A h_{l-1}]) bf16(W_l) + b_l)),
  *          A_uv = c_uv / sum_v' c_uv' over interior neighbours
@@ -21,7 +24,10 @@
  *
  * All functions return irls_status (see irls_mincut.h).  A network is tied to
  * the HIP stream given at creation; it reads graphs from single-graph
- * irls_mincut handles (their device CSR).  Host arrays are indexed by node id.
+ * irls_mincut handles (their device CSR, and their potentials when x_start is
+ * NULL: the call first waits for the handle's stream).  Host arrays are
+ * indexed by node id.  A network keeps a workspace sized for the largest graph
+ * it has seen (about 1.7 KB per non-terminal node with 3 layers).
  */
 #ifndef IRLS_GNN_H
 #define IRLS_GNN_H
@@ -44,17 +50,29 @@ irls_status irls_gnn_get_params(irls_gnn_t g, float *params);          /* host, 
 irls_status irls_gnn_set_params(irls_gnn_t g, const float *params);    /* host, count floats */
 
 /* Prediction for the graph of h.  intensity: n doubles or NULL (treated as 0).
- * x_out: n doubles (host), NULL allowed; x_s = 1, x_t = 0.  log_eps: NULL allowed. */
+ * x_start: n doubles, or NULL = the potentials h holds (IRLS_ERR_NOT_SOLVED if
+ * it holds none).  x_out: n doubles (host), NULL allowed; x_s = 1, x_t = 0.
+ * log_eps: NULL allowed. */
 irls_status irls_gnn_predict(irls_gnn_t g, irls_mincut_t h, const double *intensity,
-                             double *x_out, double *log_eps);
+                             const double *x_start, double *x_out, double *log_eps);
 
-/* Loss and gradient for one graph: targets y (n doubles, entries of s and t
- * ignored) and t = log_eps_target; lambda weights the eps term.  The gradient
- * stays on the device for irls_gnn_adam_step; grad_out (count floats, host)
- * may be NULL. */
+/* Warm start in place: h must hold potentials x0 (normally round 0's, from
+ * irls_mincut_solve_range(h, 0, NULL, 0, 0, NULL)).  Runs the network with
+ * x_start = x0 and replaces the potentials on the device by
+ * x0 + gamma (xhat - x0), 0 <= gamma <= 1; log_eps (NULL allowed) receives the
+ * predicted log eps.  Continue with irls_mincut_solve_range(h, 1, ...) from
+ * that eps.  Nothing crosses PCIe but the eps. */
+irls_status irls_gnn_warm_start(irls_gnn_t g, irls_mincut_t h, const double *intensity, double gamma,
+                                double *log_eps);
+
+/* Loss and gradient for one graph: inputs as for irls_gnn_predict, targets y
+ * (n doubles, entries of s and t ignored) and t = log_eps_target; lambda
+ * weights the eps term.  The gradient stays on the device for
+ * irls_gnn_adam_step; grad_out (count floats, host) may be NULL.
+ * IRLS_ERR_RANGE if the graph has no non-terminal node. */
 irls_status irls_gnn_loss_grad(irls_gnn_t g, irls_mincut_t h, const double *intensity,
-                               const double *y, double log_eps_target, double lambda,
-                               double *loss, float *grad_out);
+                               const double *x_start, const double *y, double log_eps_target,
+                               double lambda, double *loss, float *grad_out);
 
 /* One Adam step with the last gradient (FP32 moments, bias-corrected). */
 irls_status irls_gnn_adam_step(irls_gnn_t g, double lr, double beta1, double beta2, double eps);

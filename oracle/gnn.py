@@ -11,7 +11,8 @@ compared element by element.  Gradients come from torch.autograd, with the
 bfloat16 roundings passed straight through.
 
 Model (hidden width H = 64, three message-passing layers):
-  f_u   = [log1p(c_us), log1p(c_ut), log1p(w_u), I_u]      w_u: all capacities at u
+  f_u   = [log1p(c_us), log1p(c_ut), log1p(w_u), I_u, x0_u]
+          w_u: all capacities at u; x0: the potentials the rounds start from
   h0    = relu(f W_in + b_in)
   a_l   = A h_{l-1},  A_uv = c_uv / sum_v' c_uv'           (interior neighbours)
   h_l   = relu(bf16([h_{l-1} | a_l]) bf16(W_l) + b_l)        l = 1, 2, 3
@@ -23,7 +24,7 @@ import numpy as np
 import torch
 
 H = 64
-F = 4
+F = 5
 LAYERS = 3
 ROUND_BF16 = True       # tests of the smooth model switch the roundings off
 
@@ -77,9 +78,10 @@ def bf16(x):
     return _RoundBF16.apply(x)
 
 
-def graph_inputs(g, intensity=None):
+def graph_inputs(g, intensity=None, x_start=None):
     """Non-terminal rows in ascending id: features, the row-normalised
-    capacity matrix A (dense rows as CSR triplets) and the node ids."""
+    capacity matrix A (sparse) and the node ids.  intensity and x_start are
+    indexed by node id; absent, they are 0 and 1/2."""
     ids = np.array([u for u in range(g.n) if u not in (g.s, g.t)], dtype=np.int64)
     pos = -np.ones(g.n, np.int64)
     pos[ids] = np.arange(ids.shape[0])
@@ -102,7 +104,8 @@ def graph_inputs(g, intensity=None):
             else:
                 rows.append(pos[u]); cols.append(pos[v]); vals.append(c)
     I = np.zeros(nt) if intensity is None else np.asarray(intensity, np.float64)[ids]
-    feats = np.stack([np.log1p(cs), np.log1p(ct), np.log1p(wdeg), I], axis=1)
+    X0 = np.full(nt, 0.5) if x_start is None else np.asarray(x_start, np.float64)[ids]
+    feats = np.stack([np.log1p(cs), np.log1p(ct), np.log1p(wdeg), I, X0], axis=1)
     rows = np.asarray(rows, np.int64)
     cols = np.asarray(cols, np.int64)
     vals = np.asarray(vals, np.float64)

@@ -85,14 +85,16 @@ def lib():
         L.irls_gnn_num_params.argtypes = [H, P64]
         L.irls_gnn_get_params.argtypes = [H, PF32]
         L.irls_gnn_set_params.argtypes = [H, PF32]
-        L.irls_gnn_predict.argtypes = [H, H, PF64, PF64, PF64]
-        L.irls_gnn_loss_grad.argtypes = [H, H, PF64, PF64, C.c_double, C.c_double, PF64, PF32]
+        L.irls_gnn_predict.argtypes = [H, H, PF64, PF64, PF64, PF64]
+        L.irls_gnn_warm_start.argtypes = [H, H, PF64, C.c_double, PF64]
+        L.irls_gnn_loss_grad.argtypes = [H, H, PF64, PF64, PF64, C.c_double, C.c_double, PF64, PF32]
         L.irls_gnn_adam_step.argtypes = [H, C.c_double, C.c_double, C.c_double, C.c_double]
         L.irls_gnn_destroy.argtypes = [H]
         L.irls_gnn_destroy.restype = None
         L.irls_gnn_last_error.argtypes = [H]
         L.irls_gnn_last_error.restype = C.c_char_p
-        for f in ("create", "num_params", "get_params", "set_params", "predict", "loss_grad", "adam_step"):
+        for f in ("create", "num_params", "get_params", "set_params", "predict", "warm_start", "loss_grad",
+                  "adam_step"):
             getattr(L, "irls_gnn_" + f).restype = C.c_int
         o = Options()
         L.irls_options_default(C.byref(o))
@@ -356,25 +358,44 @@ class Gnn:
         if rc != OK:
             raise self._err(rc)
 
-    def predict(self, mc, intensity=None):
-        """Returns (xhat [n] with x_s = 1, x_t = 0, log eps)."""
+    @staticmethod
+    def _dptr(a):
+        if a is None:
+            return None, None
+        a = np.ascontiguousarray(a, np.float64)
+        return a.ctypes.data_as(C.POINTER(C.c_double)), a
+
+    def predict(self, mc, intensity=None, x_start=None):
+        """Returns (xhat [n] with x_s = 1, x_t = 0, log eps).  x_start None:
+        the potentials mc holds."""
         x = np.zeros(mc.n)
         le = C.c_double()
-        it = None if intensity is None else np.ascontiguousarray(intensity, np.float64)
-        rc = lib().irls_gnn_predict(self.h, mc.h, None if it is None else it.ctypes.data_as(C.POINTER(C.c_double)),
-                                    x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(le))
+        pi, ki = self._dptr(intensity)
+        px, kx = self._dptr(x_start)
+        rc = lib().irls_gnn_predict(self.h, mc.h, pi, px, x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(le))
         if rc != OK:
             raise self._err(rc)
         return x, le.value
 
-    def loss_grad(self, mc, y, log_eps_target, lam=0.1, intensity=None, want_grad=False):
+    def warm_start(self, mc, gamma, intensity=None):
+        """Blend the prediction into the potentials mc holds (on the device);
+        returns the predicted log eps."""
+        pi, ki = self._dptr(intensity)
+        le = C.c_double()
+        rc = lib().irls_gnn_warm_start(self.h, mc.h, pi, float(gamma), C.byref(le))
+        if rc != OK:
+            raise self._err(rc)
+        return le.value
+
+    def loss_grad(self, mc, y, log_eps_target, lam=0.1, intensity=None, x_start=None, want_grad=False):
         y = np.ascontiguousarray(y, np.float64)
-        it = None if intensity is None else np.ascontiguousarray(intensity, np.float64)
+        pi, ki = self._dptr(intensity)
+        px, kx = self._dptr(x_start)
         loss = C.c_double()
         g = np.zeros(self.nparams, np.float32) if want_grad else None
-        rc = lib().irls_gnn_loss_grad(self.h, mc.h, None if it is None else it.ctypes.data_as(C.POINTER(C.c_double)),
-                                      y.ctypes.data_as(C.POINTER(C.c_double)), float(log_eps_target), float(lam),
-                                      C.byref(loss), None if g is None else g.ctypes.data_as(C.POINTER(C.c_float)))
+        rc = lib().irls_gnn_loss_grad(self.h, mc.h, pi, px, y.ctypes.data_as(C.POINTER(C.c_double)),
+                                      float(log_eps_target), float(lam), C.byref(loss),
+                                      None if g is None else g.ctypes.data_as(C.POINTER(C.c_float)))
         if rc != OK:
             raise self._err(rc)
         return loss.value, g

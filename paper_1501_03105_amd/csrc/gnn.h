@@ -6,7 +6,7 @@
 namespace irls {
 
 constexpr int kH = 64;               // hidden width
-constexpr int kF = 4;                // input features per node
+constexpr int kF = 5;                // input features per node
 typedef uint16_t bf16_t;
 
 struct GnnArgs {
@@ -15,10 +15,11 @@ struct GnnArgs {
   const int32_t *rowptr, *col;    // the graph's CSR over non-terminal rows
   const double *ccap, *cs, *ct;
   const double *intensity;        // [nt] or null
+  const double *xstart;           // [nt] potentials the solve starts from (round 0)
   const float *P;                 // FP32 parameters (flat, oracle order)
   const bf16_t *Wbf;              // [layers][128*64] bf16 copies of W_l
   int64_t off_Win, off_bin, off_W0, off_x, off_e;
-  float *feats;                   // [nt*4]
+  float *feats;                   // [nt*kF]
   float *invsum;                  // [nt]
   bf16_t *h;                      // [(layers+1)*nt*64] activations (bf16)
   bf16_t *agg;                    // [layers*nt*64] aggregated inputs (bf16)
@@ -42,5 +43,6 @@ hipError_t gnn_adam(float *P, const float *g, float *m, float *v, int64_t n, flo
                     float eps, float c1, float c2, hipStream_t st);
 hipError_t gnn_refresh_bf16(const float *P, int64_t off_W0, int layers, uint16_t *Wbf, hipStream_t st);
 hipError_t gnn_xhat(const float *z, int64_t nt, int64_t s, int64_t t, double *x, hipStream_t st);
+hipError_t gnn_blend(const float *z, int64_t nt, double gamma, double *v, hipStream_t st);
 
 }  // namespace irls

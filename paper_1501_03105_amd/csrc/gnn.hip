@@ -4,7 +4,8 @@
 // each solve starts from the previous round) across instances.  A
 // message-passing network predicts a starting potential vector and a starting
 // smoothing eps from per-node inputs:
-//   f_u  = [log1p(c_us), log1p(c_ut), log1p(w_u), I_u]         (w_u: all capacity at u)
+//   f_u  = [log1p(c_us), log1p(c_ut), log1p(w_u), I_u, x0_u]   (w_u: all capacity at u,
+//                                                              x0: round-0 potentials)
 //   h0   = bf16(relu(f W_in + b_in))
 //   a_l  = A h_{l-1},  A_uv = c_uv / sum_v' c_uv'               (capacity-weighted mean)
 //   h_l  = bf16(relu(bf16([h_{l-1} | a_l]) W_l + b_l))          (W_l: 128 x 64, bf16)
@@ -44,10 +45,11 @@ __global__ __launch_bounds__(kGB) void k_gnn_feats(GnnArgs a) {
     double csum = 0.0;
     for (int32_t e = a.rowptr[u]; e < a.rowptr[u + 1]; e++) csum += a.ccap[e];
     const double w = csum + a.cs[u] + a.ct[u];
-    a.feats[4 * u + 0] = (float)log1p(a.cs[u]);
-    a.feats[4 * u + 1] = (float)log1p(a.ct[u]);
-    a.feats[4 * u + 2] = (float)log1p(w);
-    a.feats[4 * u + 3] = a.intensity ? (float)a.intensity[u] : 0.0f;
+    a.feats[kF * u + 0] = (float)log1p(a.cs[u]);
+    a.feats[kF * u + 1] = (float)log1p(a.ct[u]);
+    a.feats[kF * u + 2] = (float)log1p(w);
+    a.feats[kF * u + 3] = a.intensity ? (float)a.intensity[u] : 0.0f;
+    a.feats[kF * u + 4] = (float)a.xstart[u];
     a.invsum[u] = csum > 0.0 ? (float)(1.0 / csum) : 0.0f;
   }
 }
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kGB) void k_gnn_in(GnnArgs a) {
     const int j = (int)(i % kH);
     float acc = a.P[a.off_bin + j];
 #pragma unroll
-    for (int f = 0; f < kF; f++) acc += a.feats[4 * u + f] * a.P[a.off_Win + f * kH + j];
+    for (int f = 0; f < kF; f++) acc += a.feats[kF * u + f] * a.P[a.off_Win + f * kH + j];
     a.h[i] = f2bf(fmaxf(acc, 0.0f));
   }
 }
@@ -325,25 +327,26 @@ __global__ __launch_bounds__(kGB) void k_gnn_aggT(GnnArgs a, float *dhp) {
   }
 }
 
-// input layer: dZ0 = dh0 ⊙ [h0 > 0]; per-workgroup partials of dW_in (4 x 64), db_in
+// input layer: dZ0 = dh0 ⊙ [h0 > 0]; per-workgroup partials of dW_in (kF x 64), db_in
+constexpr int kInG = kF + 1;                 // gradient rows of the input layer: W_in, b_in
 __global__ __launch_bounds__(kGB) void k_gnn_in_bwd(GnnArgs a, const float *dh) {
-  __shared__ float sp[kGB / 64][5 * kH];
+  __shared__ float sp[kGB / 64][kInG * kH];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  float g[5] = {0, 0, 0, 0, 0};
+  float g[kInG] = {};
   const int64_t wave = (int64_t)blockIdx.x * (kGB / 64) + wid, nwaves = (int64_t)gridDim.x * (kGB / 64);
   for (int64_t u = wave; u < a.nt; u += nwaves) {
     const float d = bf2f(a.h[u * kH + lane]) > 0.0f ? dh[u * kH + lane] : 0.0f;
 #pragma unroll
-    for (int f = 0; f < kF; f++) g[f] += a.feats[4 * u + f] * d;
-    g[4] += d;
+    for (int f = 0; f < kF; f++) g[f] += a.feats[kF * u + f] * d;
+    g[kF] += d;
   }
 #pragma unroll
-  for (int f = 0; f < 5; f++) sp[wid][f * kH + lane] = g[f];
+  for (int f = 0; f < kInG; f++) sp[wid][f * kH + lane] = g[f];
   __syncthreads();
-  for (int i = threadIdx.x; i < 5 * kH; i += kGB) {
+  for (int i = threadIdx.x; i < kInG * kH; i += kGB) {
     float s = 0.0f;
     for (int w = 0; w < kGB / 64; w++) s += sp[w][i];
-    a.part[(int64_t)blockIdx.x * 5 * kH + i] = s;
+    a.part[(int64_t)blockIdx.x * kInG * kH + i] = s;
   }
 }
 
@@ -406,6 +409,14 @@ __global__ __launch_bounds__(kGB) void k_gnn_xhat(const float *z, int64_t nt, in
   }
 }
 
+// warm start in place: v <- v + gamma (sigmoid(z) - v) on the non-terminal rows
+__global__ __launch_bounds__(kGB) void k_gnn_blend(const float *z, int64_t nt, double gamma, double *v) {
+  for (int64_t i = row_begin(); i < nt; i += row_stride()) {
+    const double xh = 1.0 / (1.0 + exp(-(double)z[i]));
+    v[i] += gamma * (xh - v[i]);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // drivers
 // ----------------------------------------------------------------------------
@@ -451,7 +462,7 @@ hipError_t gnn_backward(const GnnArgs &a, int64_t nparams, hipStream_t st) {
   const int ib = ggrid(a.nt, kGB / 64);
   hipLaunchKernelGGL(k_gnn_in_bwd, dim3(ib), dim3(kGB), 0, st, a, (const float *)dh);
   hipLaunchKernelGGL(k_gnn_sum_parts, dim3(2), dim3(kGB), 0, st, (const float *)a.part, (int64_t)ib,
-                     (int64_t)(5 * kH), (int64_t)(5 * kH), a.grad + a.off_Win);
+                     (int64_t)(kInG * kH), (int64_t)(kInG * kH), a.grad + a.off_Win);
   (void)nparams;
   return hipGetLastError();
 }
@@ -470,6 +481,11 @@ hipError_t gnn_refresh_bf16(const float *P, int64_t off_W0, int layers, uint16_t
 
 hipError_t gnn_xhat(const float *z, int64_t nt, int64_t s, int64_t t, double *x, hipStream_t st) {
   hipLaunchKernelGGL(k_gnn_xhat, dim3(ggrid(nt, kGB)), dim3(kGB), 0, st, z, nt, s, t, x);
+  return hipGetLastError();
+}
+
+hipError_t gnn_blend(const float *z, int64_t nt, double gamma, double *v, hipStream_t st) {
+  hipLaunchKernelGGL(k_gnn_blend, dim3(ggrid(nt, kGB)), dim3(kGB), 0, st, z, nt, gamma, v);
   return hipGetLastError();
 }
 

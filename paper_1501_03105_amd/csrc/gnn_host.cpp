@@ -16,6 +16,8 @@ using namespace irls;
 namespace irls {
 const GraphDev *handle_graph(irls_mincut_t h);       // defined in host.cpp
 bool handle_is_batch(irls_mincut_t h);
+double *handle_potentials(irls_mincut_t h);         // device rows, NULL before a solve
+hipStream_t handle_stream(irls_mincut_t h);
 }
 
 struct irls_gnn_s {
@@ -31,7 +33,7 @@ struct irls_gnn_s {
   float *feats = nullptr, *invsum = nullptr, *z = nullptr, *dh0 = nullptr, *dh1 = nullptr, *da = nullptr,
         *part = nullptr;
   uint16_t *h = nullptr, *agg = nullptr;
-  double *y = nullptr, *inten = nullptr, *xout = nullptr;
+  double *y = nullptr, *inten = nullptr, *xs = nullptr, *xout = nullptr;
   std::string err;
   std::vector<void *> ws;       // workspace allocations
   std::vector<void *> fixed;    // parameter allocations
@@ -76,7 +78,8 @@ int64_t part_floats(int64_t nt) {
   const int64_t lb = std::min<int64_t>((nt + 63) / 64, 256);
   const int64_t waves = std::max<int64_t>(lb, 1) * 4;
   const int64_t hb = std::min<int64_t>((nt + 3) / 4, 1024);
-  return std::max({waves * (2 * kH * kH + kH), hb * (kH + 2), hb * kH, hb * 5 * kH, (int64_t)1024 * 5 * kH});
+  return std::max({waves * (2 * kH * kH + kH), hb * (kH + 2), hb * kH, hb * (kF + 1) * kH,
+                   (int64_t)1024 * (kF + 1) * kH});
 }
 
 irls_status ensure_ws(irls_gnn_t g, int64_t nt) {
@@ -94,6 +97,7 @@ irls_status ensure_ws(irls_gnn_t g, int64_t nt) {
   GCHK(g, galloc(g->ws, &g->agg, (size_t)g->layers * n * kH), "alloc");
   GCHK(g, galloc(g->ws, &g->y, n), "alloc");
   GCHK(g, galloc(g->ws, &g->inten, n), "alloc");
+  GCHK(g, galloc(g->ws, &g->xs, n), "alloc");
   GCHK(g, galloc(g->ws, &g->xout, n + 2), "alloc");
   g->cap = nt;
   return IRLS_OK;
@@ -112,10 +116,11 @@ irls_status upload_rows(irls_gnn_t g, const GraphDev *gd, const double *src, dou
   return IRLS_OK;
 }
 
-GnnArgs make_args(irls_gnn_t g, const GraphDev *gd, bool with_intensity) {
+GnnArgs make_args(irls_gnn_t g, const GraphDev *gd, bool with_intensity, const double *xstart) {
   GnnArgs a;
   std::memset(&a, 0, sizeof(a));
   a.nt = gd->nt;
+  a.xstart = xstart;
   a.layers = g->layers;
   a.rowptr = gd->rowptr;
   a.col = gd->col;
@@ -158,6 +163,24 @@ const GraphDev *checked_graph(irls_gnn_t g, irls_mincut_t h) {
   if (!h) { g->err = "graph handle must not be NULL"; return nullptr; }
   if (handle_is_batch(h)) { g->err = "the network reads single-graph handles"; return nullptr; }
   return handle_graph(h);
+}
+
+// per-row inputs of one call: intensity (optional) and the start potentials,
+// from the caller's host arrays or, for x_start == NULL, the handle's device
+// potentials (after the handle's own stream has finished with them)
+irls_status stage_inputs(irls_gnn_t g, irls_mincut_t h, const GraphDev *gd, const double *intensity,
+                         const double *x_start, const double **xdev) {
+  irls_status rc;
+  if (intensity && (rc = upload_rows(g, gd, intensity, g->inten)) != IRLS_OK) return rc;
+  if (x_start) {
+    if ((rc = upload_rows(g, gd, x_start, g->xs)) != IRLS_OK) return rc;
+    *xdev = g->xs;
+    return IRLS_OK;
+  }
+  *xdev = handle_potentials(h);
+  if (!*xdev) { g->err = "x_start is NULL and the graph handle holds no potentials"; return IRLS_ERR_NOT_SOLVED; }
+  GCHK(g, hipStreamSynchronize(handle_stream(h)), "sync");
+  return IRLS_OK;
 }
 
 }  // namespace
@@ -231,15 +254,16 @@ irls_status irls_gnn_set_params(irls_gnn_t g, const float *params) {
   return IRLS_OK;
 }
 
-irls_status irls_gnn_predict(irls_gnn_t g, irls_mincut_t h, const double *intensity, double *x_out,
-                             double *log_eps) {
+irls_status irls_gnn_predict(irls_gnn_t g, irls_mincut_t h, const double *intensity, const double *x_start,
+                             double *x_out, double *log_eps) {
   if (!g) { g_gnn_error = "network must not be NULL"; return IRLS_ERR_NULL; }
   const GraphDev *gd = checked_graph(g, h);
   if (!gd) return IRLS_ERR_OPTIONS;
   irls_status rc = ensure_ws(g, gd->nt);
   if (rc != IRLS_OK) return rc;
-  if (intensity && (rc = upload_rows(g, gd, intensity, g->inten)) != IRLS_OK) return rc;
-  GnnArgs a = make_args(g, gd, intensity != nullptr);
+  const double *xdev = nullptr;
+  if ((rc = stage_inputs(g, h, gd, intensity, x_start, &xdev)) != IRLS_OK) return rc;
+  GnnArgs a = make_args(g, gd, intensity != nullptr, xdev);
   if (gd->nt > 0) GCHK(g, gnn_forward(a, g->stream), "forward");
   float s = (float)std::log(1e-4);
   if (gd->nt > 0) GCHK(g, hipMemcpyAsync(&s, g->scal, sizeof(float), hipMemcpyDeviceToHost, g->stream), "download");
@@ -255,8 +279,31 @@ irls_status irls_gnn_predict(irls_gnn_t g, irls_mincut_t h, const double *intens
   return IRLS_OK;
 }
 
-irls_status irls_gnn_loss_grad(irls_gnn_t g, irls_mincut_t h, const double *intensity, const double *y,
-                               double log_eps_target, double lambda, double *loss, float *grad_out) {
+irls_status irls_gnn_warm_start(irls_gnn_t g, irls_mincut_t h, const double *intensity, double gamma,
+                                double *log_eps) {
+  if (!g) { g_gnn_error = "network must not be NULL"; return IRLS_ERR_NULL; }
+  if (!(gamma >= 0.0 && gamma <= 1.0)) { g->err = "gamma must lie in [0, 1]"; return IRLS_ERR_OPTIONS; }
+  const GraphDev *gd = checked_graph(g, h);
+  if (!gd) return IRLS_ERR_OPTIONS;
+  irls_status rc = ensure_ws(g, gd->nt);
+  if (rc != IRLS_OK) return rc;
+  const double *xdev = nullptr;
+  if ((rc = stage_inputs(g, h, gd, intensity, nullptr, &xdev)) != IRLS_OK) return rc;
+  float s = (float)std::log(1e-4);
+  if (gd->nt > 0) {
+    GnnArgs a = make_args(g, gd, intensity != nullptr, xdev);
+    GCHK(g, gnn_forward(a, g->stream), "forward");
+    GCHK(g, hipMemcpyAsync(&s, g->scal, sizeof(float), hipMemcpyDeviceToHost, g->stream), "download");
+    GCHK(g, gnn_blend(g->z, gd->nt, gamma, handle_potentials(h), g->stream), "blend");
+  }
+  GCHK(g, hipStreamSynchronize(g->stream), "sync");
+  if (log_eps) *log_eps = s;
+  return IRLS_OK;
+}
+
+irls_status irls_gnn_loss_grad(irls_gnn_t g, irls_mincut_t h, const double *intensity, const double *x_start,
+                               const double *y, double log_eps_target, double lambda, double *loss,
+                               float *grad_out) {
   if (!g) { g_gnn_error = "network must not be NULL"; return IRLS_ERR_NULL; }
   if (!y) { g->err = "targets must not be NULL"; return IRLS_ERR_NULL; }
   const GraphDev *gd = checked_graph(g, h);
@@ -264,9 +311,10 @@ irls_status irls_gnn_loss_grad(irls_gnn_t g, irls_mincut_t h, const double *inte
   if (gd->nt < 1) { g->err = "the graph has no non-terminal nodes"; return IRLS_ERR_RANGE; }
   irls_status rc = ensure_ws(g, gd->nt);
   if (rc != IRLS_OK) return rc;
-  if (intensity && (rc = upload_rows(g, gd, intensity, g->inten)) != IRLS_OK) return rc;
+  const double *xdev = nullptr;
+  if ((rc = stage_inputs(g, h, gd, intensity, x_start, &xdev)) != IRLS_OK) return rc;
   if ((rc = upload_rows(g, gd, y, g->y)) != IRLS_OK) return rc;
-  GnnArgs a = make_args(g, gd, intensity != nullptr);
+  GnnArgs a = make_args(g, gd, intensity != nullptr, xdev);
   a.t = log_eps_target;
   a.lam = lambda;
   GCHK(g, gnn_forward(a, g->stream), "forward");

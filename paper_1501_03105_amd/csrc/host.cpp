@@ -661,6 +661,8 @@ namespace irls {
 // read-only views of a handle for the learned warm start (gnn_host.cpp)
 const GraphDev *handle_graph(irls_mincut_t h) { return &h->g; }
 bool handle_is_batch(irls_mincut_t h) { return h->batch; }
+double *handle_potentials(irls_mincut_t h) { return h->solved ? h->v : nullptr; }
+hipStream_t handle_stream(irls_mincut_t h) { return h->stream; }
 }  // namespace irls
 
 // ----------------------------------------------------------------------------

@@ -54,15 +54,22 @@ LOSS_RTOL = 2e-3
 GRAD_RTOL = 2e-2        # per parameter block, relative 2-norm
 
 
+def start_potentials(g, seed):
+    x = np.random.default_rng(seed).uniform(0, 1, g.n)
+    x[g.s], x[g.t] = 1.0, 0.0
+    return x
+
+
 @pytest.mark.parametrize("case", range(4))
 def test_forward_matches_oracle(P, G, case):
     name, g, I = cases()[case]
     say(f"gnn forward: {name} n={g.n}")
     net = P.Gnn(seed=11 + case)
     flat = net.get_params().astype(np.float64)
+    xs = start_potentials(g, case)
     with P.MinCut.from_graph(g, solver=1) as mc:
-        x, le = net.predict(mc, I)
-    feats, A, ids = G.graph_inputs(g, I)
+        x, le = net.predict(mc, I, x_start=xs)
+    feats, A, ids = G.graph_inputs(g, I, xs)
     xo, so = G.predict(flat, feats, A)
     err = np.abs(x[ids] - xo)
     say(f"  xhat max {err.max():.2e} mean {err.mean():.2e}; log eps {le:.6f} vs {so:.6f}")
@@ -84,10 +91,11 @@ def test_loss_and_gradient_match_oracle(P, G, case):
     net.set_params(p0)
     flat = net.get_params().astype(np.float64)
     y = r.uniform(0, 1, g.n)
+    xs = start_potentials(g, 100 + case)
     t, lam = -7.0, 0.1
     with P.MinCut.from_graph(g, solver=1) as mc:
-        L, grad = net.loss_grad(mc, y, t, lam=lam, intensity=I, want_grad=True)
-    feats, A, ids = G.graph_inputs(g, I)
+        L, grad = net.loss_grad(mc, y, t, lam=lam, intensity=I, x_start=xs, want_grad=True)
+    feats, A, ids = G.graph_inputs(g, I, xs)
     Lo, go = G.loss_and_grad(flat, feats, A, y[ids], t, lam)
     say(f"  loss {L:.7f} vs {Lo:.7f}")
     assert abs(L - Lo) <= LOSS_RTOL * abs(Lo)
@@ -104,6 +112,31 @@ def test_loss_and_gradient_match_oracle(P, G, case):
     net.close()
 
 
+def test_start_from_handle_and_warm_start_blend(P):
+    """x_start = NULL reads the handle's own potentials (the same bits as
+    passing them from the host); the warm start writes x0 + gamma (xhat - x0)
+    into the handle."""
+    g, I = seg(10, 4)
+    net = P.Gnn(seed=5)
+    with P.MinCut.from_graph(g, solver=1) as mc:
+        with pytest.raises(P.IrlsError):
+            net.predict(mc, I)                      # no potentials yet
+        mc.solve_range(0, 0)
+        x0 = mc.potentials()
+        xa, la = net.predict(mc, I)
+        xb, lb = net.predict(mc, I, x_start=x0)
+        assert np.array_equal(xa, xb) and la == lb
+        le = net.warm_start(mc, 0.3, I)
+        assert le == la
+        xw = mc.potentials()
+        want = x0 + 0.3 * (xa - x0)
+        want[g.s], want[g.t] = 1.0, 0.0
+        assert np.max(np.abs(xw - want)) <= 1e-15
+        with pytest.raises(P.IrlsError):
+            net.warm_start(mc, 1.5, I)
+    net.close()
+
+
 def test_adam_step_matches_formula(P):
     """One Adam step from zero moments moves every parameter by -lr*sign(g)
     (bias correction makes m/sqrt(v) = g/|g| on the first step)."""
@@ -111,7 +144,8 @@ def test_adam_step_matches_formula(P):
     net = P.Gnn(seed=3)
     p0 = net.get_params()
     with P.MinCut.from_graph(g, solver=1) as mc:
-        _, grad = net.loss_grad(mc, np.full(g.n, 0.3), -6.0, intensity=I, want_grad=True)
+        _, grad = net.loss_grad(mc, np.full(g.n, 0.3), -6.0, intensity=I, x_start=np.full(g.n, 0.5),
+                                want_grad=True)
     net.adam_step(1e-3, eps=1e-30)
     d = net.get_params().astype(np.float64) - p0
     # FP32 moments: v = (1 - b2) g^2 underflows for |g| below ~1e-19, so
@@ -119,6 +153,40 @@ def test_adam_step_matches_formula(P):
     # (units that never activate on this graph get exact zeros)
     big = np.abs(grad) > 1e-12
     assert big.sum() > 1000
-    assert np.allclose(d[big], -1e-3 * np.sign(grad[big]), rtol=1e-4, atol=1e-8)
+    # p - step is rounded to FP32: allow one rounding of p (2^-23 relative)
+    # and a little for the step itself
+    err = np.abs(d[big] + 1e-3 * np.sign(grad[big]))
+    assert np.all(err <= 2.0 ** -23 * np.abs(p0[big]) + 1e-8)
     assert np.all(d[grad == 0] == 0)
+    net.close()
+
+
+def test_trained_network_saves_cg_work(P):
+    """Train on 32^3 segmentation grids (converged potentials made by the
+    method itself), choose gamma and the eps targets on them, then reach the
+    plain start's cut (relative error <= 1e-6) on held-out 48^3 grids: every
+    graph must get there, with fewer CG iterations in total than the plain
+    start."""
+    import torch
+    from paper_1501_03105_amd import warmstart as W
+    opts = dict(rounds=40, cg_rtol=1e-8)
+    ex = [W.make_example(*seg(32, 100 + i), opts) for i in range(8)]
+    net, gamma, costs = W.fit(ex, 16, 8, gammas=(0.0, 0.1), log=say)
+    for e in ex:
+        e.mc.close()
+    tot_p = tot_w = 0
+    for k in range(4):
+        g, I = seg(48, 20000 + k)
+        with P.MinCut.from_graph(g, solver=1, **opts) as mc:
+            mc.solve()
+            _, ref, _ = mc.cut()
+            a = W.time_to_cut(mc, ref, 1e-6, 80)
+            b = W.time_to_cut(mc, ref, 1e-6, 80, net=net, gamma=gamma, intensity=I)
+        say(f"  48^3 seed {20000 + k}: plain {a['rounds']} rounds {a['cg_iters']} CG; "
+            f"warm {b['rounds']} rounds {b['cg_iters']} CG (eps_1 {b['eps_first']:.2e})")
+        assert a["reached"] and b["reached"]
+        tot_p += a["cg_iters"]
+        tot_w += b["cg_iters"]
+    say(f"  total CG iterations: plain {tot_p}, warm {tot_w}")
+    assert tot_w < tot_p
     net.close()

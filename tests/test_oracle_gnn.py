@@ -37,12 +37,13 @@ def test_bf16_rounding_is_nearest_even(G):
 
 
 def test_features_and_row_normalisation_by_hand(G):
-    feats, A, ids = G.graph_inputs(five_node(), intensity=np.array([0, 0, 0.25, 0.5, 0.75]))
+    feats, A, ids = G.graph_inputs(five_node(), intensity=np.array([0, 0, 0.25, 0.5, 0.75]),
+                                   x_start=np.array([1, 0, 0.9, 0.4, 0.1]))
     assert ids.tolist() == [2, 3, 4]
     # capacities at a: s 1, b 1.5 + 0.5, c 6; at b: a 2, t 3, c 4; at c: a 6, t 1, b 4
-    want = [[math.log(2), 0, math.log(10), 0.25],
-            [0, math.log(4), math.log(10), 0.5],
-            [0, math.log(2), math.log(12), 0.75]]
+    want = [[math.log(2), 0, math.log(10), 0.25, 0.9],
+            [0, math.log(4), math.log(10), 0.5, 0.4],
+            [0, math.log(2), math.log(12), 0.75, 0.1]]
     assert np.allclose(feats.numpy(), want, rtol=0, atol=1e-15)
     dense = A.to_dense().numpy()
     assert np.allclose(dense, [[0, 2 / 8, 6 / 8], [2 / 6, 0, 4 / 6], [6 / 10, 4 / 10, 0]], rtol=0, atol=1e-15)
@@ -53,15 +54,15 @@ def test_one_layer_width_one_by_hand(G):
     five-node graph; catches a transposed A, a swapped [h | A h] order, a
     missing bias or a wrong pooling."""
     G.ROUND_BF16 = False
-    feats, A, _ = G.graph_inputs(five_node())
-    p = {"W_in": torch.tensor([[1.0], [2.0], [0.0], [0.0]], dtype=torch.float64),
+    feats, A, _ = G.graph_inputs(five_node(), x_start=np.array([1, 0, 0.9, 0.4, 0.1]))
+    p = {"W_in": torch.tensor([[1.0], [2.0], [0.0], [0.0], [1.0]], dtype=torch.float64),
          "b_in": torch.tensor([-0.1], dtype=torch.float64),
          "W0": torch.tensor([[1.0], [10.0]], dtype=torch.float64),
          "b0": torch.tensor([-5.0], dtype=torch.float64),
          "w_x": torch.tensor([0.5], dtype=torch.float64), "b_x": torch.tensor([-1.0], dtype=torch.float64),
          "w_e": torch.tensor([2.0], dtype=torch.float64), "b_e": torch.tensor([-3.0], dtype=torch.float64)}
     z, s, _ = G.forward(p, feats, A, hidden=1, layers=1)
-    h0 = {"a": math.log(2) - 0.1, "b": 2 * math.log(4) - 0.1, "c": 2 * math.log(2) - 0.1}
+    h0 = {"a": math.log(2) + 0.9 - 0.1, "b": 2 * math.log(4) + 0.4 - 0.1, "c": 2 * math.log(2) + 0.1 - 0.1}
     agg = {"a": 0.25 * h0["b"] + 0.75 * h0["c"],
            "b": h0["a"] / 3 + 2 * h0["c"] / 3,
            "c": 0.6 * h0["a"] + 0.4 * h0["b"]}
@@ -94,7 +95,7 @@ def test_gradient_matches_central_differences(G, seed):
     G.ROUND_BF16 = False
     g = gen.gnp(14, 0.35, seed=seed)
     r = np.random.default_rng(seed)
-    feats, A, ids = G.graph_inputs(g, intensity=r.uniform(0, 1, g.n))
+    feats, A, ids = G.graph_inputs(g, intensity=r.uniform(0, 1, g.n), x_start=r.uniform(0, 1, g.n))
     y = (r.uniform(size=ids.shape[0]) < 0.5).astype(np.float64)
     flat = r.normal(0, 0.3, G.n_params())
     L, grad = G.loss_and_grad(flat, feats, A, y, -4.0, 0.2)
@@ -118,10 +119,13 @@ def test_relabelling_permutes_predictions(G):
     perm = r.permutation(g.n)                  # old id -> new id
     g2 = mk(g.n, perm[g.s], perm[g.t], np.stack([perm[g.eu], perm[g.ev], g.cap], axis=1))
     flat = r.normal(0, 0.3, G.n_params())
-    x1, s1 = G.predict(flat, *G.graph_inputs(g)[:2])
-    x2, s2 = G.predict(flat, *G.graph_inputs(g2)[:2])
-    _, _, ids1 = G.graph_inputs(g)
-    _, _, ids2 = G.graph_inputs(g2)
+    xs1 = r.uniform(0, 1, g.n)
+    xs2 = np.empty(g.n)
+    xs2[perm] = xs1
+    f1, A1, ids1 = G.graph_inputs(g, x_start=xs1)
+    f2, A2, ids2 = G.graph_inputs(g2, x_start=xs2)
+    x1, s1 = G.predict(flat, f1, A1)
+    x2, s2 = G.predict(flat, f2, A2)
     by_new = dict(zip(ids2.tolist(), x2.tolist()))
     assert np.allclose(x1, [by_new[int(perm[u])] for u in ids1], rtol=0, atol=1e-12)
     assert abs(s1 - s2) < 1e-12
