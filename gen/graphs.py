@@ -72,6 +72,33 @@ def grid2d(nx=64, ny=64, seed=0, cap_lo=0.1, cap_hi=1.0, term_lo=0.5, term_hi=2.
                  meta=dict(kind="grid2d", shape=(nx, ny), seed=seed, interior=mi))
 
 
+def grid3d_box(nx, ny, nn, seed=0, cap_lo=0.1, cap_hi=1.0, term_lo=0.5, term_hi=2.0):
+    """nn nodes numbered x + nx*y + nx*ny*z, 6-connected where both ends
+    exist: whole nx*ny planes and, if nx*ny does not divide nn, a partial
+    last plane.  s links the nodes of plane 0, t those of the last (partial)
+    plane.  Streams: 0 interior capacities, 1 source, 2 sink capacities."""
+    P = nx * ny
+    ids = np.arange(nn, dtype=np.int64)
+    x = ids % nx
+    y = (ids // nx) % ny
+    has = np.stack([(x < nx - 1) & (ids + 1 < nn), (y < ny - 1) & (ids + nx < nn), ids + P < nn], axis=1)
+    nbr = np.stack([ids + 1, ids + nx, ids + P], axis=1)
+    src = np.broadcast_to(ids[:, None], has.shape)[has]
+    dst = nbr[has]
+    mi = src.shape[0]
+    c_int = rng.uniform_range(seed, 0, mi, cap_lo, cap_hi)
+    s, t = nn, nn + 1
+    first = np.arange(min(P, nn), dtype=np.int64)
+    last = np.arange((nn - 1) // P * P, nn, dtype=np.int64)
+    c_s = rng.uniform_range(seed, 1, first.shape[0], term_lo, term_hi)
+    c_t = rng.uniform_range(seed, 2, last.shape[0], term_lo, term_hi)
+    eu = np.concatenate([src, np.full(first.shape[0], s, np.int64), last])
+    ev = np.concatenate([dst, first, np.full(last.shape[0], t, np.int64)])
+    cap = np.concatenate([c_int, c_s, c_t])
+    return Graph(nn + 2, s, t, eu, ev, cap,
+                 meta=dict(kind="grid3d_box", shape=(nx, ny), nodes=nn, seed=seed, interior=mi))
+
+
 # ----------------------------------------------------------------------------
 # G(n, p) for exhaustive checks
 # ----------------------------------------------------------------------------

@@ -146,36 +146,67 @@ __global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
 // vector update, or the FP64 residual replacement), the stopping test, and
 // beta = rho_i / rho_{i-1}.  Workgroup 0 publishes the state.  Returns false
 // when CG has stopped.
+// Start of a CG iteration, in two halves so that a kernel can issue its own
+// first loads in between.  The first half loads the scalar-block fields and
+// this thread's share of the vector update's partial sums (the usual
+// predecessor); the second reduces them together (the done flag by max), so
+// the kernel waits for one memory round trip before it knows whether and how
+// to run.  Every thread reads the flag; the max makes the workgroup agree,
+// and workgroups that read it at different times still agree, since each
+// computes the same stopping decision from the same partial sums.
+struct IterStartLoads {
+  int32_t done, refine;
+  int64_t i, maxit;
+  double bb, rho0, rho1;
+  double part[2];
+};
+
 template <typename T>
-__device__ bool cg_iteration_start(const CGArgs<T> &a, double *lds, double *bc, int64_t &i_out,
-                                   double &beta_out) {
+__device__ __forceinline__ IterStartLoads cg_iteration_load(const CGArgs<T> &a) {
+  const Scalars *sc = a.sc;
+  IterStartLoads l;
+  l.done = sc->done;
+  l.refine = sc->refine_every;
+  l.i = sc->iter_b;
+  l.maxit = sc->maxit;
+  l.bb = sc->bb;
+  l.rho0 = sc->rho[0];
+  l.rho1 = sc->rho[1];
+  partial_share<2>(a.partials, kPUpd, a.grid_main, l.part);
+  return l;
+}
+
+// Second half: the stopping test and beta = rho_i / rho_{i-1}; workgroup 0
+// publishes the state.  Returns false when CG has stopped.
+template <typename T>
+__device__ bool cg_iteration_finish(const CGArgs<T> &a, const IterStartLoads &l, double *lds, double *bc,
+                                    int64_t &i_out, double &beta_out) {
   Scalars *sc = a.sc;
-  if (block_done(sc)) return false;
-  const int nb = gridDim.x;
-  const int64_t i = sc->iter_b;
-  double rz, rr, bb;
-  if (i == 0) {
+  const int nb = a.grid_main;
+  const int64_t i = l.i;
+  __shared__ double s_start[3 * (kBlock / 64)];      // used once per kernel
+  double t[3] = {l.part[0], l.part[1], l.done != 0 ? 1.0 : 0.0};
+  block_allreduce_once<3, 0x4u>(t, s_start);
+  if (t[2] != 0.0) return false;
+  double rz = t[0], rr = t[1], bb = l.bb;
+  if (i == 0) {                                      // after the CG start
     double t3[3];
     read_totals<3>(a.partials, kPInit, nb, t3, lds, bc);
     rz = t3[0]; bb = t3[1]; rr = t3[2];
-  } else {
-    double t2[2];
-    read_totals<2>(a.partials, kPUpd, nb, t2, lds, bc);
-    rz = t2[0]; rr = t2[1]; bb = sc->bb;
-    if (sc->refine_every > 0) {
-      const bool conv_rec = sqrt(rr) <= a.rtol * sqrt(bb);
-      if (conv_rec || i % sc->refine_every == 0) {      // the replacement kernel ran
-        read_totals<2>(a.partials, kPRep, nb, t2, lds, bc);
-        rz = t2[0]; rr = t2[1];
-      }
+  } else if (l.refine > 0) {
+    const bool conv_rec = sqrt(rr) <= a.rtol * sqrt(bb);
+    if (conv_rec || i % l.refine == 0) {             // the replacement kernel ran
+      double t2[2];
+      read_totals<2>(a.partials, kPRep, nb, t2, lds, bc);
+      rz = t2[0]; rr = t2[1];
     }
   }
   bool stop = false;
   int status = IRLS_OK;
   if (!isfinite(rz) || !isfinite(rr)) { stop = true; status = IRLS_ERR_CG_BREAKDOWN; }
   else if (sqrt(rr) <= a.rtol * sqrt(bb)) stop = true;
-  else if (i >= sc->maxit) { stop = true; status = IRLS_WARN_CG_MAXIT; }
-  const double beta = i == 0 ? 0.0 : rz / sc->rho[(i - 1) & 1];
+  else if (i >= l.maxit) { stop = true; status = IRLS_WARN_CG_MAXIT; }
+  const double beta = i == 0 ? 0.0 : rz / (((i - 1) & 1) ? l.rho1 : l.rho0);
   if (first_thread()) {
     sc->rr = rr;
     if (i == 0) sc->bb = bb;
@@ -191,6 +222,62 @@ __device__ bool cg_iteration_start(const CGArgs<T> &a, double *lds, double *bc, 
   i_out = i;
   beta_out = beta;
   return !stop;
+}
+
+template <typename T>
+__device__ __forceinline__ bool cg_iteration_start(const CGArgs<T> &a, double *lds, double *bc, int64_t &i_out,
+                                                   double &beta_out) {
+  const IterStartLoads l = cg_iteration_load(a);
+  return cg_iteration_finish(a, l, lds, bc, i_out, beta_out);
+}
+
+// Start of the vector update of iteration it = iter_a: the total of p^T q
+// (the SpMV's partials) and alpha = rho_it / p^T q, in the same two halves.
+// Returns false when CG has stopped or broken down (pq <= 0 marks the
+// breakdown).
+struct UpdateStartLoads {
+  int32_t done;
+  int64_t it;
+  double rho0, rho1;
+  double part[1];
+};
+
+template <typename T>
+__device__ __forceinline__ UpdateStartLoads cg_update_load(const CGArgs<T> &a) {
+  const Scalars *sc = a.sc;
+  UpdateStartLoads l;
+  l.done = sc->done;
+  l.it = sc->iter_a;
+  l.rho0 = sc->rho[0];
+  l.rho1 = sc->rho[1];
+  partial_share<1>(a.partials, kPSpmv, a.grid_spmv, l.part);
+  return l;
+}
+
+template <typename T>
+__device__ bool cg_update_finish(const CGArgs<T> &a, const UpdateStartLoads &l, double *lds, double *bc,
+                                 int64_t &it_out, double &alpha_out, double &pq_out) {
+  Scalars *sc = a.sc;
+  __shared__ double s_start[2 * (kBlock / 64)];      // used once per kernel
+  double t[2] = {l.part[0], l.done != 0 ? 1.0 : 0.0};
+  block_allreduce_once<2, 0x2u>(t, s_start);
+  if (t[1] != 0.0) return false;
+  const double pq = t[0];
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (first_thread()) { sc->done = 1; sc->status = IRLS_ERR_CG_BREAKDOWN; }
+    return false;
+  }
+  it_out = l.it;
+  pq_out = pq;
+  alpha_out = ((l.it & 1) ? l.rho1 : l.rho0) / pq;
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ bool cg_update_start(const CGArgs<T> &a, double *lds, double *bc, int64_t &it_out,
+                                                double &alpha_out, double &pq_out) {
+  const UpdateStartLoads l = cg_update_load(a);
+  return cg_update_finish(a, l, lds, bc, it_out, alpha_out, pq_out);
 }
 
 // ----------------------------------------------------------------------------
@@ -246,54 +333,264 @@ __device__ __forceinline__ vec_t<T, R> vload(const T *p) { return *reinterpret_c
 template <typename T, int R>
 __device__ __forceinline__ void vstore(T *p, vec_t<T, R> v) { *reinterpret_cast<vec_t<T, R> *>(p) = v; }
 
+// Loads of one R-row group of the vectorised diagonal SpMV, taken before beta
+// is known.  Neighbours outside the matrix load as zeros (their terms vanish).
+template <typename T, int K, int R>
+struct DiaRow {
+  vec_t<T, R> zc, pc, D, w0;                // the group itself and its offset-1 edges
+  T zr, pr, wl, zl, pl;                     // the rows just right and left of the group
+  static constexpr int KO = K > 1 ? K - 1 : 1;
+  vec_t<T, R> wf[KO], zf[KO], pf[KO];       // offset +off[k], k >= 1
+  vec_t<T, R> wb[KO], zb[KO], pb[KO];       // offset -off[k], k >= 1
+};
+
+template <typename T, int K, int R>
+__device__ __forceinline__ void dia_load_p(const CGArgs<T> &a, const T *pin, int64_t u0, DiaRow<T, K, R> &r) {
+  const vec_t<T, R> zero = (T)0;
+  r.pc = vload<T, R>(pin + u0);
+  r.pr = u0 + R < a.nt ? pin[u0 + R] : (T)0;
+  r.pl = u0 > 0 ? pin[u0 - 1] : (T)0;
+#pragma unroll
+  for (int k = 1; k < K; k++) {
+    const int64_t o = a.off[k];
+    r.pf[k - 1] = u0 + o < a.nt ? vload<T, R>(pin + u0 + o) : zero;
+    r.pb[k - 1] = u0 >= o ? vload<T, R>(pin + u0 - o) : zero;
+  }
+}
+
+template <typename T, int K, int R>
+__device__ __forceinline__ void dia_load(const CGArgs<T> &a, const T *pin, int64_t u0, DiaRow<T, K, R> &r) {
+  const vec_t<T, R> zero = (T)0;
+  const int64_t nt = a.nt;
+  r.zc = vload<T, R>(a.z + u0);
+  r.D = vload<T, R>(a.D + u0);
+  r.w0 = vload<T, R>(a.w + u0);
+  r.zr = u0 + R < nt ? a.z[u0 + R] : (T)0;
+  r.wl = u0 > 0 ? a.w[u0 - 1] : (T)0;
+  r.zl = u0 > 0 ? a.z[u0 - 1] : (T)0;
+#pragma unroll
+  for (int k = 1; k < K; k++) {
+    const int64_t o = a.off[k];
+    const bool f = u0 + o < nt, b = u0 >= o;
+    r.wf[k - 1] = f ? vload<T, R>(a.w + k * nt + u0) : zero;
+    r.zf[k - 1] = f ? vload<T, R>(a.z + u0 + o) : zero;
+    r.wb[k - 1] = b ? vload<T, R>(a.w + k * nt + u0 - o) : zero;
+    r.zb[k - 1] = b ? vload<T, R>(a.z + u0 - o) : zero;
+  }
+  dia_load_p(a, pin, u0, r);
+}
+
+// Vectorised form of k_spmv_dia for grids: each thread owns R consecutive
+// rows and moves them with 16-byte loads (R = 2 in FP64, 4 in FP32).  Needs
+// off[0] == 1, every other offset and nt divisible by R.  The +-1 neighbours
+// inside the group come from registers; the rows just outside it are scalar
+// loads that hit in L1 (the neighbouring lanes loaded them).  The first row
+// group's loads are issued before the start-of-iteration reduction (which
+// reads every workgroup's partial sums and waits on barriers), so the memory
+// pipes are busy while it runs.
 template <typename T, int K, int R>
 __global__ __launch_bounds__(kBlock) void k_spmv_dia_vec(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   typedef vec_t<T, R> V;
+  const int64_t nt = a.nt, ng = nt / R;
+  int64_t gb, ge, gs;
+  slab_rows(ng, gb, ge, gs);
+  const IterStartLoads sl = cg_iteration_load(a);     // first: the reduction waits only for these
+  const T *__restrict__ pin = (a.it_hint & 1) ? a.p1 : a.p0;
+  DiaRow<T, K, R> r;
+  if (gb < ge) dia_load(a, pin, gb * R, r);
   int64_t it;
   double beta64;
-  if (!cg_iteration_start(a, lds, bc, it, beta64)) return;
+  if (!cg_iteration_finish(a, sl, lds, bc, it, beta64)) return;
+  if (((it ^ a.it_hint) & 1) != 0) {                  // the host's guess was wrong
+    pin = (it & 1) ? a.p1 : a.p0;
+    if (gb < ge) dia_load_p(a, pin, gb * R, r);
+  }
+  T *__restrict__ pout = (it & 1) ? a.p0 : a.p1;
   const T beta = (T)beta64;
   const bool first = it == 0;
-  const T *__restrict__ pin = (it & 1) ? a.p1 : a.p0;
-  T *__restrict__ pout = (it & 1) ? a.p0 : a.p1;
-  const T *__restrict__ z = a.z;
-  const T *__restrict__ D = a.D;
-  const T *__restrict__ w = a.w;
-  const int64_t nt = a.nt, ng = nt / R;
-  auto dirv = [&](int64_t u0) -> V {
-    V zv = vload<T, R>(z + u0);
-    return first ? zv : zv + beta * vload<T, R>(pin + u0);
-  };
-  auto dirs = [&](int64_t j) -> T { return first ? z[j] : z[j] + beta * pin[j]; };
+  auto dir = [&](V zv, V pv) -> V { return first ? zv : zv + beta * pv; };
+  auto dirs = [&](T zv, T pv) -> T { return first ? zv : zv + beta * pv; };
   double x[1] = {0.0};
-  FOR_ROWS(gi, ng) {
+  for (int64_t gi = gb; gi < ge; gi += gs) {
     const int64_t u0 = gi * R;
-    const V pc = dirv(u0);
-    V acc = vload<T, R>(D + u0) * pc;
+    if (gi != gb) dia_load(a, pin, u0, r);
+    const V pc = dir(r.zc, r.pc);
+    V acc = r.D * pc;
     // offset 1: edges inside the group, and to the rows just outside it
-    {
-      const V w0 = vload<T, R>(w + u0);
-      const T right = u0 + R < nt ? dirs(u0 + R) : (T)0;
-      const T wl = u0 > 0 ? w[u0 - 1] : (T)0;
-      const T left = u0 > 0 ? dirs(u0 - 1) : (T)0;
+    const T right = dirs(r.zr, r.pr), left = dirs(r.zl, r.pl);
 #pragma unroll
-      for (int i = 0; i < R; i++) {
-        acc[i] -= w0[i] * (i + 1 < R ? pc[i + 1] : right);
-        acc[i] -= (i > 0 ? w0[i - 1] : wl) * (i > 0 ? pc[i - 1] : left);
-      }
+    for (int i = 0; i < R; i++) {
+      acc[i] -= r.w0[i] * (i + 1 < R ? pc[i + 1] : right);
+      acc[i] -= (i > 0 ? r.w0[i - 1] : r.wl) * (i > 0 ? pc[i - 1] : left);
     }
 #pragma unroll
     for (int k = 1; k < K; k++) {
-      const int64_t o = a.off[k];
-      if (u0 + o < nt) acc -= vload<T, R>(w + k * nt + u0) * dirv(u0 + o);
-      if (u0 >= o) acc -= vload<T, R>(w + k * nt + u0 - o) * dirv(u0 - o);
+      acc -= r.wf[k - 1] * dir(r.zf[k - 1], r.pf[k - 1]);
+      acc -= r.wb[k - 1] * dir(r.zb[k - 1], r.pb[k - 1]);
     }
     vstore<T, R>(pout + u0, pc);
     vstore<T, R>(a.q + u0, acc);
 #pragma unroll
     for (int i = 0; i < R; i++) x[0] += (double)pc[i] * (double)acc[i];
+  }
+  write_partials<1>(x, a.partials, kPSpmv, lds);
+}
+
+// Loads of one step of the marching SpMV (one R-row group of plane k), taken
+// before beta is known: the group's next-plane values, its own conductances,
+// and the neighbours at the offsets below the plane size.  Neighbours outside
+// the matrix load as zeros.
+template <typename T, int K, int R>
+struct MarchStep {
+  static constexpr int KM = K > 2 ? K - 2 : 1;
+  vec_t<T, R> zp, pp, D, w0, wP;            // plane k + 1; diagonal; offsets 1 and P
+  T zr, pr, wl, zl, pl;                     // the rows just right and left of the group
+  vec_t<T, R> wf[KM], zf[KM], pf[KM];       // offsets off[1..K-2], forward
+  vec_t<T, R> wb[KM], zb[KM], pb[KM];       // and backward
+};
+
+template <typename T, int K, int R>
+__device__ __forceinline__ void march_load_p(const CGArgs<T> &a, const T *pin, int64_t u0, MarchStep<T, K, R> &s) {
+  const vec_t<T, R> zero = (T)0;
+  const int64_t nt = a.nt, P = a.off[K - 1];
+  s.pp = u0 + P < nt ? vload<T, R>(pin + u0 + P) : zero;
+  s.pr = u0 + R < nt ? pin[u0 + R] : (T)0;
+  s.pl = u0 > 0 ? pin[u0 - 1] : (T)0;
+#pragma unroll
+  for (int kk = 1; kk < K - 1; kk++) {
+    const int64_t o = a.off[kk];
+    s.pf[kk - 1] = u0 + o < nt ? vload<T, R>(pin + u0 + o) : zero;
+    s.pb[kk - 1] = u0 >= o ? vload<T, R>(pin + u0 - o) : zero;
+  }
+}
+
+template <typename T, int K, int R>
+__device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int64_t u0, MarchStep<T, K, R> &s) {
+  const vec_t<T, R> zero = (T)0;
+  const int64_t nt = a.nt, P = a.off[K - 1];
+  s.zp = u0 + P < nt ? vload<T, R>(a.z + u0 + P) : zero;
+  s.D = vload<T, R>(a.D + u0);
+  s.w0 = vload<T, R>(a.w + u0);
+  s.wP = vload<T, R>(a.w + (K - 1) * nt + u0);
+  s.zr = u0 + R < nt ? a.z[u0 + R] : (T)0;
+  s.wl = u0 > 0 ? a.w[u0 - 1] : (T)0;
+  s.zl = u0 > 0 ? a.z[u0 - 1] : (T)0;
+#pragma unroll
+  for (int kk = 1; kk < K - 1; kk++) {
+    const int64_t o = a.off[kk];
+    const bool f = u0 + o < nt, b = u0 >= o;
+    s.wf[kk - 1] = f ? vload<T, R>(a.w + kk * nt + u0) : zero;
+    s.zf[kk - 1] = f ? vload<T, R>(a.z + u0 + o) : zero;
+    s.wb[kk - 1] = b ? vload<T, R>(a.w + kk * nt + u0 - o) : zero;
+    s.zb[kk - 1] = b ? vload<T, R>(a.z + u0 - o) : zero;
+  }
+  march_load_p(a, pin, u0, s);
+}
+
+// Diagonal SpMV marching along the largest offset P = off[K-1] (the plane
+// size of a grid: rows u = c + P k).  A workgroup owns a tile of kBlock
+// R-row groups of one plane and walks a chunk of consecutive planes; each
+// thread keeps the direction values of planes k-1 and k and the conductance
+// of its edge to plane k-1 in registers, so the +-P neighbours, which lie a
+// whole plane away in memory, are never reloaded.  Offsets below P are read
+// as in k_spmv_dia_vec.  All loads of the first step are issued before the
+// start-of-iteration reduction, so they are in flight while it runs.
+// Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of chunks,
+// so the planes at chunk seams are shared in its L2.  The summation order per
+// row is that of k_spmv_dia_vec.
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  __shared__ double bc[4];
+  typedef vec_t<T, R> V;
+  const V zero = (T)0;
+  const int64_t nt = a.nt, P = a.off[K - 1];
+  const int64_t gp = P / R, tiles = (gp + kBlock - 1) / kBlock;
+  const int64_t nplanes = (nt + P - 1) / P, zc = a.march_planes;
+  const int64_t L = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+  const int64_t tile = L % tiles, chunk = L / tiles;
+  const int64_t cgrp = tile * kBlock + threadIdx.x;
+  const int64_t c = cgrp * R;
+  const int64_t k0 = chunk * zc;
+  const int64_t k1 = k0 + zc < nplanes ? k0 + zc : nplanes;
+  const bool active = cgrp < gp && k0 < nplanes && c + P * k0 < nt;
+  // planes of this chunk that hold this thread's rows (a last plane may be partial)
+  const int64_t kmax = active ? (nt - c + P - 1) / P : 0;
+  const int64_t kend = k1 < kmax ? k1 : kmax;
+  const IterStartLoads sl = cg_iteration_load(a);     // first: the reduction waits only for these
+  const T *__restrict__ pin = (a.it_hint & 1) ? a.p1 : a.p0;
+  V zm = zero, pm = zero, wm = zero, zk = zero, pk = zero;
+  // the first two steps are loaded before the reduction
+  MarchStep<T, K, R> s0, s1;
+  const bool two = kend > k0 + 1;
+  if (active) {
+    const int64_t u = c + P * k0;
+    zk = vload<T, R>(a.z + u);
+    pk = vload<T, R>(pin + u);
+    if (k0 > 0) {
+      zm = vload<T, R>(a.z + u - P);
+      pm = vload<T, R>(pin + u - P);
+      wm = vload<T, R>(a.w + (K - 1) * nt + u - P);
+    }
+    march_load(a, pin, u, s0);
+    if (two) march_load(a, pin, u + P, s1);
+  }
+  int64_t it;
+  double beta64;
+  if (!cg_iteration_finish(a, sl, lds, bc, it, beta64)) return;
+  if (((it ^ a.it_hint) & 1) != 0) {                  // the host's guess was wrong
+    pin = (it & 1) ? a.p1 : a.p0;
+    if (active) {
+      const int64_t u = c + P * k0;
+      pk = vload<T, R>(pin + u);
+      if (k0 > 0) pm = vload<T, R>(pin + u - P);
+      march_load_p(a, pin, u, s0);
+      if (two) march_load_p(a, pin, u + P, s1);
+    }
+  }
+  T *__restrict__ pout = (it & 1) ? a.p0 : a.p1;
+  const T beta = (T)beta64;
+  const bool first = it == 0;
+  auto dir = [&](V zv, V pv) -> V { return first ? zv : zv + beta * pv; };
+  auto dirs = [&](T zv, T pv) -> T { return first ? zv : zv + beta * pv; };
+  double x[1] = {0.0};
+  V dm = dir(zm, pm);                                    // plane k - 1
+  auto step = [&](const MarchStep<T, K, R> &st, int64_t k) {
+    const int64_t u0 = c + P * k;
+    const V pc = dir(zk, pk);
+    V acc = st.D * pc;
+    const T right = dirs(st.zr, st.pr), left = dirs(st.zl, st.pl);
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      acc[i] -= st.w0[i] * (i + 1 < R ? pc[i + 1] : right);
+      acc[i] -= (i > 0 ? st.w0[i - 1] : st.wl) * (i > 0 ? pc[i - 1] : left);
+    }
+#pragma unroll
+    for (int kk = 1; kk < K - 1; kk++) {
+      acc -= st.wf[kk - 1] * dir(st.zf[kk - 1], st.pf[kk - 1]);
+      acc -= st.wb[kk - 1] * dir(st.zb[kk - 1], st.pb[kk - 1]);
+    }
+    const V dp = dir(st.zp, st.pp);
+    if (u0 + P < nt) acc -= st.wP * dp;
+    if (k > 0) acc -= wm * dm;
+    vstore<T, R>(pout + u0, pc);
+    vstore<T, R>(a.q + u0, acc);
+#pragma unroll
+    for (int i = 0; i < R; i++) x[0] += (double)pc[i] * (double)acc[i];
+    dm = pc;
+    wm = st.wP;
+    zk = st.zp;
+    pk = st.pp;
+  };
+  if (active) {
+    step(s0, k0);
+    if (two) step(s1, k0 + 1);
+    for (int64_t k = k0 + 2; k < kend; k++) {
+      march_load(a, pin, c + P * k, s0);
+      step(s0, k);
+    }
   }
   write_partials<1>(x, a.partials, kPSpmv, lds);
 }
@@ -357,16 +654,9 @@ __global__ __launch_bounds__(kBlock) void k_update(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   Scalars *sc = a.sc;
-  if (block_done(sc)) return;
-  const int64_t it = sc->iter_a;
-  double t1[1];
-  read_totals<1>(a.partials, kPSpmv, gridDim.x, t1, lds, bc);
-  const double pq = t1[0];
-  if (!(pq > 0.0) || !isfinite(pq)) {
-    if (first_thread()) { sc->done = 1; sc->status = IRLS_ERR_CG_BREAKDOWN; }
-    return;
-  }
-  const double alpha = sc->rho[it & 1] / pq;
+  int64_t it;
+  double alpha, pq;
+  if (!cg_update_start(a, lds, bc, it, alpha, pq)) return;
   const T *__restrict__ p = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;   // fused diagonal kernel's output
   double x[2] = {0.0, 0.0};
   FOR_ROWS(u, a.nt) {
@@ -394,25 +684,34 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
   __shared__ double bc[4];
   typedef vec_t<T, R> V;
   typedef vec_t<double, R> VD;
-  Scalars *sc = a.sc;
-  if (block_done(sc)) return;
-  const int64_t it = sc->iter_a;
-  double t1[1];
-  read_totals<1>(a.partials, kPSpmv, gridDim.x, t1, lds, bc);
-  const double pq = t1[0];
-  if (!(pq > 0.0) || !isfinite(pq)) {
-    if (first_thread()) { sc->done = 1; sc->status = IRLS_ERR_CG_BREAKDOWN; }
-    return;
-  }
-  const double alpha = sc->rho[it & 1] / pq;
-  const T *__restrict__ p = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;
   const int64_t ng = a.nt / R;
+  int64_t gb, ge, gs;
+  slab_rows(ng, gb, ge, gs);
+  const UpdateStartLoads sl = cg_update_load(a);      // first: the reduction waits only for these
+  // the first row group's loads go out before the start-of-kernel reduction
+  const T *__restrict__ p = (a.K > 0 && (a.it_hint & 1) == 0) ? a.p1 : a.p0;
+  V pv, zv, qv, Dv;
+  VD vv;
+  if (gb < ge) {
+    const int64_t u0 = gb * R;
+    pv = vload<T, R>(p + u0); zv = vload<T, R>(a.z + u0); qv = vload<T, R>(a.q + u0);
+    Dv = vload<T, R>(a.D + u0); vv = vload<double, R>(a.v + u0);
+  }
+  Scalars *sc = a.sc;
+  int64_t it;
+  double alpha, pq;
+  if (!cg_update_finish(a, sl, lds, bc, it, alpha, pq)) return;
+  if (((it ^ a.it_hint) & 1) != 0 && a.K > 0) {        // the host's guess was wrong
+    p = (it & 1) == 0 ? a.p1 : a.p0;
+    if (gb < ge) pv = vload<T, R>(p + gb * R);
+  }
   double x[2] = {0.0, 0.0};
-  FOR_ROWS(gi, ng) {
+  for (int64_t gi = gb; gi < ge; gi += gs) {
     const int64_t u0 = gi * R;
-    const V pv = vload<T, R>(p + u0), zv = vload<T, R>(a.z + u0), qv = vload<T, R>(a.q + u0);
-    const V Dv = vload<T, R>(a.D + u0);
-    VD vv = vload<double, R>(a.v + u0);
+    if (gi != gb) {
+      pv = vload<T, R>(p + u0); zv = vload<T, R>(a.z + u0); qv = vload<T, R>(a.q + u0);
+      Dv = vload<T, R>(a.D + u0); vv = vload<double, R>(a.v + u0);
+    }
     V zn;
 #pragma unroll
     for (int i = 0; i < R; i++) {
@@ -441,12 +740,22 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   Scalars *sc = a.sc;
-  if (block_done(sc)) return;
+  const int32_t done = sc->done;
   const int64_t i = sc->iter_b;
-  double t2[2];
-  read_totals<2>(a.partials, kPUpd, gridDim.x, t2, lds, bc);
-  const bool conv_rec = sqrt(t2[1]) <= a.rtol * sqrt(sc->bb);
-  if (!(conv_rec || i % sc->refine_every == 0)) return;
+  const int32_t refine = sc->refine_every;
+  const double bb = sc->bb;
+  double t[3];
+  {
+    double u[2];
+    partial_share<2>(a.partials, kPUpd, a.grid_main, u);
+    t[0] = u[0];
+    t[1] = u[1];
+    t[2] = done != 0 ? 1.0 : 0.0;
+  }
+  block_allreduce<3, 0x4u>(t, lds, bc);
+  if (t[2] != 0.0) return;
+  const bool conv_rec = sqrt(t[1]) <= a.rtol * sqrt(bb);
+  if (!(conv_rec || i % refine == 0)) return;
   double x[2] = {0.0, 0.0};
   FOR_ROWS(u, a.nt) {
     double ru64 = a.b[u] - row_apply64<DIA>(a, u, a.v);
@@ -580,9 +889,39 @@ bool vec_ok(const CGArgs<T> &a) {
   return true;
 }
 
+// Marching needs the vector layout, at least two planes, and planes of at
+// least one full tile (kBlock groups); the chunk length keeps the grid near
+// kMarchGrid workgroups (two per CU).
+constexpr int kMarchGrid = 512;
+
+template <typename T>
+void spmv_layout(CGArgs<T> &a, int grid_main) {
+  constexpr int R = kVecRows<T>;
+  a.grid_spmv = grid_main;
+  a.march_planes = 0;
+  if (a.K < 2 || !vec_ok(a)) return;
+  const int64_t P = a.off[a.K - 1];
+  const int64_t gp = P / R, tiles = (gp + kBlock - 1) / kBlock, nplanes = (a.nt + P - 1) / P;
+  if (gp < kBlock || nplanes < 2 || tiles > kMaxGrid) return;
+  int64_t zc = (tiles * nplanes + kMarchGrid - 1) / kMarchGrid;
+  if (zc < 4) zc = 4;
+  int64_t grid = tiles * ((nplanes + zc - 1) / zc);
+  while ((grid + kXcds - 1) / kXcds * kXcds > kMaxGrid) {       // never more partials than slots
+    zc *= 2;
+    grid = tiles * ((nplanes + zc - 1) / zc);
+  }
+  a.march_planes = (int32_t)zc;
+  a.grid_spmv = (int)((grid + kXcds - 1) / kXcds * kXcds);
+}
+
 template <typename T>
 hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hipStream_t st) {
   constexpr int R = kVecRows<T>;
+  if (a.march_planes > 0) {
+    if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+  }
   if (a.K > 0 && vec_ok(a)) {
     switch (a.K) {
       case 1: hipLaunchKernelGGL((k_spmv_dia_vec<T, 1, R>), dim3(grid), dim3(kBlock), 0, st, a); break;
@@ -663,6 +1002,7 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
   template hipError_t launch_assemble<T>(const CGArgs<T> &, int, hipStream_t);             \
   template hipError_t launch_cginit<T>(const CGArgs<T> &, int, hipStream_t);               \
   template hipError_t launch_spmv<T>(const CGArgs<T> &, int, int, bool, hipStream_t);      \
+  template void spmv_layout<T>(CGArgs<T> &, int);                                          \
   template hipError_t launch_direction<T>(const CGArgs<T> &, int, hipStream_t);            \
   template hipError_t launch_update<T>(const CGArgs<T> &, int, hipStream_t);               \
   template hipError_t launch_replace_residual<T>(const CGArgs<T> &, int, hipStream_t);     \

@@ -53,6 +53,32 @@ __device__ __forceinline__ void block_reduce(double (&x)[NQ], double *lds) {
   __syncthreads();
 }
 
+// All-reduce with a single barrier: every thread adds the wavefront totals
+// in the order thread 0 of block_reduce does, so the bits are the same.  The
+// LDS array (NQ * waves doubles) must not be reused by the workgroup
+// afterwards, since there is no barrier after the reads.
+template <int NQ, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void block_allreduce_once(double (&x)[NQ], double *lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    double v = x[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      double u = __shfl_xor(v, o, 64);
+      v = ((MAXMASK >> q) & 1u) ? fmax(v, u) : v + u;
+    }
+    if (lane == 0) lds[q * nw + wid] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    double acc = lds[q * nw];
+    for (int w = 1; w < nw; w++) acc = ((MAXMASK >> q) & 1u) ? fmax(acc, lds[q * nw + w]) : acc + lds[q * nw + w];
+    x[q] = acc;
+  }
+}
+
 template <int NQ, unsigned MAXMASK = 0u>
 __device__ __forceinline__ void block_allreduce(double (&x)[NQ], double *lds, double *bc) {
   block_reduce<NQ, MAXMASK>(x, lds);
@@ -79,19 +105,58 @@ __device__ __forceinline__ void write_partials(double (&x)[NQ], double *partials
   }
 }
 
-// Totals of the partial sums a previous kernel of `nblocks` workgroups left in
-// `slot`.  Every workgroup adds them in the same fixed order, so all get the
-// same bits; no atomics and no fences are needed (kernel boundaries order the
-// memory traffic).
-template <int NQ, unsigned MAXMASK = 0u>
-__device__ __forceinline__ void read_totals(const double *partials, int slot, int nblocks,
-                                            double (&tot)[NQ], double *lds, double *bc) {
+// This thread's share of the totals of NQ partial-sum arrays (the sums over
+// partials threadIdx.x, threadIdx.x + kBlock, ...); block_allreduce then
+// finishes them.  For workgroups of kBlock threads.  The loads are unrolled
+// so they are all in flight at once; the sum order is the loop order.  Split
+// from read_totals so a kernel can issue other loads in the same memory
+// round trip and reduce them together.
+template <int NQ>
+__device__ __forceinline__ void partial_share(const double *partials, int slot, int nblocks, double (&acc)[NQ]) {
+  constexpr int kPer = kMaxGrid / kBlock;
+  double v[NQ][kPer];
 #pragma unroll
   for (int q = 0; q < NQ; q++) {
     const double *P = partials + ((size_t)slot * kNumPartial + q) * kMaxGrid;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const int b = threadIdx.x + j * kBlock;
+      v[q][j] = b < nblocks ? P[b] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) s += v[q][j];
+    acc[q] = s;
+  }
+}
+
+// Totals of the partial sums a previous kernel of `nblocks` workgroups left in
+// `slot`.  Every workgroup adds them in the same fixed order, so all get the
+// same bits; no atomics and no fences are needed (kernel boundaries order the
+// memory traffic).  For workgroups of kBlock threads; MAXMASK marks the
+// components reduced by max instead of sum.
+template <int NQ, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void read_totals(const double *partials, int slot, int nblocks,
+                                            double (&tot)[NQ], double *lds, double *bc) {
+  constexpr int kPer = kMaxGrid / kBlock;
+  double v[NQ][kPer];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    const double *P = partials + ((size_t)slot * kNumPartial + q) * kMaxGrid;
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const int b = threadIdx.x + j * kBlock;
+      v[q][j] = b < nblocks ? P[b] : (((MAXMASK >> q) & 1u) ? -INFINITY : 0.0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
     double acc = ((MAXMASK >> q) & 1u) ? -INFINITY : 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
-      acc = ((MAXMASK >> q) & 1u) ? fmax(acc, P[b]) : acc + P[b];
+#pragma unroll
+    for (int j = 0; j < kPer; j++) acc = ((MAXMASK >> q) & 1u) ? fmax(acc, v[q][j]) : acc + v[q][j];
     tot[q] = acc;
   }
   block_allreduce<NQ, MAXMASK>(tot, lds, bc);

@@ -392,13 +392,20 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.cst = h->g.cst;
   a.rtol = h->opt.cg_rtol;
   a.weights_fp64 = 1;
+  a.grid_main = h->grid;
+  spmv_layout(a, h->grid);
   return a;
 }
 
+// CG iterations first .. first + count - 1 of this round (the kernels learn
+// the true iteration from the scalar block; the index only steers loads that
+// are issued before they read it)
 template <typename T>
-hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a, int64_t count) {
+hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a0, int64_t first, int64_t count) {
   hipError_t e = hipSuccess;
+  CGArgs<T> a = a0;
   for (int64_t i = 0; i < count && e == hipSuccess; i++) {
+    a.it_hint = first + i;
     if (a.K == 0) e = launch_direction(a, h->grid, h->stream);
     if (e == hipSuccess) e = launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream);
     if (e == hipSuccess) e = launch_update(a, h->grid, h->stream);
@@ -421,7 +428,7 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
   int64_t next = pred > 0 ? 16 : 32;
   if (h->opt.chunk > 0) first = next = h->opt.chunk;
   first = std::min(first, maxit);
-  HIPCHK(h, launch_iterations(h, a, first), "CG launch");
+  HIPCHK(h, launch_iterations(h, a, 0, first), "CG launch");
   HIPCHK(h, hipMemcpyAsync(&h->pinned[0], h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream), "readback");
   HIPCHK(h, hipEventRecord(h->ev[0], h->stream), "event");
   int64_t launched = first;
@@ -430,7 +437,7 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
     bool queued = false;
     if (launched < maxit) {
       int64_t c = std::min(next, maxit - launched);
-      HIPCHK(h, launch_iterations(h, a, c), "CG launch");
+      HIPCHK(h, launch_iterations(h, a, launched, c), "CG launch");
       HIPCHK(h, hipMemcpyAsync(&h->pinned[1 - slot], h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream), "readback");
       HIPCHK(h, hipEventRecord(h->ev[1 - slot], h->stream), "event");
       launched += c;
@@ -969,8 +976,6 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
   if (h->batch || h->solver != 1) { h->err = "kernel timing needs the multi-workgroup solver"; return IRLS_ERR_OPTIONS; }
   if (!h->solved) { h->err = "call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
   try {
-    // a private scalar block: beta = 0 and alpha = 0 make every launch
-    // idempotent (p = z, q = L~ z; v and r unchanged), done = 0 keeps it running
     // The launches run on the live system of the last round with a private
     // scalar block (iteration 1, done = 0, no stopping); the potentials are
     // saved first and restored afterwards.
@@ -989,10 +994,12 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
       if (h->opt.precision == 1) {
         CGArgs<float> a = make_args<float>(h);
         a.sc = h->sc_bench;
+        a.it_hint = 1;
         return which == 0 ? launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream) : launch_update(a, h->grid, h->stream);
       }
       CGArgs<double> a = make_args<double>(h);
       a.sc = h->sc_bench;
+      a.it_hint = 1;
       return which == 0 ? launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream) : launch_update(a, h->grid, h->stream);
     };
     hipError_t e = one();

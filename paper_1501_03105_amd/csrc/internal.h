@@ -70,6 +70,13 @@ struct CGArgs {
   int32_t weights_fp64;           // precision 1: compute conductances in FP64
   double cst;                     // s-t capacity
   double rtol;                    // CG stopping tolerance relative to ||b||
+  int32_t grid_main;              // workgroups of the init / update / replacement kernels
+  int32_t grid_spmv;              // workgroups of the SpMV kernel (its partial-sum count)
+  int32_t march_planes;           // diagonal SpMV marching along off[K-1]: planes per
+                                  // workgroup (0: the row-slab kernels)
+  int64_t it_hint;                // CG iteration the host expects this launch to run: picks
+                                  // the p buffer for loads issued before the kernel has read
+                                  // the scalar block (checked there; a mismatch reloads)
 };
 
 // Device arrays of one graph.
@@ -107,6 +114,8 @@ struct SweepBufs {
 // ----------------------------------------------------------------------------
 template <typename T> hipError_t launch_assemble(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st);
+// SpMV grid and kernel choice for a system: sets a.grid_spmv and a.march_planes
+template <typename T> void spmv_layout(CGArgs<T> &a, int grid_main);
 template <typename T> hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave,
                                              bool fused_dia, hipStream_t st);
 template <typename T> hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st);

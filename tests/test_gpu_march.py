@@ -1,0 +1,56 @@
+"""The diagonal SpMV that marches along the plane offset, against the CPU
+oracle.  Layouts chosen to hit its edge cases: a 2-D grid whose rows (the
+planes of two offsets) fill one and a fraction of a tile, and a 3-D box whose
+last plane is partial, in FP64 and in the FP32 form."""
+import numpy as np
+import pytest
+
+import gen
+from tests.gpu_util import max_pot_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1501_03105_amd as P
+    P.lib()
+    return P
+
+
+OPTS = dict(rounds=20, cg_rtol=1e-10)
+
+
+def cases():
+    # grid2d 1200 x 20: planes (x-rows) of 1200 rows = 600 FP64 / 300 FP32
+    #   groups, so the last tile of each plane is partial; 20 planes
+    # box 32 x 32, 10 planes + 500 rows: full tiles, a partial last plane
+    # box 48 x 24, 7 planes + 36 rows: partial tiles and a partial plane
+    return [("grid2d 1200x20", gen.grid2d(1200, 20, seed=2)),
+            ("box 32x32, 10 planes + 500", gen.grid3d_box(32, 32, 32 * 32 * 10 + 500, seed=3)),
+            ("box 48x24, 7 planes + 36", gen.grid3d_box(48, 24, 48 * 24 * 7 + 36, seed=4))]
+
+
+@pytest.mark.parametrize("case", range(3))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_march_matches_oracle(P, oracle_mod, case, precision):
+    name, g = cases()[case]
+    say(f"march: {name}, precision {precision}")
+    xo, so, _ = oracle_mod.irls(g, **OPTS)
+    So, vo, _, _ = oracle_mod.sweep(g, xo)
+    with P.MinCut.from_graph(g, solver=1, precision=precision, **OPTS) as mc:
+        info = mc.info()
+        rc, st = mc.solve()
+        x = mc.potentials()
+        S, v, _ = mc.cut()
+    assert info["format"] == 2 and info["n_diagonals"] == (2 if case == 0 else 3)
+    err = max_pot_err(x, xo)
+    say(f"  potential error {err:.2e}; cut {v!r} vs {vo!r}")
+    if precision == 0:
+        assert err <= 1e-8
+        assert v == vo and np.array_equal(S, So)
+    else:
+        assert err <= 1e-4
+        assert abs(v - vo) <= 1e-4 * vo
