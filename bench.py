@@ -309,11 +309,11 @@ def main():
         upd_ms = mc.time_kernel(1, args.kernel_reps)
         nbytes = spmv_bytes(info, opts.get("precision", 0))
         achieved = nbytes / (spmv_ms * 1e-3) / 1e9
-        kname = "k_spmv_dia" if info["format"] == 2 else "k_spmv_csr"
+        kname, spmv_grid = mc.spmv_kernel()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(kname, args.workload), "kernel": kname,
-                "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5),
+                "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5), "workgroups": spmv_grid,
                 "update_kernel_ms": round(upd_ms, 5)}
         print(f"[bench] spmv {spmv_ms*1e3:.1f} us ({achieved:.0f} GB/s), update {upd_ms*1e3:.1f} us",
               file=sys.stderr, flush=True)

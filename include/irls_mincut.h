@@ -157,6 +157,14 @@ irls_status irls_mincut_info(irls_mincut_t h, int64_t *n_nonterminal, int64_t *n
                              int32_t *format, int32_t *n_diagonals, int32_t *solver,
                              int32_t *rows_per_wave);
 
+/* The SpMV kernel the CG loop of a multi-workgroup handle launches and its
+ * workgroup count.  variant: 0 CSR (rows_per_wave rows per wavefront),
+ * 1 diagonal format with a row per thread, 2 diagonal with 16-byte row
+ * vectors, 3 diagonal marching along the largest offset (the plane of a 3-D
+ * grid, the row of a 2-D one).  IRLS_ERR_OPTIONS for the resident solver or a
+ * batch. */
+irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *grid);
+
 /* Time one hot kernel of the CG loop on the handle's stream with HIP events:
  * `which` 0 = SpMV (with its fused direction update), 1 = the CG vector
  * update.  `reps` back-to-back launches after one warm-up launch; *avg_ms is

@@ -69,6 +69,7 @@ def lib():
         L.irls_mincut_info.argtypes = [H, P64, P64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.irls_mincut_time_kernel.argtypes = [H, C.c_int32, C.c_int32, PF64]
+        L.irls_mincut_spmv_kernel.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.irls_mincut_destroy.argtypes = [H]
         L.irls_mincut_destroy.restype = None
         L.irls_mincut_last_error.argtypes = [H]
@@ -78,7 +79,7 @@ def lib():
         L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
         L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
         for f in ("create", "solve", "solve_range", "cut", "potentials", "set_potentials", "info",
-                  "time_kernel", "create_batch", "solve_batch", "cut_batch"):
+                  "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
         PF32 = C.POINTER(C.c_float)
         L.irls_gnn_create.argtypes = [C.POINTER(H), C.c_int32, C.c_int32, C.c_uint64, C.c_void_p]
@@ -221,6 +222,16 @@ class MinCut:
             raise self._err(rc)
         return dict(n_nonterminal=nt.value, nnz_offdiag=nnz.value, format=fmt.value,
                     n_diagonals=K.value, solver=sol.value, rows_per_wave=rpw.value)
+
+    SPMV_KERNELS = {0: "k_spmv_csr", 1: "k_spmv_dia", 2: "k_spmv_dia_vec", 3: "k_spmv_dia_march"}
+
+    def spmv_kernel(self):
+        """(kernel name, workgroups) of the CG loop's SpMV (irls_mincut_spmv_kernel)."""
+        v, g = C.c_int32(), C.c_int32()
+        rc = lib().irls_mincut_spmv_kernel(self.h, C.byref(v), C.byref(g))
+        if rc != OK:
+            raise self._err(rc)
+        return self.SPMV_KERNELS[v.value], g.value
 
     def time_kernel(self, which=0, reps=50):
         ms = C.c_double(0)

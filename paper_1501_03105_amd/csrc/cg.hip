@@ -915,6 +915,13 @@ void spmv_layout(CGArgs<T> &a, int grid_main) {
 }
 
 template <typename T>
+int spmv_variant(const CGArgs<T> &a) {
+  if (a.K == 0) return 0;
+  if (a.march_planes > 0) return 3;
+  return vec_ok(a) ? 2 : 1;
+}
+
+template <typename T>
 hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hipStream_t st) {
   constexpr int R = kVecRows<T>;
   if (a.march_planes > 0) {
@@ -1003,6 +1010,7 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
   template hipError_t launch_cginit<T>(const CGArgs<T> &, int, hipStream_t);               \
   template hipError_t launch_spmv<T>(const CGArgs<T> &, int, int, bool, hipStream_t);      \
   template void spmv_layout<T>(CGArgs<T> &, int);                                          \
+  template int spmv_variant<T>(const CGArgs<T> &);                                         \
   template hipError_t launch_direction<T>(const CGArgs<T> &, int, hipStream_t);            \
   template hipError_t launch_update<T>(const CGArgs<T> &, int, hipStream_t);               \
   template hipError_t launch_replace_residual<T>(const CGArgs<T> &, int, hipStream_t);     \

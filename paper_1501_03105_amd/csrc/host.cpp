@@ -281,6 +281,68 @@ int lanes_for(int64_t rows, int64_t nnz) {
   return L;
 }
 
+// Heavy rows of one graph for the resident solver (rows with more than
+// kHeavyRow entries, cut into kChunk-entry chunks), appended to the lists of a
+// batch; also the lane count for the remaining (light) rows.
+struct HeavyLists {
+  std::vector<int32_t> crow, cbeg, cend, hrow, hc0, hc1;
+  std::vector<int32_t> brow, bbeg, bend;          // light rows by bin, nt slots per graph
+};
+
+void add_heavy_rows(const std::vector<int32_t> &rowptr, int64_t nt, HeavyLists &H, BatchGraph &B) {
+  B.chunk0 = (int64_t)H.crow.size();
+  B.heavy0 = (int64_t)H.hrow.size();
+  B.nnz = rowptr[nt];
+  int32_t nchunks = 0, nheavy = 0;
+  int64_t light_rows = 0, light_nnz = 0;
+  // light rows by bin (stable within a bin), padded to nt slots per graph
+  std::vector<int32_t> cnt(kBins + 1, 0);
+  auto bin_of = [](int32_t d) {
+    int b = 0;
+    while (b < kBins - 1 && d > (2 << b)) b++;
+    return b;
+  };
+  for (int64_t i = 0; i < nt; i++) {
+    const int32_t d = rowptr[i + 1] - rowptr[i];
+    if (d <= kHeavyRow) cnt[bin_of(d) + 1]++;
+  }
+  for (int b = 0; b < kBins; b++) cnt[b + 1] += cnt[b];
+  for (int b = 0; b <= kBins; b++) B.bin[b] = cnt[b];
+  const size_t base = H.brow.size();
+  H.brow.resize(base + nt, 0);
+  H.bbeg.resize(base + nt, 0);
+  H.bend.resize(base + nt, 0);
+  for (int64_t i = 0; i < nt; i++) {
+    const int32_t d = rowptr[i + 1] - rowptr[i];
+    if (d > kHeavyRow) continue;
+    const int32_t j = cnt[bin_of(d)]++;
+    H.brow[base + j] = (int32_t)i;
+    H.bbeg[base + j] = rowptr[i];
+    H.bend[base + j] = rowptr[i + 1];
+  }
+  for (int64_t i = 0; i < nt; i++) {
+    const int32_t e0 = rowptr[i], e1 = rowptr[i + 1];
+    if (e1 - e0 <= kHeavyRow) {
+      light_rows++;
+      light_nnz += e1 - e0;
+      continue;
+    }
+    H.hrow.push_back((int32_t)i);
+    H.hc0.push_back(nchunks);
+    for (int32_t e = e0; e < e1; e += kChunk) {
+      H.crow.push_back((int32_t)i);
+      H.cbeg.push_back(e);
+      H.cend.push_back(std::min(e + kChunk, e1));
+      nchunks++;
+    }
+    H.hc1.push_back(nchunks);
+    nheavy++;
+  }
+  B.nchunks = nchunks;
+  B.nheavy = nheavy;
+  B.lanes = lanes_for(light_rows, light_nnz);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -308,6 +370,12 @@ struct irls_mincut_s {
   irls_round_stats *dstats = nullptr;
   int64_t stats_cap = 0;            // records dstats holds
   int64_t last_iters = 0;           // CG iterations of the last round solved (chunk sizing)
+  // resident solver: heavy-row chunks (device) and the single graph's record
+  int32_t *hv_crow = nullptr, *hv_cbeg = nullptr, *hv_cend = nullptr;
+  int32_t *hv_hrow = nullptr, *hv_hc0 = nullptr, *hv_hc1 = nullptr;
+  int32_t *hv_brow = nullptr, *hv_bbeg = nullptr, *hv_bend = nullptr;
+  double *hv_part = nullptr;
+  BatchGraph res_graph;             // single-graph handles with solver 2
   Scalars *pinned = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   // resident solver (one graph, or every graph of a batch)
@@ -423,9 +491,12 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
   // cg_maxit iterations need cg_maxit + 1 direction launches
   const int64_t maxit = h->opt.cg_maxit + 1;
   // first chunk: the previous round's count (counts rarely fall between
-  // rounds); then small chunks, so at most two chunks run past convergence
-  int64_t first = pred > 0 ? std::max<int64_t>(16, pred) : 32;
-  int64_t next = pred > 0 ? 16 : 32;
+  // rounds); then chunks of 8, so at most two chunks run past convergence.
+  // A launch past convergence still issues its first loads, so the chunks
+  // stay short; 8 iterations (hundreds of microseconds on large systems)
+  // outlast the host's read-back and relaunch.
+  int64_t first = pred > 0 ? std::max<int64_t>(8, pred) : 16;
+  int64_t next = 8;
   if (h->opt.chunk > 0) first = next = h->opt.chunk;
   first = std::min(first, maxit);
   HIPCHK(h, launch_iterations(h, a, 0, first), "CG launch");
@@ -551,6 +622,16 @@ irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
   a.stats = h->dstats;
   a.next_graph = h->rnext;
   a.order = h->rorder;
+  a.chunk_row = h->hv_crow;
+  a.chunk_beg = h->hv_cbeg;
+  a.chunk_end = h->hv_cend;
+  a.heavy_row = h->hv_hrow;
+  a.heavy_c0 = h->hv_hc0;
+  a.heavy_c1 = h->hv_hc1;
+  a.chunk_part = h->hv_part;
+  a.bin_row = h->hv_brow;
+  a.bin_beg = h->hv_bbeg;
+  a.bin_end = h->hv_bend;
   a.rounds = o.rounds;
   a.eps0 = o.eps0;
   a.eps_factor = o.eps_factor;
@@ -638,14 +719,15 @@ irls_status alloc_state(irls_mincut_t h) {
     HIPCHK(h, h->dalloc(&h->rgraphs, 1), "alloc");
     HIPCHK(h, h->dalloc(&h->rorder, 1), "alloc");
     HIPCHK(h, h->dalloc(&h->rnext, 1), "alloc");
-    BatchGraph rg;
-    std::memset(&rg, 0, sizeof(rg));
+    BatchGraph rg = h->res_graph;      // heavy-row counts and lanes from create
+    rg.node0 = 0;
+    rg.nnz0 = 0;
+    rg.node_off = 0;
     rg.nt = nt;
     rg.s = h->g.s;
     rg.t = h->g.t;
     rg.cst = h->g.cst;
     rg.fx_k = h->g.fx_k;
-    rg.lanes = lanes_for(nt, h->g.nnz);
     rg.no_source_edges = h->g.no_source_edges ? 1 : 0;
     int32_t zero = 0;
     HIPCHK(h, hipMemcpy(h->rgraphs, &rg, sizeof(rg), hipMemcpyHostToDevice), "upload");
@@ -659,6 +741,18 @@ template <typename T>
 irls_status upload(irls_mincut_t h, T **dst, const std::vector<T> &src) {
   HIPCHK(h, h->dalloc(dst, src.size()), "alloc");
   if (!src.empty()) HIPCHK(h, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return IRLS_OK;
+}
+
+irls_status upload_heavy(irls_mincut_t h, const HeavyLists &H) {
+  irls_status rc;
+  if ((rc = upload(h, &h->hv_crow, H.crow)) != IRLS_OK || (rc = upload(h, &h->hv_cbeg, H.cbeg)) != IRLS_OK ||
+      (rc = upload(h, &h->hv_cend, H.cend)) != IRLS_OK || (rc = upload(h, &h->hv_hrow, H.hrow)) != IRLS_OK ||
+      (rc = upload(h, &h->hv_hc0, H.hc0)) != IRLS_OK || (rc = upload(h, &h->hv_hc1, H.hc1)) != IRLS_OK ||
+      (rc = upload(h, &h->hv_brow, H.brow)) != IRLS_OK || (rc = upload(h, &h->hv_bbeg, H.bbeg)) != IRLS_OK ||
+      (rc = upload(h, &h->hv_bend, H.bend)) != IRLS_OK)
+    return rc;
+  HIPCHK(h, h->dalloc(&h->hv_part, H.crow.size() * kChunkQ), "alloc");
   return IRLS_OK;
 }
 
@@ -763,12 +857,16 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
       while (L < 64 && L < avg) L <<= 1;
       h->rpw = o.rows_per_wave ? o.rows_per_wave : 64 / L;
     }
+    HeavyLists H;
+    std::memset(&h->res_graph, 0, sizeof(h->res_graph));
+    if (h->solver == 2) add_heavy_rows(hg.rowptr, hg.nt, H, h->res_graph);
     if ((rc = upload(h, &g.rowptr, hg.rowptr)) != IRLS_OK ||
         (rc = upload(h, &g.col, hg.col)) != IRLS_OK ||
         (rc = upload(h, &g.ccap, hg.ccap)) != IRLS_OK ||
         (rc = upload(h, &g.cs, hg.cs)) != IRLS_OK ||
         (rc = upload(h, &g.ct, hg.ct)) != IRLS_OK ||
         (use_dia && (rc = upload(h, &g.dcap, hg.dcap)) != IRLS_OK) ||
+        (rc = upload_heavy(h, H)) != IRLS_OK ||
         (rc = alloc_state(h)) != IRLS_OK) {
       g_thread_error = h->err;
       h->release();
@@ -969,6 +1067,21 @@ irls_status irls_mincut_info(irls_mincut_t h, int64_t *n_nonterminal, int64_t *n
   return IRLS_OK;
 }
 
+irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *grid) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch || h->solver != 1) { h->err = "only the multi-workgroup solver has an SpMV kernel"; return IRLS_ERR_OPTIONS; }
+  if (h->opt.precision == 1) {
+    const CGArgs<float> a = make_args<float>(h);
+    if (variant) *variant = spmv_variant(a);
+    if (grid) *grid = a.grid_spmv;
+  } else {
+    const CGArgs<double> a = make_args<double>(h);
+    if (variant) *variant = spmv_variant(a);
+    if (grid) *grid = a.grid_spmv;
+  }
+  return IRLS_OK;
+}
+
 irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps, double *avg_ms) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (!avg_ms) { h->err = "avg_ms must not be NULL"; return IRLS_ERR_NULL; }
@@ -1087,6 +1200,7 @@ irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t G, const int64_
     std::vector<int32_t> rowptr, col;
     std::vector<double> ccap, cs, ct;
     std::vector<BatchGraph> graphs(G);
+    HeavyLists heavy;
     std::vector<uint32_t> gid;
     std::vector<i128> D0s(G);
     int64_t rows = 0, nnz = 0;
@@ -1106,7 +1220,7 @@ irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t G, const int64_
       B.t = t[g];
       B.cst = hg.cst;
       B.fx_k = hg.fx_k;
-      B.lanes = lanes_for(hg.nt, (int64_t)hg.col.size());
+      add_heavy_rows(hg.rowptr, hg.nt, heavy, B);
       B.no_source_edges = hg.no_source_edges ? 1 : 0;
       D0s[g] = hg.D0;
       rowptr.insert(rowptr.end(), hg.rowptr.begin(), hg.rowptr.end());
@@ -1149,7 +1263,7 @@ irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t G, const int64_
         (rc = upload(h, &gd.ccap, ccap)) != IRLS_OK || (rc = upload(h, &gd.cs, cs)) != IRLS_OK ||
         (rc = upload(h, &gd.ct, ct)) != IRLS_OK || (rc = upload(h, &h->rgraphs, graphs)) != IRLS_OK ||
         (rc = upload(h, &h->rorder, order)) != IRLS_OK || (rc = upload(h, &h->gid, gid)) != IRLS_OK ||
-        (rc = alloc_state(h)) != IRLS_OK) {
+        (rc = upload_heavy(h, heavy)) != IRLS_OK || (rc = alloc_state(h)) != IRLS_OK) {
       g_thread_error = h->err;
       h->release();
       delete h;

@@ -116,6 +116,8 @@ template <typename T> hipError_t launch_assemble(const CGArgs<T> &a, int grid, h
 template <typename T> hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st);
 // SpMV grid and kernel choice for a system: sets a.grid_spmv and a.march_planes
 template <typename T> void spmv_layout(CGArgs<T> &a, int grid_main);
+// 0 CSR, 1 diagonal (a row per thread), 2 diagonal (R-row vectors), 3 diagonal marching
+template <typename T> int spmv_variant(const CGArgs<T> &a);
 template <typename T> hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave,
                                              bool fused_dia, hipStream_t st);
 template <typename T> hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st);
@@ -129,6 +131,18 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
 
 // One graph of a batch (the single-graph resident solver uses one of these).
 // Rows of all graphs are concatenated; each graph keeps local CSR indices.
+// Rows with more than kHeavyRow entries (the hubs of power-law graphs) are
+// not walked by one lane group in the resident solver: their entries are cut
+// into chunks of kChunk (one wavefront each) whose partial sums are then
+// added per row in a fixed order.
+constexpr int32_t kHeavyRow = 128;
+constexpr int32_t kChunk = 64;
+constexpr int kChunkQ = 4;        // partial sums kept per chunk (the most any pass needs)
+// Light rows are binned by length: bin b holds rows of at most 2^(b+1)
+// entries (bin 5: at most 128), walked by groups of min(2^(b+1), 64) lanes,
+// so the lanes of a wavefront finish their rows together.
+constexpr int kBins = 6;
+
 struct BatchGraph {
   int64_t node0;                  // first row in the concatenated non-terminal arrays
   int64_t nt;                     // rows of this graph
@@ -136,8 +150,13 @@ struct BatchGraph {
   int64_t node_off;               // first node id of this graph in the caller's arrays
   int64_t s, t;                   // local source and sink
   double cst;                     // s-t capacity
+  int64_t chunk0;                 // first chunk of this graph's heavy rows
+  int64_t heavy0;                 // first heavy-row record of this graph
+  int32_t nchunks, nheavy;        // its chunks and heavy rows
+  int32_t bin[kBins + 1];         // light rows of bin b: [bin[b], bin[b+1]) of its binned list
+  int32_t nnz;                    // its CSR entries
   int32_t fx_k;                   // fixed-point scale of its cut values
-  int32_t lanes;                  // SpMV lanes per row (64 / rows per wavefront)
+  int32_t lanes;                  // lanes per light row (64 / rows per wavefront)
   int32_t no_source_edges;
   int32_t pad;
 };
@@ -153,6 +172,14 @@ struct ResidentArgs {
   irls_round_stats *stats;        // [G * (T+1)]
   unsigned *next_graph;           // work-queue counter
   const int32_t *order;           // graph processing order (largest first)
+  // heavy rows, per graph at chunk0 / heavy0: chunk c covers local entries
+  // [chunk_beg[c], chunk_end[c]) of local row chunk_row[c]; heavy row h is
+  // local row heavy_row[h] with chunks [heavy_c0[h], heavy_c1[h]) of its graph
+  const int32_t *chunk_row, *chunk_beg, *chunk_end;
+  const int32_t *heavy_row, *heavy_c0, *heavy_c1;
+  double *chunk_part;             // [total chunks * kChunkQ] partial sums
+  // light rows by bin, per graph at node0: local row and its entry range
+  const int32_t *bin_row, *bin_beg, *bin_end;
   int32_t rounds;
   double eps0, eps_factor;
   int32_t form, init, warm;

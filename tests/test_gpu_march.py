@@ -42,6 +42,7 @@ def test_march_matches_oracle(P, oracle_mod, case, precision):
     So, vo, _, _ = oracle_mod.sweep(g, xo)
     with P.MinCut.from_graph(g, solver=1, precision=precision, **OPTS) as mc:
         info = mc.info()
+        assert mc.spmv_kernel()[0] == "k_spmv_dia_march"
         rc, st = mc.solve()
         x = mc.potentials()
         S, v, _ = mc.cut()
@@ -54,3 +55,12 @@ def test_march_matches_oracle(P, oracle_mod, case, precision):
     else:
         assert err <= 1e-4
         assert abs(v - vo) <= 1e-4 * vo
+
+
+def test_small_planes_use_the_vector_kernel(P):
+    """64 x 64: a plane (x-row) of 32 FP64 groups is less than a tile, so the
+    row-slab vector kernel runs instead."""
+    with P.MinCut.from_graph(gen.grid2d(64, 64, seed=0), solver=1) as mc:
+        assert mc.spmv_kernel()[0] == "k_spmv_dia_vec"
+    with P.MinCut.from_graph(gen.grid2d(64, 64, seed=0), solver=1, format=1) as mc:
+        assert mc.spmv_kernel()[0] == "k_spmv_csr"
