@@ -256,8 +256,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not part of it "
-              "(see the sharding design in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the library solves on one GPU; run with --gpus 1 (multi-GPU runs are "
+              "not supported)", file=sys.stderr)
         sys.exit(2)
 
     import torch
