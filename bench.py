@@ -40,6 +40,9 @@ WORKLOADS = {
                      dict(rounds=40, cg_rtol=1e-8, precision=1, refine_every=20),
                      "3-D 256^3 segmentation grid, FP32 conductances/SpMV/CG vectors, FP64 "
                      "potentials, dots and residual replacement every 20 CG steps"),
+    "seg128-bj": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8, precond=1),
+                  "3-D 128^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi "
+                  "preconditioner (x-lines of 128 rows, tridiagonal blocks)"),
     "gnn192": (dict(kind="gnn", train64=24, train128=4, eval_n=192, eval_seeds=8),
                dict(rounds=40, cg_rtol=1e-8),
                "learned warm start: network trained on 64^3 and 128^3 segmentation grids, "

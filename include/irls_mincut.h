@@ -74,6 +74,15 @@ typedef struct {
   int32_t inputs_on_device;   /* 1: edge arrays and x0 are device pointers */
   int32_t rows_per_wave;      /* CSR SpMV rows per 64-lane wavefront: 0 autotune, else
                                  1,2,4,...,64 */
+  int32_t precond;            /* 0: Jacobi, M = diag(L~) (default);
+                                 1: block-Jacobi (Section 3.1), M = the principal submatrices
+                                    of L~ over blocks of block_size consecutive rows, each
+                                    solved exactly.  Needs a grid (diagonal format, offsets
+                                    1 < off[1] < ...), FP64 and the multi-workgroup solver;
+                                    a block then lies inside one line of offset-1 edges, so
+                                    it is tridiagonal */
+  int32_t block_size;         /* precond 1: rows per block, even, 2..128 and at most
+                                 off[1]; 0 = min(off[1], 128) rounded down to even */
 } irls_options;
 
 /* Per-round record (round 0 first). */

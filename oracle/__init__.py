@@ -21,7 +21,8 @@ _U8P = C.POINTER(C.c_uint8)
 class Options(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("eps0", C.c_double), ("eps_factor", C.c_double),
                 ("weight_form", C.c_int32), ("init", C.c_int32), ("warm_start", C.c_int32),
-                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int64), ("threads", C.c_int32)]
+                ("cg_rtol", C.c_double), ("cg_maxit", C.c_int64), ("threads", C.c_int32),
+                ("precond", C.c_int32), ("block_size", C.c_int32)]
 
 
 class Round(C.Structure):

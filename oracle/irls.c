@@ -9,9 +9,13 @@
  * the rows and columns of s and t and b_u is the conductance of edge {u,s}.
  * Round 0 uses W = C, i.e. conductance = capacity.
  *
- * Section 3.1: the system is solved by preconditioned CG (Saad's PCG) with a
- * Jacobi preconditioner here (diagonal blocks of size one), warm-started
- * from the previous round's solution when requested.
+ * Section 3.1: the system is solved by preconditioned CG (Saad's PCG),
+ * warm-started from the previous round's solution when requested, with the
+ * paper's block-Jacobi preconditioner: M = blockdiag of the principal
+ * submatrices of L~ over blocks of consecutive rows.  Blocks of size one
+ * (precond 0) are the Jacobi preconditioner; precond 1 uses blocks of
+ * block_size rows, each factored by a dense Cholesky factorisation once per
+ * round and applied by forward and back substitution.
  *
  * Two conductance forms are provided:
  *   form 0: g = c / sqrt(d^2 + eps)
@@ -41,6 +45,8 @@ void orc_options_default(orc_options *o) {
   o->cg_rtol = 1e-10;
   o->cg_maxit = 100000;
   o->threads = 0;
+  o->precond = 0;
+  o->block_size = 1;
 }
 
 int orc_max_threads(void) {
@@ -111,8 +117,70 @@ static void spmv(const ograph *g, const osys *S, const double *p, double *q) {
   }
 }
 
-/* Jacobi PCG from the initial guess in v; returns status, fills iters/res */
-static int pcg(const ograph *g, const osys *S, double *v, double rtol, int64_t maxit,
+/* block-Jacobi preconditioner: dense Cholesky factors L (lower, row-major
+ * bs x bs) of each block's principal submatrix of L~ */
+typedef struct {
+  int64_t bs, nblk;
+  double *L;          /* [nblk][bs][bs] */
+} oprec;
+
+static void prec_factor(const ograph *g, const osys *S, oprec *P) {
+  const int64_t nt = g->nt, bs = P->bs;
+  #pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < P->nblk; k++) {
+    const int64_t lo = k * bs, hi = lo + bs < nt ? lo + bs : nt, nb = hi - lo;
+    double *A = P->L + (size_t)k * bs * bs;
+    for (int64_t i = 0; i < bs * bs; i++) A[i] = 0.0;
+    for (int64_t i = lo; i < hi; i++) {          /* the block of L~ = D - W */
+      A[(i - lo) * bs + (i - lo)] = S->D[i];
+      for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) {
+        const int64_t j = g->nb[a];
+        if (j >= lo && j < hi) A[(i - lo) * bs + (j - lo)] -= S->w[a];
+      }
+    }
+    for (int64_t j = 0; j < nb; j++) {           /* Cholesky A = L L^T, in place */
+      double d = A[j * bs + j];
+      for (int64_t c = 0; c < j; c++) d -= A[j * bs + c] * A[j * bs + c];
+      d = sqrt(d);
+      A[j * bs + j] = d;
+      for (int64_t i = j + 1; i < nb; i++) {
+        double x = A[i * bs + j];
+        for (int64_t c = 0; c < j; c++) x -= A[i * bs + c] * A[j * bs + c];
+        A[i * bs + j] = x / d;
+      }
+    }
+  }
+}
+
+/* z = M^-1 r */
+static void prec_apply(const ograph *g, const osys *S, const oprec *P, const double *r, double *z) {
+  const int64_t nt = g->nt;
+  if (!P) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nt; i++) z[i] = r[i] / S->D[i];
+    return;
+  }
+  const int64_t bs = P->bs;
+  #pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < P->nblk; k++) {
+    const int64_t lo = k * bs, hi = lo + bs < nt ? lo + bs : nt, nb = hi - lo;
+    const double *L = P->L + (size_t)k * bs * bs;
+    for (int64_t i = 0; i < nb; i++) {           /* L y = r */
+      double x = r[lo + i];
+      for (int64_t c = 0; c < i; c++) x -= L[i * bs + c] * z[lo + c];
+      z[lo + i] = x / L[i * bs + i];
+    }
+    for (int64_t i = nb - 1; i >= 0; i--) {      /* L^T z = y */
+      double x = z[lo + i];
+      for (int64_t c = i + 1; c < nb; c++) x -= L[c * bs + i] * z[lo + c];
+      z[lo + i] = x / L[i * bs + i];
+    }
+  }
+}
+
+/* PCG from the initial guess in v; returns status, fills iters/res.
+ * P == NULL: Jacobi. */
+static int pcg(const ograph *g, const osys *S, const oprec *P, double *v, double rtol, int64_t maxit,
                double *r, double *z, double *p, double *q, int64_t *iters, double *relres) {
   int64_t nt = g->nt;
   double bnorm = sqrt(dot(S->b, S->b, nt));
@@ -126,7 +194,8 @@ static int pcg(const ograph *g, const osys *S, double *v, double rtol, int64_t m
   for (int64_t i = 0; i < nt; i++) r[i] = S->b[i] - q[i];
   double rnorm = sqrt(dot(r, r, nt));
   if (rnorm <= rtol * bnorm) { *relres = rnorm / bnorm; return ORC_OK; }
-  for (int64_t i = 0; i < nt; i++) { z[i] = r[i] / S->D[i]; p[i] = z[i]; }
+  prec_apply(g, S, P, r, z);
+  for (int64_t i = 0; i < nt; i++) p[i] = z[i];
   double rho = dot(r, z, nt);
   int64_t k = 0;
   while (k < maxit) {
@@ -139,8 +208,7 @@ static int pcg(const ograph *g, const osys *S, double *v, double rtol, int64_t m
     k++;
     rnorm = sqrt(dot(r, r, nt));
     if (rnorm <= rtol * bnorm) break;
-    #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < nt; i++) z[i] = r[i] / S->D[i];
+    prec_apply(g, S, P, r, z);
     double rho_new = dot(r, z, nt);
     double beta = rho_new / rho;
     rho = rho_new;
@@ -213,7 +281,8 @@ int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
   if (!x_out) return ORC_ERR_NULL;
   if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
       !(o.cg_rtol > 0.0) || o.cg_maxit < 1 || (o.rounds > 0 && !(o.eps0 > 0.0)) ||
-      !(o.eps_factor > 0.0) || o.eps_factor > 1.0)
+      !(o.eps_factor > 0.0) || o.eps_factor > 1.0 || o.precond < 0 || o.precond > 1 ||
+      (o.precond == 1 && o.block_size < 1))
     return ORC_ERR_OPTIONS;
   if (o.init == 2 && !x0) return ORC_ERR_NULL;
 #ifdef _OPENMP
@@ -235,8 +304,16 @@ int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
   double *z = (double *)malloc(sizeof(double) * nv);
   double *p = (double *)malloc(sizeof(double) * nv);
   double *q = (double *)malloc(sizeof(double) * nv);
+  oprec Pr = {0, 0, NULL}, *P = NULL;
   int status = ORC_OK;
   if (!S.w || !S.ws || !S.wt || !S.D || !S.b || !v || !r || !z || !p || !q) { status = ORC_ERR_NOMEM; goto done; }
+  if (o.precond == 1 && nt > 0) {
+    Pr.bs = o.block_size < nt ? o.block_size : nt;
+    Pr.nblk = (nt + Pr.bs - 1) / Pr.bs;
+    Pr.L = (double *)malloc(sizeof(double) * (size_t)Pr.nblk * Pr.bs * Pr.bs);
+    if (!Pr.L) { status = ORC_ERR_NOMEM; goto done; }
+    P = &Pr;
+  }
 
   if (o.init == 2) {
     for (int64_t i = 0; i < nt; i++) {
@@ -256,15 +333,17 @@ int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
     int st = ORC_OK;
     if (l == 0) {
       assemble(&g, &S, v, 1, 0.0, o.weight_form);
+      if (P) prec_factor(&g, &S, P);
       if (o.init == 0) {                          /* x(0): WLS with W0 = C, cold start */
         for (int64_t i = 0; i < nt; i++) v[i] = 0.0;
-        st = nt ? pcg(&g, &S, v, o.cg_rtol, o.cg_maxit, r, z, p, q, &it, &rel) : ORC_OK;
+        st = nt ? pcg(&g, &S, P, v, o.cg_rtol, o.cg_maxit, r, z, p, q, &it, &rel) : ORC_OK;
       }
       R.eps = 0.0;
     } else {
       assemble(&g, &S, v, 0, eps, o.weight_form);
+      if (P) prec_factor(&g, &S, P);
       if (!o.warm_start) for (int64_t i = 0; i < nt; i++) v[i] = 0.0;
-      st = nt ? pcg(&g, &S, v, o.cg_rtol, o.cg_maxit, r, z, p, q, &it, &rel) : ORC_OK;
+      st = nt ? pcg(&g, &S, P, v, o.cg_rtol, o.cg_maxit, r, z, p, q, &it, &rel) : ORC_OK;
       R.eps = eps;
     }
     R.cg_iters = it;
@@ -284,6 +363,7 @@ int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
 done:
   free(S.w); free(S.ws); free(S.wt); free(S.D); free(S.b);
   free(v); free(r); free(z); free(p); free(q);
+  free(Pr.L);
   og_free(&g);
   return status;
 }

@@ -40,6 +40,9 @@ typedef struct {
   double  cg_rtol;       /* stop when ||r||_2 <= rtol ||b||_2 */
   int64_t cg_maxit;
   int32_t threads;       /* OpenMP threads, 0 = runtime default */
+  int32_t precond;       /* 0: Jacobi (diagonal); 1: block-Jacobi, blocks of block_size
+                            consecutive non-terminal rows (the principal submatrices of L~) */
+  int32_t block_size;    /* rows per block for precond 1 (>= 1) */
 } orc_options;
 
 typedef struct {

@@ -25,7 +25,7 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("refine_every", C.c_int32),
                 ("fp64_weights_below_eps", C.c_double), ("format", C.c_int32),
                 ("solver", C.c_int32), ("chunk", C.c_int32), ("inputs_on_device", C.c_int32),
-                ("rows_per_wave", C.c_int32)]
+                ("rows_per_wave", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32)]
 
 
 class RoundStats(C.Structure):

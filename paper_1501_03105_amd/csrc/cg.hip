@@ -125,10 +125,13 @@ __global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
       ru = bu;
     }
     T rt = (T)ru;
-    T zt = rt / a.D[u];
-    a.z[u] = zt;                               // z = M^-1 r is what CG keeps
-    double zu = (double)zt;
-    x[0] += (double)rt * zu;
+    if (a.bj_block > 0) {                      // block-Jacobi: z and r^T z come from k_bj_apply
+      a.rbuf[u] = ru;
+    } else {
+      T zt = rt / a.D[u];
+      a.z[u] = zt;                             // z = M^-1 r is what CG keeps
+      x[0] += (double)rt * (double)zt;
+    }
     x[1] += bu * bu;
     x[2] += (double)rt * (double)rt;
   }
@@ -732,6 +735,111 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
   }
 }
 
+// ----------------------------------------------------------------------------
+// Block-Jacobi (Section 3.1).  Blocks are bj_block consecutive rows inside one
+// line of offset-1 edges, so each block of L~ is tridiagonal:
+//   diagonal D_i, sub- and super-diagonal -w0 (w0[i] couples rows i and i+1).
+// Its LU factors are formed once per round (Thomas): pivot m_i = D_i - a_i c'_{i-1}
+// with a_i = c_{i-1} = -w0[i-1], c'_i = c_i / m_i.  Applying M^-1 is the forward
+// recurrence y_i = f_i y_{i-1} + r_i / m_i (f_i = -a_i / m_i) and the backward one
+// z_i = y_i + g_i z_{i+1} (g_i = -c'_i); both are affine maps composed by a
+// wavefront scan, one block (up to 128 rows, 2 per lane) per wavefront.
+// ----------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bj_factor(CGArgs<T> a) {
+  const int64_t B = a.bj_block, nb = (a.nt + B - 1) / B;
+  const T *w0 = a.w;
+  for (int64_t k = row_begin(); k < nb; k += row_stride()) {
+    const int64_t lo = k * B, hi = lo + B < a.nt ? lo + B : a.nt;
+    double cprev = 0.0;                        // c'_{i-1}
+    for (int64_t i = lo; i < hi; i++) {
+      const double ai = i > lo ? -(double)w0[i - 1] : 0.0;
+      const double ci = i + 1 < hi ? -(double)w0[i] : 0.0;
+      const double m = (double)a.D[i] - ai * cprev;
+      const double im = 1.0 / m;
+      const double cp = ci * im;
+      a.bj_f[i] = -ai * im;
+      a.bj_im[i] = im;
+      a.bj_g[i] = -cp;
+      cprev = cp;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bj_apply(CGArgs<T> a, int slot) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  if (block_done(a.sc)) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t B = a.bj_block, nb = (a.nt + B - 1) / B;
+  double x[1] = {0.0};
+  for (int64_t k = wave; k < nb; k += nwaves) {
+    const int64_t lo = k * B, hi = lo + B < a.nt ? lo + B : a.nt;
+    const int64_t u0 = lo + 2 * lane;
+    const bool v0 = u0 < hi, v1 = u0 + 1 < hi;
+    const double r0 = v0 ? a.rbuf[u0] : 0.0, r1 = v1 ? a.rbuf[u0 + 1] : 0.0;
+    const double f0 = v0 ? a.bj_f[u0] : 0.0, f1 = v1 ? a.bj_f[u0 + 1] : 0.0;
+    const double i0 = v0 ? a.bj_im[u0] : 0.0, i1 = v1 ? a.bj_im[u0 + 1] : 0.0;
+    const double g0 = v0 ? a.bj_g[u0] : 0.0, g1 = v1 ? a.bj_g[u0 + 1] : 0.0;
+    // forward: this lane's pair maps y before it to y at its second row
+    double A = f1 * f0, Bv = f1 * (i0 * r0) + i1 * r1;
+    for (int d = 1; d < 64; d <<= 1) {
+      const double Ap = __shfl_up(A, d, 64), Bp = __shfl_up(Bv, d, 64);
+      if (lane >= d) {
+        Bv = A * Bp + Bv;
+        A = A * Ap;
+      }
+    }
+    double yprev = __shfl_up(Bv, 1, 64);
+    if (lane == 0) yprev = 0.0;
+    const double y0 = f0 * yprev + i0 * r0, y1 = Bv;
+    // backward: this lane's pair maps z after it to z at its first row
+    double Cm = g0 * g1, Cb = y0 + g0 * y1;
+    for (int d = 1; d < 64; d <<= 1) {
+      const double Cn = __shfl_down(Cm, d, 64), Cbn = __shfl_down(Cb, d, 64);
+      if (lane + d < 64) {
+        Cb = Cm * Cbn + Cb;
+        Cm = Cm * Cn;
+      }
+    }
+    double znext = __shfl_down(Cb, 1, 64);
+    if (lane == 63) znext = 0.0;
+    const double z0 = Cb, z1 = y1 + g1 * znext;
+    if (v0) a.z[u0] = (T)z0;
+    if (v1) a.z[u0 + 1] = (T)z1;
+    x[0] += r0 * z0 + r1 * z1;
+  }
+  write_partials<1>(x, a.partials, slot, lds);
+}
+
+// vector update with the residual kept explicitly (block-Jacobi):
+// v += alpha p, r -= alpha q; partial sums [0, ||r||^2] (k_bj_apply fills r^T z)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_bj(CGArgs<T> a) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  __shared__ double bc[4];
+  Scalars *sc = a.sc;
+  int64_t it;
+  double alpha, pq;
+  if (!cg_update_start(a, lds, bc, it, alpha, pq)) return;
+  const T *__restrict__ p = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;
+  double x[2] = {0.0, 0.0};
+  FOR_ROWS(u, a.nt) {
+    a.v[u] += alpha * (double)p[u];
+    const double ru = a.rbuf[u] - alpha * (double)a.q[u];
+    a.rbuf[u] = ru;
+    x[1] += ru * ru;
+  }
+  write_partials<2>(x, a.partials, kPUpd, lds);
+  if (first_thread()) {
+    sc->iter_b = it + 1;
+    sc->alpha = alpha;
+    sc->pq = pq;
+  }
+}
+
 // precision 1: r = b - L~ v in FP64 replaces the recursive FP32 residual every
 // refine_every iterations and whenever the recursive residual claims
 // convergence (the stopping test then uses the true residual)
@@ -969,8 +1077,22 @@ hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st) {
 }
 
 template <typename T>
+hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_bj_factor<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
+  hipLaunchKernelGGL((k_bj_apply<T>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
-  if (a.nt % kVecRows<T> == 0)
+  if (a.bj_block > 0)
+    hipLaunchKernelGGL((k_update_bj<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  else if (a.nt % kVecRows<T> == 0)
     hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>>), dim3(grid), dim3(kBlock), 0, st, a);
   else
     hipLaunchKernelGGL((k_update<T>), dim3(grid), dim3(kBlock), 0, st, a);
@@ -1013,6 +1135,8 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
   template int spmv_variant<T>(const CGArgs<T> &);                                         \
   template hipError_t launch_direction<T>(const CGArgs<T> &, int, hipStream_t);            \
   template hipError_t launch_update<T>(const CGArgs<T> &, int, hipStream_t);               \
+  template hipError_t launch_bj_factor<T>(const CGArgs<T> &, int, hipStream_t);            \
+  template hipError_t launch_bj_apply<T>(const CGArgs<T> &, int, int, hipStream_t);        \
   template hipError_t launch_replace_residual<T>(const CGArgs<T> &, int, hipStream_t);     \
   template hipError_t launch_stats<T>(const CGArgs<T> &, int, hipStream_t);
 IRLS_INSTANTIATE(double)

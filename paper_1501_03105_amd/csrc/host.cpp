@@ -255,11 +255,16 @@ irls_status check_options(const irls_options &o, std::string &err) {
       o.refine_every < 0 || o.format < 0 || o.format > 2 || o.solver < 0 || o.solver > 2 ||
       o.chunk < 0 || (o.warm_start != 0 && o.warm_start != 1) ||
       (o.inputs_on_device != 0 && o.inputs_on_device != 1) || o.rows_per_wave < 0 ||
-      o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0) {
+      o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0 || o.precond < 0 ||
+      o.precond > 1 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0) {
     err = "an option is out of range";
     return IRLS_ERR_OPTIONS;
   }
   if (o.precision == 1 && o.solver == 2) { err = "the resident solver runs in FP64 only"; return IRLS_ERR_OPTIONS; }
+  if (o.precond == 1 && (o.precision != 0 || o.solver == 2 || o.format == 1)) {
+    err = "block-Jacobi runs in FP64 on the multi-workgroup solver in the diagonal format";
+    return IRLS_ERR_OPTIONS;
+  }
   return IRLS_OK;
 }
 
@@ -370,6 +375,8 @@ struct irls_mincut_s {
   irls_round_stats *dstats = nullptr;
   int64_t stats_cap = 0;            // records dstats holds
   int64_t last_iters = 0;           // CG iterations of the last round solved (chunk sizing)
+  int32_t bj_block = 0;             // block-Jacobi rows per block (0: Jacobi)
+  double *bj_r = nullptr, *bj_f = nullptr, *bj_im = nullptr, *bj_g = nullptr;
   // resident solver: heavy-row chunks (device) and the single graph's record
   int32_t *hv_crow = nullptr, *hv_cbeg = nullptr, *hv_cend = nullptr;
   int32_t *hv_hrow = nullptr, *hv_hc0 = nullptr, *hv_hc1 = nullptr;
@@ -462,6 +469,11 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.weights_fp64 = 1;
   a.grid_main = h->grid;
   spmv_layout(a, h->grid);
+  a.bj_block = h->bj_block;
+  a.rbuf = h->bj_r;
+  a.bj_f = h->bj_f;
+  a.bj_im = h->bj_im;
+  a.bj_g = h->bj_g;
   return a;
 }
 
@@ -477,6 +489,7 @@ hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a0, int64_t first
     if (a.K == 0) e = launch_direction(a, h->grid, h->stream);
     if (e == hipSuccess) e = launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream);
     if (e == hipSuccess) e = launch_update(a, h->grid, h->stream);
+    if (e == hipSuccess && a.bj_block > 0) e = launch_bj_apply(a, h->grid, kPUpd, h->stream);
     if (e == hipSuccess && h->opt.precision == 1) e = launch_replace_residual(a, h->grid, h->stream);
   }
   return e;
@@ -569,6 +582,7 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
     const int32_t refine = o.refine_every > 0 ? o.refine_every : INT32_MAX;
     HIPCHK(h, launch_scalars_reset(h->sc, o.cg_maxit, fp64 ? 0 : refine, h->stream), "reset");
     if (nt > 0) HIPCHK(h, launch_assemble(a, h->grid, h->stream), "assemble");
+    if (nt > 0 && a.bj_block > 0) HIPCHK(h, launch_bj_factor(a, h->grid, h->stream), "block-Jacobi factors");
     bool solve = !(l == 0 && o.init != 0) && nt > 0;
     if (solve && h->g.no_source_edges) {
       HIPCHK(h, launch_fill(h->v, nt, 0.0, h->stream), "fill");
@@ -576,6 +590,7 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
     }
     if (solve) {
       HIPCHK(h, launch_cginit(a, h->grid, h->stream), "cg init");
+      if (a.bj_block > 0) HIPCHK(h, launch_bj_apply(a, h->grid, kPInit, h->stream), "block-Jacobi apply");
       int64_t it = 0;
       int st = IRLS_OK;
       irls_status rc = run_cg(h, a, pred, &it, &st);
@@ -693,6 +708,12 @@ irls_status alloc_state(irls_mincut_t h) {
   };
   HIPCHK(h, h->dalloc(&h->v, nt), "alloc");
   HIPCHK(h, h->dalloc(&h->b, nt), "alloc");
+  if (h->bj_block > 0) {
+    HIPCHK(h, h->dalloc(&h->bj_r, nt), "alloc");
+    HIPCHK(h, h->dalloc(&h->bj_f, nt), "alloc");
+    HIPCHK(h, h->dalloc(&h->bj_im, nt), "alloc");
+    HIPCHK(h, h->dalloc(&h->bj_g, nt), "alloc");
+  }
   HIPCHK(h, h->dalloc(&h->gt, nt), "alloc");
   HIPCHK(h, rawalloc(&h->w, nw * ts), "alloc");
   HIPCHK(h, rawalloc(&h->D, nt * ts), "alloc");
@@ -791,6 +812,8 @@ void irls_options_default(irls_options *o) {
   o->chunk = 0;
   o->inputs_on_device = 0;
   o->rows_per_wave = 0;
+  o->precond = 0;
+  o->block_size = 0;
 }
 
 irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const int64_t *edge_u,
@@ -839,7 +862,8 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
     g.cmax = hg.cmax;
     g.no_source_edges = hg.no_source_edges;
     h->D0 = hg.D0;
-    h->solver = o.solver ? o.solver : ((o.precision == 0 && hg.nt <= kResidentMaxRows) ? 2 : 1);
+    h->solver = o.solver ? o.solver
+                         : ((o.precision == 0 && o.precond == 0 && hg.nt <= kResidentMaxRows) ? 2 : 1);
     if (h->solver == 2 && o.format == 2) {
       g_thread_error = "the resident solver stores the graph in CSR form";
       delete h;
@@ -850,6 +874,22 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
     g.format = use_dia ? 2 : 1;
     g.K = use_dia ? hg.K : 0;
     for (int k = 0; k < kMaxDiag; k++) g.off[k] = hg.off[k];
+    if (o.precond == 1) {
+      // blocks of consecutive rows inside one line of offset-1 edges
+      if (!use_dia || hg.off[0] != 1) {
+        g_thread_error = "block-Jacobi needs a graph in the diagonal format with offset 1";
+        delete h;
+        return IRLS_ERR_OPTIONS;
+      }
+      const int32_t line = hg.K >= 2 ? hg.off[1] : 128;
+      int32_t B = o.block_size ? o.block_size : std::min<int32_t>(line, 128) & ~1;
+      if (B < 2 || B > line) {
+        g_thread_error = "block_size must be even, at least 2 and at most the offset-1 line length";
+        delete h;
+        return IRLS_ERR_OPTIONS;
+      }
+      h->bj_block = B;
+    }
     h->grid = grid_for(hg.nt);
     {
       double avg = hg.nt > 0 ? (double)hg.col.size() / (double)hg.nt : 1.0;

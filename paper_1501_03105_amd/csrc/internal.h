@@ -70,6 +70,11 @@ struct CGArgs {
   int32_t weights_fp64;           // precision 1: compute conductances in FP64
   double cst;                     // s-t capacity
   double rtol;                    // CG stopping tolerance relative to ||b||
+  // block-Jacobi (precond 1, FP64): the residual kept explicitly and, per row,
+  // the forward multiplier, 1/pivot and backward multiplier of its block's
+  // tridiagonal LU factors; bj_block rows per block (0: Jacobi)
+  double *rbuf, *bj_f, *bj_im, *bj_g;
+  int32_t bj_block;
   int32_t grid_main;              // workgroups of the init / update / replacement kernels
   int32_t grid_spmv;              // workgroups of the SpMV kernel (its partial-sum count)
   int32_t march_planes;           // diagonal SpMV marching along off[K-1]: planes per
@@ -122,6 +127,9 @@ template <typename T> hipError_t launch_spmv(const CGArgs<T> &a, int grid, int r
                                              bool fused_dia, hipStream_t st);
 template <typename T> hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st);
+// block-Jacobi: factors once per round, and z = M^-1 r with r^T z into partial slot `slot`
+template <typename T> hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st);
+template <typename T> hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t st);
 template <typename T> hipError_t launch_replace_residual(const CGArgs<T> &a, int grid,
                                                          hipStream_t st);
 template <typename T> hipError_t launch_stats(const CGArgs<T> &a, int grid, hipStream_t st);

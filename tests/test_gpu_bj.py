@@ -1,0 +1,62 @@
+"""Block-Jacobi preconditioning (Section 3.1) on the GPU against the oracle's
+block-Jacobi PCG: blocks of consecutive rows inside one line of offset-1
+edges (tridiagonal), factored once per round and applied by wavefront scans."""
+import numpy as np
+import pytest
+
+import gen
+from tests.gpu_util import max_pot_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1501_03105_amd as P
+    P.lib()
+    return P
+
+
+OPTS = dict(rounds=20, cg_rtol=1e-10)
+
+
+def cases():
+    return [("grid2d 64x64, lines of 64", gen.grid2d(64, 64, seed=0), 0, 64),
+            ("grid2d 64x64, blocks of 2", gen.grid2d(64, 64, seed=0), 2, 2),
+            ("grid2d 64x64, blocks of 48 (not dividing a line)", gen.grid2d(64, 64, seed=0), 48, 48),
+            ("seg 24^3, lines of 24", gen.grid3d_seg(24, seed=6), 0, 24),
+            ("box 32x32 + partial plane (marching SpMV)", gen.grid3d_box(32, 32, 32 * 32 * 10 + 500, seed=3), 32, 32)]
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_block_jacobi_matches_oracle(P, oracle_mod, case):
+    name, g, bs, bs_oracle = cases()[case]
+    say(f"block-Jacobi: {name}")
+    xo, so, _ = oracle_mod.irls(g, precond=1, block_size=bs_oracle, **OPTS)
+    So, vo, _, _ = oracle_mod.sweep(g, xo)
+    _, sj, _ = oracle_mod.irls(g, **OPTS)
+    with P.MinCut.from_graph(g, precond=1, block_size=bs, **OPTS) as mc:
+        assert mc.info()["solver"] == 1 and mc.info()["format"] == 2
+        rc, st = mc.solve()
+        x = mc.potentials()
+        S, v, _ = mc.cut()
+    err = max_pot_err(x, xo)
+    it_g = [r["cg_iters"] for r in st]
+    it_o = [r["cg_iters"] for r in so]
+    say(f"  potential error {err:.2e}; CG iterations {sum(it_g)} (oracle {sum(it_o)}, Jacobi {sum(r['cg_iters'] for r in sj)})")
+    assert rc == P.OK
+    assert err <= 1e-8
+    assert v == vo and np.array_equal(S, So)
+    assert all(abs(a - b) <= max(3, 0.02 * b) for a, b in zip(it_g, it_o))
+    assert all(r["true_rel_res"] <= 1e-9 for r in st)
+
+
+def test_block_jacobi_option_errors(P):
+    g = gen.grid2d(16, 16, seed=1)
+    for kw in (dict(precision=1), dict(format=1), dict(solver=2), dict(block_size=3),
+               dict(block_size=18), dict(block_size=130)):
+        assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=1, **kw) == P.ERR_OPTIONS, kw
+    h = gen.gnp(16, 0.3, seed=2)                       # no diagonal layout
+    assert P.create_error(h.n, h.eu, h.ev, h.cap, h.s, h.t, precond=1) == P.ERR_OPTIONS

@@ -382,3 +382,46 @@ def test_degenerate_graphs(oracle_mod):
     assert x[3] == 0.0
     inS, val, _, _ = oracle_mod.sweep(g, x)
     assert val == pytest.approx(1.1) and not inS[3]
+
+
+# ---------------------------------------------------------------------------
+# block-Jacobi preconditioner (Section 3.1: blocks of the reduced Laplacian)
+# ---------------------------------------------------------------------------
+def test_block_jacobi_single_block_is_the_exact_solve(oracle_mod):
+    """One block covering every row makes M = L~: PCG then ends after one
+    iteration of every round, and the rounds still match the series circuit
+    (same check as the Jacobi run above)."""
+    caps = [0.9, 0.35, 0.8, 0.6, 0.25, 1.1, 0.7]
+    g = path_graph(caps)
+    k = len(caps) - 1
+    x, st, _ = oracle_mod.irls(g, rounds=6, cg_rtol=1e-14, precond=1, block_size=k)
+    assert all(r["cg_iters"] <= 1 for r in st)
+    xj, _, _ = oracle_mod.irls(g, rounds=6, cg_rtol=1e-14)
+    np.testing.assert_allclose(x, xj, rtol=0, atol=1e-12)
+    g2 = gen.gnp(16, 0.3, seed=7)
+    _, st2, _ = oracle_mod.irls(g2, rounds=5, cg_rtol=1e-12, precond=1, block_size=14)
+    assert all(r["cg_iters"] <= 1 for r in st2)
+
+
+def test_block_jacobi_size_one_is_jacobi(oracle_mod):
+    """Blocks of one row are the diagonal: same iteration counts, potentials
+    equal up to the rounding of sqrt(D)^2 against D."""
+    g = gen.grid2d(20, 16, seed=2)
+    xj, sj, _ = oracle_mod.irls(g, rounds=12, cg_rtol=1e-10)
+    xb, sb, _ = oracle_mod.irls(g, rounds=12, cg_rtol=1e-10, precond=1, block_size=1)
+    assert [r["cg_iters"] for r in sj] == [r["cg_iters"] for r in sb]
+    np.testing.assert_allclose(xb, xj, rtol=0, atol=1e-11)
+
+
+def test_block_jacobi_same_solution_fewer_iterations(oracle_mod):
+    """Line blocks of a grid: the rounds converge to the same potentials (the
+    preconditioner changes the path, not the system) in fewer CG iterations;
+    block sizes that do not divide the row count leave a short last block."""
+    g = gen.grid3d_seg(10, seed=4)
+    xj, sj, _ = oracle_mod.irls(g, rounds=15, cg_rtol=1e-12)
+    for bs in (10, 7, 100):
+        xb, sb, _ = oracle_mod.irls(g, rounds=15, cg_rtol=1e-12, precond=1, block_size=bs)
+        np.testing.assert_allclose(xb, xj, rtol=0, atol=1e-8)
+        assert sum(r["cg_iters"] for r in sb) < sum(r["cg_iters"] for r in sj)
+    assert oracle_mod.error_code(oracle_mod.irls, g, rounds=1, precond=1, block_size=0) != 0
+    assert oracle_mod.error_code(oracle_mod.irls, g, rounds=1, precond=2) != 0
