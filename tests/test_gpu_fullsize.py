@@ -51,8 +51,15 @@ def test_fullsize_sweep_and_invariants(P, oracle_mod, seg128):
         assert r["flow_t"] == pytest.approx(r["flow"], rel=1e-3), l
         assert r["s_eps"] <= prev * (1 + 1e-9), l                        # MM descent
         prev = r["s_eps"]
-    # chain: the sweep value is at most ||CBx||_1 of the same potentials
+    # chain: the sweep value is at most ||CBx||_1 of the same potentials, and
+    # at least the exact minimum cut (push-relabel); delta is the paper's
+    # relative excess over the minimum (Table 4)
     assert val <= st[-1]["l1"] * (1 + 1e-12)
+    _, mu = oracle_mod.maxflow(g)
+    delta = (val - mu) / mu
+    say(f"128^3: exact minimum cut {mu!r}, delta {delta:.2e}")
+    assert val >= mu * (1 - 1e-12)
+    assert delta < 1e-3
 
 
 @pytest.mark.parametrize("l", [1, 25])
