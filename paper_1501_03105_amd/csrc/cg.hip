@@ -454,40 +454,46 @@ struct MarchStep {
   vec_t<T, R> wb[KM], zb[KM], pb[KM];       // and backward
 };
 
+// A step's loads are unconditional, so the compiler can keep the next step's
+// loads in flight while it waits for this one's.  A neighbour row outside the
+// matrix is read at a valid index instead, chosen so that its product
+// vanishes: a direction or residual value from row u0 meets a conductance
+// that is zero there (the edge to a row past the end is stored as 0), and a
+// conductance of an edge from before row 0 is read where one is known to be
+// 0 (offset 1 at row nt - 1; offset o >= R at rows nt - R .. nt - 1).  nt and
+// every offset are multiples of R, so a group lies wholly inside or outside.
 template <typename T, int K, int R>
 __device__ __forceinline__ void march_load_p(const CGArgs<T> &a, const T *pin, int64_t u0, MarchStep<T, K, R> &s) {
-  const vec_t<T, R> zero = (T)0;
   const int64_t nt = a.nt, P = a.off[K - 1];
-  s.pp = u0 + P < nt ? vload<T, R>(pin + u0 + P) : zero;
-  s.pr = u0 + R < nt ? pin[u0 + R] : (T)0;
-  s.pl = u0 > 0 ? pin[u0 - 1] : (T)0;
+  s.pp = vload<T, R>(pin + (u0 + P < nt ? u0 + P : u0));     // unused past the last plane
+  s.pr = pin[u0 + R < nt ? u0 + R : u0];
+  s.pl = pin[u0 > 0 ? u0 - 1 : u0];
 #pragma unroll
   for (int kk = 1; kk < K - 1; kk++) {
     const int64_t o = a.off[kk];
-    s.pf[kk - 1] = u0 + o < nt ? vload<T, R>(pin + u0 + o) : zero;
-    s.pb[kk - 1] = u0 >= o ? vload<T, R>(pin + u0 - o) : zero;
+    s.pf[kk - 1] = vload<T, R>(pin + (u0 + o < nt ? u0 + o : u0));
+    s.pb[kk - 1] = vload<T, R>(pin + (u0 >= o ? u0 - o : u0));
   }
 }
 
 template <typename T, int K, int R>
 __device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int64_t u0, MarchStep<T, K, R> &s) {
-  const vec_t<T, R> zero = (T)0;
   const int64_t nt = a.nt, P = a.off[K - 1];
-  s.zp = u0 + P < nt ? vload<T, R>(a.z + u0 + P) : zero;
+  s.zp = vload<T, R>(a.z + (u0 + P < nt ? u0 + P : u0));
   s.D = vload<T, R>(a.D + u0);
   s.w0 = vload<T, R>(a.w + u0);
   s.wP = vload<T, R>(a.w + (K - 1) * nt + u0);
-  s.zr = u0 + R < nt ? a.z[u0 + R] : (T)0;
-  s.wl = u0 > 0 ? a.w[u0 - 1] : (T)0;
-  s.zl = u0 > 0 ? a.z[u0 - 1] : (T)0;
+  s.zr = a.z[u0 + R < nt ? u0 + R : u0];
+  s.wl = a.w[u0 > 0 ? u0 - 1 : nt - 1];
+  s.zl = a.z[u0 > 0 ? u0 - 1 : u0];
 #pragma unroll
   for (int kk = 1; kk < K - 1; kk++) {
     const int64_t o = a.off[kk];
     const bool f = u0 + o < nt, b = u0 >= o;
-    s.wf[kk - 1] = f ? vload<T, R>(a.w + kk * nt + u0) : zero;
-    s.zf[kk - 1] = f ? vload<T, R>(a.z + u0 + o) : zero;
-    s.wb[kk - 1] = b ? vload<T, R>(a.w + kk * nt + u0 - o) : zero;
-    s.zb[kk - 1] = b ? vload<T, R>(a.z + u0 - o) : zero;
+    s.wf[kk - 1] = vload<T, R>(a.w + kk * nt + u0);
+    s.zf[kk - 1] = vload<T, R>(a.z + (f ? u0 + o : u0));
+    s.wb[kk - 1] = vload<T, R>(a.w + kk * nt + (b ? u0 - o : nt - R));
+    s.zb[kk - 1] = vload<T, R>(a.z + (b ? u0 - o : u0));
   }
   march_load_p(a, pin, u0, s);
 }
@@ -587,13 +593,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
     zk = st.zp;
     pk = st.pp;
   };
+  // Two steps in flight: s0 holds step k and s1 step k + 1; the buffer a step
+  // frees is refilled with the step two planes on while the other computes.
+  // The first pair runs before the loop, so the loop is entered with the same
+  // loads outstanding, in the same order, as at its back edge (else the waits
+  // at its top would cover both buffers).  The last two or three steps follow.
   if (active) {
-    step(s0, k0);
-    if (two) step(s1, k0 + 1);
-    for (int64_t k = k0 + 2; k < kend; k++) {
-      march_load(a, pin, c + P * k, s0);
+    int64_t k = k0;
+    auto pair = [&]() {
       step(s0, k);
+      march_load(a, pin, c + P * (k + 2), s0);
+      __builtin_amdgcn_sched_barrier(0);                // keep the two steps apart
+      step(s1, k + 1);
+      march_load(a, pin, c + P * (k + 3), s1);
+      __builtin_amdgcn_sched_barrier(0);
+      k += 2;
+    };
+    if (k + 3 < kend) {
+      pair();
+      while (k + 3 < kend) pair();
     }
+    step(s0, k);
+    if (k + 2 < kend) march_load(a, pin, c + P * (k + 2), s0);
+    if (k + 1 < kend) step(s1, k + 1);
+    if (k + 2 < kend) step(s0, k + 2);
   }
   write_partials<1>(x, a.partials, kPSpmv, lds);
 }
@@ -681,51 +704,75 @@ __global__ __launch_bounds__(kBlock) void k_update(CGArgs<T> a) {
 }
 
 // Vectorised k_update: R consecutive rows per thread (nt divisible by R).
+// The row groups of a thread are processed in pairs from two register
+// buffers, so the loads of one group are in flight while the other computes;
+// the first two groups are loaded before the start-of-kernel reduction.
+template <typename T, int R>
+struct UpdGroup {
+  vec_t<T, R> p, z, q, D;
+  vec_t<double, R> v;
+};
+
 template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   typedef vec_t<T, R> V;
-  typedef vec_t<double, R> VD;
   const int64_t ng = a.nt / R;
   int64_t gb, ge, gs;
   slab_rows(ng, gb, ge, gs);
   const UpdateStartLoads sl = cg_update_load(a);      // first: the reduction waits only for these
-  // the first row group's loads go out before the start-of-kernel reduction
   const T *__restrict__ p = (a.K > 0 && (a.it_hint & 1) == 0) ? a.p1 : a.p0;
-  V pv, zv, qv, Dv;
-  VD vv;
-  if (gb < ge) {
-    const int64_t u0 = gb * R;
-    pv = vload<T, R>(p + u0); zv = vload<T, R>(a.z + u0); qv = vload<T, R>(a.q + u0);
-    Dv = vload<T, R>(a.D + u0); vv = vload<double, R>(a.v + u0);
-  }
+  auto load = [&](int64_t g, UpdGroup<T, R> &b) {
+    const int64_t u0 = g * R;
+    b.p = vload<T, R>(p + u0); b.z = vload<T, R>(a.z + u0); b.q = vload<T, R>(a.q + u0);
+    b.D = vload<T, R>(a.D + u0); b.v = vload<double, R>(a.v + u0);
+  };
+  UpdGroup<T, R> b0, b1;
+  if (gb < ge) load(gb, b0);
+  if (gb + gs < ge) load(gb + gs, b1);
   Scalars *sc = a.sc;
   int64_t it;
   double alpha, pq;
   if (!cg_update_finish(a, sl, lds, bc, it, alpha, pq)) return;
   if (((it ^ a.it_hint) & 1) != 0 && a.K > 0) {        // the host's guess was wrong
     p = (it & 1) == 0 ? a.p1 : a.p0;
-    if (gb < ge) pv = vload<T, R>(p + gb * R);
+    if (gb < ge) b0.p = vload<T, R>(p + gb * R);
+    if (gb + gs < ge) b1.p = vload<T, R>(p + (gb + gs) * R);
   }
   double x[2] = {0.0, 0.0};
-  for (int64_t gi = gb; gi < ge; gi += gs) {
-    const int64_t u0 = gi * R;
-    if (gi != gb) {
-      pv = vload<T, R>(p + u0); zv = vload<T, R>(a.z + u0); qv = vload<T, R>(a.q + u0);
-      Dv = vload<T, R>(a.D + u0); vv = vload<double, R>(a.v + u0);
-    }
+  auto work = [&](int64_t g, UpdGroup<T, R> &b) {
     V zn;
 #pragma unroll
     for (int i = 0; i < R; i++) {
-      vv[i] += alpha * (double)pv[i];
-      const T ru = (T)((double)Dv[i] * (double)zv[i] - alpha * (double)qv[i]);
-      zn[i] = ru / Dv[i];
+      b.v[i] += alpha * (double)b.p[i];
+      const T ru = (T)((double)b.D[i] * (double)b.z[i] - alpha * (double)b.q[i]);
+      zn[i] = ru / b.D[i];
       x[0] += (double)ru * (double)zn[i];
       x[1] += (double)ru * (double)ru;
     }
-    vstore<double, R>(a.v + u0, vv);
-    vstore<T, R>(a.z + u0, zn);
+    vstore<double, R>(a.v + g * R, b.v);
+    vstore<T, R>(a.z + g * R, zn);
+  };
+  int64_t g = gb;
+  if (g + 3 * gs < ge) {                               // loop entered with both buffers' loads in flight
+    auto pair = [&]() {
+      work(g, b0);
+      load(g + 2 * gs, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      work(g + gs, b1);
+      load(g + 3 * gs, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      g += 2 * gs;
+    };
+    pair();
+    while (g + 3 * gs < ge) pair();
+  }
+  if (g < ge) {
+    work(g, b0);
+    if (g + 2 * gs < ge) load(g + 2 * gs, b0);
+    if (g + gs < ge) work(g + gs, b1);
+    if (g + 2 * gs < ge) work(g + 2 * gs, b0);
   }
   write_partials<2>(x, a.partials, kPUpd, lds);
   if (first_thread()) {
@@ -999,8 +1046,10 @@ bool vec_ok(const CGArgs<T> &a) {
 
 // Marching needs the vector layout, at least two planes, and planes of at
 // least one full tile (kBlock groups); the chunk length keeps the grid near
-// kMarchGrid workgroups (two per CU).
-constexpr int kMarchGrid = 512;
+// kMarchGrid workgroups: one per CU, each keeping two steps of loads in
+// flight per thread (measured faster than two or four per CU on 256^3 grids,
+// and no slower on 128^3, where the longer chunks halve the re-read seams).
+constexpr int kMarchGrid = 256;
 
 template <typename T>
 void spmv_layout(CGArgs<T> &a, int grid_main) {
