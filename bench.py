@@ -62,12 +62,15 @@ def make_graph(spec):
     return gen.grid2d(spec["nx"], spec["ny"], seed=spec["seed"])
 
 
-def spmv_bytes(info, precision):
+def spmv_bytes(info, precision, variant):
     """Algorithmic bytes of one SpMV launch (each array element touched once)."""
     nt, nnz, K = info["n_nonterminal"], info["nnz_offdiag"], info["n_diagonals"]
     ts = 4 if precision == 1 else 8
+    if variant == 4:
+        # scaled system: reads K scaled conductances, z, p_old; writes p_new, q
+        return nt * (ts * (K + 2) + 2 * ts)
     if info["format"] == 2:
-        # reads D, K conductances, r, p_old; writes p_new, q
+        # reads D, K conductances, z, p_old; writes p_new, q
         return nt * (ts * (K + 3) + 2 * ts)
     # CSR: values + column indices + row pointers, D, p, q
     return nnz * (ts + 4) + (nt + 1) * 4 + nt * 3 * ts
@@ -154,9 +157,31 @@ def bench_batch(args, spec, opts, desc):
     dt = time.perf_counter() - t0
     iters = [sum(r["cg_iters"] for r in s) for s in st]
     mb.close()
+    # The plain FP64 GPU path (one multi-workgroup solve per graph, one graph
+    # after another) on every 16th graph in size order, each after one untimed
+    # solve; its summed time x 16 estimates that path's time for the whole
+    # batch.  Its cuts are compared with the batch's.
+    order = sorted(range(len(gs)), key=lambda i: gs[i].n)
+    sample = order[8::16]
+    t_plain, worst = 0.0, 0.0
+    for i in sample:
+        with P.MinCut.from_graph(gs[i], stream=torch.cuda.current_stream(), solver=1, **opts) as mc:
+            mc.solve()                                       # warm-up, as for the batch
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mc.solve()
+            _, v1, _ = mc.cut()
+            torch.cuda.synchronize()
+            t_plain += time.perf_counter() - t0
+        worst = max(worst, abs(v1 - vals[i]) / max(abs(vals[i]), 1e-300))
+    plain_rate = len(sample) / t_plain
+    print(f"[bench] plain FP64 path, {len(sample)} sampled graphs one by one: {t_plain:.2f} s "
+          f"({plain_rate:.1f} cuts/s); largest cut difference from the batch {worst:.1e}",
+          file=sys.stderr, flush=True)
+    rate = len(gs) * args.steps / dt
     out = {
         "metric": "IRLS s-t min-cut throughput of the batched form (cuts per second)",
-        "value": round(len(gs) * args.steps / dt, 3), "unit": "cuts/s", "n_gpus": 1,
+        "value": round(rate, 3), "unit": "cuts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
@@ -164,7 +189,13 @@ def bench_batch(args, spec, opts, desc):
                    "nodes": int(sum(g.n for g in gs)),
                    "interior_edges": int(sum(g.meta["interior"] for g in gs)),
                    "cg_iters_total": int(sum(iters)), "cg_iters_max_graph": int(max(iters)),
-                   "setup_s": round(t_setup, 3)},
+                   "setup_s": round(t_setup, 3),
+                   "plain_fp64_one_by_one": {
+                       "cuts_per_s": round(plain_rate, 3),
+                       "speedup_of_batch": round(rate / plain_rate, 2),
+                       "max_rel_cut_difference": worst,
+                       "sample": f"every 16th graph in size order ({len(sample)} graphs), "
+                                 "multi-workgroup FP64 solver, solve + sweep each"}},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))
@@ -310,9 +341,10 @@ def main():
     if info["solver"] == 1:
         spmv_ms = mc.time_kernel(0, args.kernel_reps)
         upd_ms = mc.time_kernel(1, args.kernel_reps)
-        nbytes = spmv_bytes(info, opts.get("precision", 0))
+        variant, spmv_grid = mc.spmv_variant()
+        kname = mc.SPMV_KERNELS[variant]
+        nbytes = spmv_bytes(info, opts.get("precision", 0), variant)
         achieved = nbytes / (spmv_ms * 1e-3) / 1e9
-        kname, spmv_grid = mc.spmv_kernel()
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(kname, args.workload), "kernel": kname,

@@ -83,6 +83,11 @@ typedef struct {
                                     it is tridiagonal */
   int32_t block_size;         /* precond 1: rows per block, even, 2..128 and at most
                                  off[1]; 0 = min(off[1], 128) rounded down to even */
+  int32_t unscaled_cg;        /* 0 (default): where the marching SpMV runs (3-D grids) with
+                                 Jacobi in FP64, CG runs on the symmetrically scaled system
+                                 D^-1/2 L~ D^-1/2 -- in exact arithmetic the same iterates as
+                                 Jacobi PCG (Section 3.1), but the SpMV reads no diagonal;
+                                 1: always the z = D^-1 r form */
 } irls_options;
 
 /* Per-round record (round 0 first). */
@@ -170,8 +175,9 @@ irls_status irls_mincut_info(irls_mincut_t h, int64_t *n_nonterminal, int64_t *n
  * workgroup count.  variant: 0 CSR (rows_per_wave rows per wavefront),
  * 1 diagonal format with a row per thread, 2 diagonal with 16-byte row
  * vectors, 3 diagonal marching along the largest offset (the plane of a 3-D
- * grid, the row of a 2-D one).  IRLS_ERR_OPTIONS for the resident solver or a
- * batch. */
+ * grid, the row of a 2-D one), 4 the marching kernel on the symmetrically
+ * scaled system (no diagonal read; see unscaled_cg).  IRLS_ERR_OPTIONS for
+ * the resident solver or a batch. */
 irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *grid);
 
 /* Time one hot kernel of the CG loop on the handle's stream with HIP events:

@@ -25,7 +25,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("refine_every", C.c_int32),
                 ("fp64_weights_below_eps", C.c_double), ("format", C.c_int32),
                 ("solver", C.c_int32), ("chunk", C.c_int32), ("inputs_on_device", C.c_int32),
-                ("rows_per_wave", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32)]
+                ("rows_per_wave", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32),
+                ("unscaled_cg", C.c_int32)]
 
 
 class RoundStats(C.Structure):
@@ -223,15 +224,21 @@ class MinCut:
         return dict(n_nonterminal=nt.value, nnz_offdiag=nnz.value, format=fmt.value,
                     n_diagonals=K.value, solver=sol.value, rows_per_wave=rpw.value)
 
-    SPMV_KERNELS = {0: "k_spmv_csr", 1: "k_spmv_dia", 2: "k_spmv_dia_vec", 3: "k_spmv_dia_march"}
+    SPMV_KERNELS = {0: "k_spmv_csr", 1: "k_spmv_dia", 2: "k_spmv_dia_vec", 3: "k_spmv_dia_march",
+                    4: "k_spmv_dia_march"}
 
-    def spmv_kernel(self):
-        """(kernel name, workgroups) of the CG loop's SpMV (irls_mincut_spmv_kernel)."""
+    def spmv_variant(self):
+        """(variant, workgroups) of the CG loop's SpMV (irls_mincut_spmv_kernel)."""
         v, g = C.c_int32(), C.c_int32()
         rc = lib().irls_mincut_spmv_kernel(self.h, C.byref(v), C.byref(g))
         if rc != OK:
             raise self._err(rc)
-        return self.SPMV_KERNELS[v.value], g.value
+        return v.value, g.value
+
+    def spmv_kernel(self):
+        """(kernel name, workgroups) of the CG loop's SpMV."""
+        v, g = self.spmv_variant()
+        return self.SPMV_KERNELS[v], g
 
     def time_kernel(self, which=0, reps=50):
         ms = C.c_double(0)

@@ -127,6 +127,10 @@ __global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
     T rt = (T)ru;
     if (a.bj_block > 0) {                      // block-Jacobi: z and r^T z come from k_bj_apply
       a.rbuf[u] = ru;
+    } else if (a.scaled) {                     // scaled form: z = D^-1/2 r, r^T M^-1 r = z^T z
+      const T zt = (T)(ru / sqrt((double)a.D[u]));
+      a.z[u] = zt;
+      x[0] += (double)zt * (double)zt;
     } else {
       T zt = rt / a.D[u];
       a.z[u] = zt;                             // z = M^-1 r is what CG keeps
@@ -141,6 +145,30 @@ __global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
     a.sc->iter_a = 0;
     a.sc->done = 0;
     a.sc->status = IRLS_OK;
+  }
+}
+
+// Scaled form (Jacobi as symmetric scaling, diagonal layout): the scaled
+// conductances w_uj / sqrt(D_u D_j), 0 where the edge does not exist, and the
+// change of variables of the potentials, v <- D^1/2 v before CG and
+// v <- D^-1/2 v after it.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_w(CGArgs<T> a) {
+  FOR_ROWS(u, a.nt) {
+    const double du = (double)a.D[u];
+    for (int k = 0; k < a.K; k++) {
+      const int64_t j = u + a.off[k];
+      const double wv = j < a.nt ? (double)a.w[k * a.nt + u] : 0.0;
+      a.wh[k * a.nt + u] = (T)(wv != 0.0 ? wv / sqrt(du * (double)a.D[j]) : 0.0);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scale_v(CGArgs<T> a, int dir) {
+  FOR_ROWS(u, a.nt) {
+    const double sd = sqrt((double)a.D[u]);
+    a.v[u] = dir > 0 ? a.v[u] * sd : a.v[u] / sd;
   }
 }
 
@@ -476,23 +504,25 @@ __device__ __forceinline__ void march_load_p(const CGArgs<T> &a, const T *pin, i
   }
 }
 
-template <typename T, int K, int R>
+// SC: the scaled form (scaled conductances, unit diagonal: no D load).
+template <typename T, int K, int R, bool SC>
 __device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int64_t u0, MarchStep<T, K, R> &s) {
   const int64_t nt = a.nt, P = a.off[K - 1];
+  const T *__restrict__ w = SC ? a.wh : a.w;
   s.zp = vload<T, R>(a.z + (u0 + P < nt ? u0 + P : u0));
-  s.D = vload<T, R>(a.D + u0);
-  s.w0 = vload<T, R>(a.w + u0);
-  s.wP = vload<T, R>(a.w + (K - 1) * nt + u0);
+  if constexpr (!SC) s.D = vload<T, R>(a.D + u0);
+  s.w0 = vload<T, R>(w + u0);
+  s.wP = vload<T, R>(w + (K - 1) * nt + u0);
   s.zr = a.z[u0 + R < nt ? u0 + R : u0];
-  s.wl = a.w[u0 > 0 ? u0 - 1 : nt - 1];
+  s.wl = w[u0 > 0 ? u0 - 1 : nt - 1];
   s.zl = a.z[u0 > 0 ? u0 - 1 : u0];
 #pragma unroll
   for (int kk = 1; kk < K - 1; kk++) {
     const int64_t o = a.off[kk];
     const bool f = u0 + o < nt, b = u0 >= o;
-    s.wf[kk - 1] = vload<T, R>(a.w + kk * nt + u0);
+    s.wf[kk - 1] = vload<T, R>(w + kk * nt + u0);
     s.zf[kk - 1] = vload<T, R>(a.z + (f ? u0 + o : u0));
-    s.wb[kk - 1] = vload<T, R>(a.w + kk * nt + (b ? u0 - o : nt - R));
+    s.wb[kk - 1] = vload<T, R>(w + kk * nt + (b ? u0 - o : nt - R));
     s.zb[kk - 1] = vload<T, R>(a.z + (b ? u0 - o : u0));
   }
   march_load_p(a, pin, u0, s);
@@ -509,7 +539,7 @@ __device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of chunks,
 // so the planes at chunk seams are shared in its L2.  The summation order per
 // row is that of k_spmv_dia_vec.
-template <typename T, int K, int R>
+template <typename T, int K, int R, bool SC>
 __global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
@@ -541,10 +571,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
     if (k0 > 0) {
       zm = vload<T, R>(a.z + u - P);
       pm = vload<T, R>(pin + u - P);
-      wm = vload<T, R>(a.w + (K - 1) * nt + u - P);
+      wm = vload<T, R>((SC ? a.wh : a.w) + (K - 1) * nt + u - P);
     }
-    march_load(a, pin, u, s0);
-    if (two) march_load(a, pin, u + P, s1);
+    march_load<T, K, R, SC>(a, pin, u, s0);
+    if (two) march_load<T, K, R, SC>(a, pin, u + P, s1);
   }
   int64_t it;
   double beta64;
@@ -569,7 +599,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
   auto step = [&](const MarchStep<T, K, R> &st, int64_t k) {
     const int64_t u0 = c + P * k;
     const V pc = dir(zk, pk);
-    V acc = st.D * pc;
+    V acc;
+    if constexpr (SC) acc = pc;
+    else acc = st.D * pc;
     const T right = dirs(st.zr, st.pr), left = dirs(st.zl, st.pl);
 #pragma unroll
     for (int i = 0; i < R; i++) {
@@ -602,10 +634,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
     int64_t k = k0;
     auto pair = [&]() {
       step(s0, k);
-      march_load(a, pin, c + P * (k + 2), s0);
+      march_load<T, K, R, SC>(a, pin, c + P * (k + 2), s0);
       __builtin_amdgcn_sched_barrier(0);                // keep the two steps apart
       step(s1, k + 1);
-      march_load(a, pin, c + P * (k + 3), s1);
+      march_load<T, K, R, SC>(a, pin, c + P * (k + 3), s1);
       __builtin_amdgcn_sched_barrier(0);
       k += 2;
     };
@@ -614,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
       while (k + 3 < kend) pair();
     }
     step(s0, k);
-    if (k + 2 < kend) march_load(a, pin, c + P * (k + 2), s0);
+    if (k + 2 < kend) march_load<T, K, R, SC>(a, pin, c + P * (k + 2), s0);
     if (k + 1 < kend) step(s1, k + 1);
     if (k + 2 < kend) step(s0, k + 2);
   }
@@ -713,7 +745,9 @@ struct UpdGroup {
   vec_t<double, R> v;
 };
 
-template <typename T, int R>
+// SC: the scaled form, where z holds D^-1/2 r: z -= alpha q, r^T M^-1 r = z^T z
+// and ||r||^2 = sum D z^2.
+template <typename T, int R, bool SC>
 __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
@@ -746,10 +780,16 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < R; i++) {
       b.v[i] += alpha * (double)b.p[i];
-      const T ru = (T)((double)b.D[i] * (double)b.z[i] - alpha * (double)b.q[i]);
-      zn[i] = ru / b.D[i];
-      x[0] += (double)ru * (double)zn[i];
-      x[1] += (double)ru * (double)ru;
+      if constexpr (SC) {
+        zn[i] = (T)((double)b.z[i] - alpha * (double)b.q[i]);
+        x[0] += (double)zn[i] * (double)zn[i];
+        x[1] += (double)b.D[i] * (double)zn[i] * (double)zn[i];
+      } else {
+        const T ru = (T)((double)b.D[i] * (double)b.z[i] - alpha * (double)b.q[i]);
+        zn[i] = ru / b.D[i];
+        x[0] += (double)ru * (double)zn[i];
+        x[1] += (double)ru * (double)ru;
+      }
     }
     vstore<double, R>(a.v + g * R, b.v);
     vstore<T, R>(a.z + g * R, zn);
@@ -1029,6 +1069,18 @@ hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_scale_w(const CGArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_w<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_v(const CGArgs<T> &a, int dir, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_v<T>), dim3(grid), dim3(kBlock), 0, st, a, dir);
+  return hipGetLastError();
+}
+
 // rows per thread of the vectorised kernels: one 16-byte vector
 template <typename T>
 constexpr int kVecRows = 16 / (int)sizeof(T);
@@ -1074,7 +1126,7 @@ void spmv_layout(CGArgs<T> &a, int grid_main) {
 template <typename T>
 int spmv_variant(const CGArgs<T> &a) {
   if (a.K == 0) return 0;
-  if (a.march_planes > 0) return 3;
+  if (a.march_planes > 0) return a.scaled ? 4 : 3;
   return vec_ok(a) ? 2 : 1;
 }
 
@@ -1082,8 +1134,13 @@ template <typename T>
 hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hipStream_t st) {
   constexpr int R = kVecRows<T>;
   if (a.march_planes > 0) {
-    if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+    if (a.scaled) {
+      if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, true>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+      else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, true>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+    } else {
+      if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, false>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+      else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, false>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+    }
     return hipGetLastError();
   }
   if (a.K > 0 && vec_ok(a)) {
@@ -1141,8 +1198,10 @@ template <typename T>
 hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
   if (a.bj_block > 0)
     hipLaunchKernelGGL((k_update_bj<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  else if (a.scaled)
+    hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>, true>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.nt % kVecRows<T> == 0)
-    hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>>), dim3(grid), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>, false>), dim3(grid), dim3(kBlock), 0, st, a);
   else
     hipLaunchKernelGGL((k_update<T>), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();
@@ -1179,6 +1238,8 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
 #define IRLS_INSTANTIATE(T)                                                                  \
   template hipError_t launch_assemble<T>(const CGArgs<T> &, int, hipStream_t);             \
   template hipError_t launch_cginit<T>(const CGArgs<T> &, int, hipStream_t);               \
+  template hipError_t launch_scale_w<T>(const CGArgs<T> &, int, hipStream_t);              \
+  template hipError_t launch_scale_v<T>(const CGArgs<T> &, int, int, hipStream_t);         \
   template hipError_t launch_spmv<T>(const CGArgs<T> &, int, int, bool, hipStream_t);      \
   template void spmv_layout<T>(CGArgs<T> &, int);                                          \
   template int spmv_variant<T>(const CGArgs<T> &);                                         \

@@ -256,7 +256,8 @@ irls_status check_options(const irls_options &o, std::string &err) {
       o.chunk < 0 || (o.warm_start != 0 && o.warm_start != 1) ||
       (o.inputs_on_device != 0 && o.inputs_on_device != 1) || o.rows_per_wave < 0 ||
       o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0 || o.precond < 0 ||
-      o.precond > 1 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0) {
+      o.precond > 1 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0 ||
+      (o.unscaled_cg != 0 && o.unscaled_cg != 1)) {
     err = "an option is out of range";
     return IRLS_ERR_OPTIONS;
   }
@@ -369,6 +370,8 @@ struct irls_mincut_s {
   double *w64 = nullptr, *D64 = nullptr;
   // working-precision state (double for precision 0, float for 1)
   void *w = nullptr, *D = nullptr, *r = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
+  void *wh = nullptr;               // scaled conductances (scaled form only)
+  bool scaled = false;              // CG on D^-1/2 L~ D^-1/2 (Jacobi as symmetric scaling)
   double *partials = nullptr;
   double *vsave = nullptr;         // potentials saved across kernel timing
   Scalars *sc = nullptr, *sc_bench = nullptr;
@@ -474,6 +477,8 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.bj_f = h->bj_f;
   a.bj_im = h->bj_im;
   a.bj_g = h->bj_g;
+  a.wh = (T *)h->wh;
+  a.scaled = h->scaled ? 1 : 0;
   return a;
 }
 
@@ -583,6 +588,7 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
     HIPCHK(h, launch_scalars_reset(h->sc, o.cg_maxit, fp64 ? 0 : refine, h->stream), "reset");
     if (nt > 0) HIPCHK(h, launch_assemble(a, h->grid, h->stream), "assemble");
     if (nt > 0 && a.bj_block > 0) HIPCHK(h, launch_bj_factor(a, h->grid, h->stream), "block-Jacobi factors");
+    if (nt > 0 && a.scaled) HIPCHK(h, launch_scale_w(a, h->grid, h->stream), "scaling");
     bool solve = !(l == 0 && o.init != 0) && nt > 0;
     if (solve && h->g.no_source_edges) {
       HIPCHK(h, launch_fill(h->v, nt, 0.0, h->stream), "fill");
@@ -591,10 +597,12 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
     if (solve) {
       HIPCHK(h, launch_cginit(a, h->grid, h->stream), "cg init");
       if (a.bj_block > 0) HIPCHK(h, launch_bj_apply(a, h->grid, kPInit, h->stream), "block-Jacobi apply");
+      if (a.scaled) HIPCHK(h, launch_scale_v(a, +1, h->grid, h->stream), "scaling");
       int64_t it = 0;
       int st = IRLS_OK;
       irls_status rc = run_cg(h, a, pred, &it, &st);
       if (rc != IRLS_OK) return rc;
+      if (a.scaled) HIPCHK(h, launch_scale_v(a, -1, h->grid, h->stream), "scaling");
       pred = it;
       h->last_iters = it;
       if (st == IRLS_ERR_CG_BREAKDOWN) {
@@ -721,6 +729,7 @@ irls_status alloc_state(irls_mincut_t h) {
   HIPCHK(h, rawalloc(&h->q, nt * ts), "alloc");
   HIPCHK(h, rawalloc(&h->p0, nt * ts), "alloc");
   if (h->g.format == 2) HIPCHK(h, rawalloc(&h->p1, nt * ts), "alloc");
+  if (h->scaled) HIPCHK(h, rawalloc(&h->wh, nw * ts), "alloc");
   if (f32) {
     HIPCHK(h, h->dalloc(&h->w64, nw), "alloc");
     HIPCHK(h, h->dalloc(&h->D64, nt), "alloc");
@@ -814,6 +823,7 @@ void irls_options_default(irls_options *o) {
   o->rows_per_wave = 0;
   o->precond = 0;
   o->block_size = 0;
+  o->unscaled_cg = 0;
 }
 
 irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const int64_t *edge_u,
@@ -891,6 +901,10 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
       h->bj_block = B;
     }
     h->grid = grid_for(hg.nt);
+    // Jacobi as symmetric scaling wherever the marching SpMV runs with point
+    // Jacobi in FP64: that SpMV then reads no diagonal
+    if (use_dia && o.precision == 0 && o.precond == 0 && !o.unscaled_cg)
+      h->scaled = make_args<double>(h).march_planes > 0;
     {
       double avg = hg.nt > 0 ? (double)hg.col.size() / (double)hg.nt : 1.0;
       int L = 1;

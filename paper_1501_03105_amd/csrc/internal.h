@@ -59,6 +59,12 @@ struct CGArgs {
   double *v;                      // potentials (FP64 always)
   T *z, *q;                       // z = M^-1 r (Jacobi), q = L~ p
   T *p0, *p1;                     // direction, double-buffered for the fused diagonal kernel
+  // Jacobi as symmetric scaling (scaled = 1): CG runs on D^-1/2 L~ D^-1/2,
+  // whose unit diagonal needs no storage.  Then z holds D^-1/2 r, p and q the
+  // scaled direction and product, v holds D^1/2 v during CG, and wh the
+  // scaled conductances w_uj / sqrt(D_u D_j) in the diagonal layout.
+  T *wh;
+  int32_t scaled;
   // reductions
   double *partials;               // [kNumPSlots][kNumPartial][kMaxGrid]
   Scalars *sc;
@@ -119,6 +125,9 @@ struct SweepBufs {
 // ----------------------------------------------------------------------------
 template <typename T> hipError_t launch_assemble(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st);
+// scaled form: wh from w and D (after the assembly), and v <- D^(dir/2) v
+template <typename T> hipError_t launch_scale_w(const CGArgs<T> &a, int grid, hipStream_t st);
+template <typename T> hipError_t launch_scale_v(const CGArgs<T> &a, int dir, int grid, hipStream_t st);
 // SpMV grid and kernel choice for a system: sets a.grid_spmv and a.march_planes
 template <typename T> void spmv_layout(CGArgs<T> &a, int grid_main);
 // 0 CSR, 1 diagonal (a row per thread), 2 diagonal (R-row vectors), 3 diagonal marching

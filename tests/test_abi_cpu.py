@@ -60,7 +60,8 @@ def test_create_validation_errors(P):
     for kw in (dict(rounds=-1), dict(eps0=0.0), dict(eps_factor=1.5), dict(weight_form=2),
                dict(init=3), dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precision=2),
                dict(format=3), dict(solver=3), dict(rows_per_wave=3), dict(rows_per_wave=128),
-               dict(precision=1, solver=2), dict(struct_size=8)):
+               dict(precision=1, solver=2), dict(struct_size=8), dict(unscaled_cg=2),
+               dict(unscaled_cg=-1)):
         assert E(g.n, g.eu, g.ev, g.cap, g.s, g.t, **kw) == P.ERR_OPTIONS, kw
     # a graph that is not a grid cannot be forced into the diagonal format
     assert E(g.n, g.eu, g.ev, g.cap, g.s, g.t, format=2, solver=1) == P.ERR_OPTIONS

@@ -1,7 +1,8 @@
 """The diagonal SpMV that marches along the plane offset, against the CPU
 oracle.  Layouts chosen to hit its edge cases: a 2-D grid whose rows (the
 planes of two offsets) fill one and a fraction of a tile, and a 3-D box whose
-last plane is partial, in FP64 and in the FP32 form."""
+last plane is partial, in FP64 (on the symmetrically scaled system, the
+default, and in the z = D^-1 r form) and in the FP32 form."""
 import numpy as np
 import pytest
 
@@ -33,25 +34,36 @@ def cases():
             ("box 48x24, 7 planes + 36", gen.grid3d_box(48, 24, 48 * 24 * 7 + 36, seed=4))]
 
 
+FORMS = {"fp64": (dict(precision=0), 4),                       # scaled system (default)
+         "fp64-unscaled": (dict(precision=0, unscaled_cg=1), 3),  # z = D^-1 r form
+         "fp32": (dict(precision=1), 3)}
+
+
 @pytest.mark.parametrize("case", range(3))
-@pytest.mark.parametrize("precision", [0, 1])
-def test_march_matches_oracle(P, oracle_mod, case, precision):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_march_matches_oracle(P, oracle_mod, case, form):
     name, g = cases()[case]
-    say(f"march: {name}, precision {precision}")
+    kw, variant = FORMS[form]
+    say(f"march: {name}, {form}")
     xo, so, _ = oracle_mod.irls(g, **OPTS)
     So, vo, _, _ = oracle_mod.sweep(g, xo)
-    with P.MinCut.from_graph(g, solver=1, precision=precision, **OPTS) as mc:
+    with P.MinCut.from_graph(g, solver=1, **kw, **OPTS) as mc:
         info = mc.info()
+        assert mc.spmv_variant()[0] == variant
         assert mc.spmv_kernel()[0] == "k_spmv_dia_march"
         rc, st = mc.solve()
         x = mc.potentials()
         S, v, _ = mc.cut()
     assert info["format"] == 2 and info["n_diagonals"] == (2 if case == 0 else 3)
     err = max_pot_err(x, xo)
-    say(f"  potential error {err:.2e}; cut {v!r} vs {vo!r}")
-    if precision == 0:
+    it_g = [r["cg_iters"] for r in st]
+    it_o = [r["cg_iters"] for r in so]
+    say(f"  potential error {err:.2e}; cut {v!r} vs {vo!r}; CG iterations {sum(it_g)} (oracle {sum(it_o)})")
+    if kw["precision"] == 0:
         assert err <= 1e-8
         assert v == vo and np.array_equal(S, So)
+        assert all(abs(a - b) <= 3 for a, b in zip(it_g, it_o))
+        assert all(r["true_rel_res"] <= 1e-9 for r in st)
     else:
         assert err <= 1e-4
         assert abs(v - vo) <= 1e-4 * vo
