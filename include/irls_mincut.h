@@ -182,7 +182,9 @@ irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *
 
 /* Time one hot kernel of the CG loop on the handle's stream with HIP events:
  * `which` 0 = SpMV (with its fused direction update), 1 = the CG vector
- * update.  `reps` back-to-back launches after one warm-up launch; *avg_ms is
+ * update of an odd iteration, 2 = of an even one (they differ only on the
+ * scaled system, where the potentials move every second iteration: the odd
+ * update adds both steps).  `reps` back-to-back launches after one warm-up launch; *avg_ms is
  * the mean duration.  Needs a prior solve; overwrites the CG work vectors
  * (p, q; potentials untouched) -- call solve again before resuming. */
 irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps,

@@ -270,6 +270,7 @@ struct UpdateStartLoads {
   int32_t done;
   int64_t it;
   double rho0, rho1;
+  double alpha_even;   // alpha of the last even iteration (the scaled form's odd updates)
   double part[1];
 };
 
@@ -281,6 +282,7 @@ __device__ __forceinline__ UpdateStartLoads cg_update_load(const CGArgs<T> &a) {
   l.it = sc->iter_a;
   l.rho0 = sc->rho[0];
   l.rho1 = sc->rho[1];
+  l.alpha_even = sc->alpha_par[0];
   partial_share<1>(a.partials, kPSpmv, a.grid_spmv, l.part);
   return l;
 }
@@ -745,9 +747,7 @@ struct UpdGroup {
   vec_t<double, R> v;
 };
 
-// SC: the scaled form, where z holds D^-1/2 r: z -= alpha q, r^T M^-1 r = z^T z
-// and ||r||^2 = sum D z^2.
-template <typename T, int R, bool SC>
+template <typename T, int R>
 __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
@@ -780,16 +780,10 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < R; i++) {
       b.v[i] += alpha * (double)b.p[i];
-      if constexpr (SC) {
-        zn[i] = (T)((double)b.z[i] - alpha * (double)b.q[i]);
-        x[0] += (double)zn[i] * (double)zn[i];
-        x[1] += (double)b.D[i] * (double)zn[i] * (double)zn[i];
-      } else {
-        const T ru = (T)((double)b.D[i] * (double)b.z[i] - alpha * (double)b.q[i]);
-        zn[i] = ru / b.D[i];
-        x[0] += (double)ru * (double)zn[i];
-        x[1] += (double)ru * (double)ru;
-      }
+      const T ru = (T)((double)b.D[i] * (double)b.z[i] - alpha * (double)b.q[i]);
+      zn[i] = ru / b.D[i];
+      x[0] += (double)ru * (double)zn[i];
+      x[1] += (double)ru * (double)ru;
     }
     vstore<double, R>(a.v + g * R, b.v);
     vstore<T, R>(a.z + g * R, zn);
@@ -820,6 +814,102 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
     sc->alpha = alpha;
     sc->pq = pq;
   }
+}
+
+// Vector update of the scaled form (z holds D^-1/2 r): z -= alpha q,
+// r^T M^-1 r = z^T z and ||r||^2 = sum D z^2.  The potentials move every
+// second iteration: an even iteration leaves its alpha p pending, and the odd
+// one after it adds alpha_{it-1} p_{it-1} + alpha_it p_it, reading both
+// direction buffers (iteration j's direction is in p0 for odd j, p1 for
+// even j).  A pending step left when CG stops is added by k_flush_v.  ODD is
+// the parity the host expects; the kernel checks it against the iteration it
+// reads.  Rows are processed in pairs of groups as in k_update_vec.
+template <typename T, int R, bool ODD>
+struct ScaledGroup {
+  vec_t<T, R> z, q, D, p, pp;
+  vec_t<double, R> v;
+};
+
+template <typename T, int R, bool ODD>
+__global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  __shared__ double bc[4];
+  typedef vec_t<T, R> V;
+  const int64_t ng = a.nt / R;
+  int64_t gb, ge, gs;
+  slab_rows(ng, gb, ge, gs);
+  const UpdateStartLoads sl = cg_update_load(a);
+  const T *__restrict__ p_it = ODD ? a.p0 : a.p1;
+  const T *__restrict__ p_prev = ODD ? a.p1 : a.p0;
+  auto load = [&](int64_t g, ScaledGroup<T, R, ODD> &b) {
+    const int64_t u0 = g * R;
+    b.z = vload<T, R>(a.z + u0); b.q = vload<T, R>(a.q + u0); b.D = vload<T, R>(a.D + u0);
+    if constexpr (ODD) {
+      b.p = vload<T, R>(p_it + u0); b.pp = vload<T, R>(p_prev + u0); b.v = vload<double, R>(a.v + u0);
+    }
+  };
+  ScaledGroup<T, R, ODD> b0, b1;
+  if (gb < ge) load(gb, b0);
+  if (gb + gs < ge) load(gb + gs, b1);
+  Scalars *sc = a.sc;
+  int64_t it;
+  double alpha, pq;
+  if (!cg_update_finish(a, sl, lds, bc, it, alpha, pq)) return;
+  if (((it & 1) != 0) != ODD) {                          // the launch sequence is out of step
+    if (first_thread()) { sc->done = 1; sc->status = IRLS_ERR_DEVICE; }
+    return;
+  }
+  const double alpha_prev = sl.alpha_even;
+  double x[2] = {0.0, 0.0};
+  auto work = [&](int64_t g, ScaledGroup<T, R, ODD> &b) {
+    V zn;
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+      if constexpr (ODD) b.v[i] += alpha_prev * (double)b.pp[i] + alpha * (double)b.p[i];
+      zn[i] = (T)((double)b.z[i] - alpha * (double)b.q[i]);
+      x[0] += (double)zn[i] * (double)zn[i];
+      x[1] += (double)b.D[i] * (double)zn[i] * (double)zn[i];
+    }
+    if constexpr (ODD) vstore<double, R>(a.v + g * R, b.v);
+    vstore<T, R>(a.z + g * R, zn);
+  };
+  int64_t g = gb;
+  if (g + 3 * gs < ge) {
+    auto pair = [&]() {
+      work(g, b0);
+      load(g + 2 * gs, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      work(g + gs, b1);
+      load(g + 3 * gs, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      g += 2 * gs;
+    };
+    pair();
+    while (g + 3 * gs < ge) pair();
+  }
+  if (g < ge) {
+    work(g, b0);
+    if (g + 2 * gs < ge) load(g + 2 * gs, b0);
+    if (g + gs < ge) work(g + gs, b1);
+    if (g + 2 * gs < ge) work(g + 2 * gs, b0);
+  }
+  write_partials<2>(x, a.partials, kPUpd, lds);
+  if (first_thread()) {
+    sc->iter_b = it + 1;
+    sc->alpha = alpha;
+    sc->alpha_par[it & 1] = alpha;
+    sc->pq = pq;
+  }
+}
+
+// After CG in the scaled form: if the last completed update was an even
+// iteration, its alpha p is still pending; add it (its direction is in p1).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_flush_v(CGArgs<T> a) {
+  const int64_t done_updates = a.sc->iter_b;
+  if ((done_updates & 1) == 0) return;
+  const double alpha = a.sc->alpha_par[0];
+  FOR_ROWS(u, a.nt) a.v[u] += alpha * (double)a.p1[u];
 }
 
 // ----------------------------------------------------------------------------
@@ -1077,6 +1167,7 @@ hipError_t launch_scale_w(const CGArgs<T> &a, int grid, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_scale_v(const CGArgs<T> &a, int dir, int grid, hipStream_t st) {
+  if (dir < 0) hipLaunchKernelGGL((k_flush_v<T>), dim3(grid), dim3(kBlock), 0, st, a);
   hipLaunchKernelGGL((k_scale_v<T>), dim3(grid), dim3(kBlock), 0, st, a, dir);
   return hipGetLastError();
 }
@@ -1198,10 +1289,12 @@ template <typename T>
 hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
   if (a.bj_block > 0)
     hipLaunchKernelGGL((k_update_bj<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  else if (a.scaled && (a.it_hint & 1))
+    hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, true>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.scaled)
-    hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, false>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.nt % kVecRows<T> == 0)
-    hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>>), dim3(grid), dim3(kBlock), 0, st, a);
   else
     hipLaunchKernelGGL((k_update<T>), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();

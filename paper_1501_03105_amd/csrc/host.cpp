@@ -605,6 +605,10 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
       if (a.scaled) HIPCHK(h, launch_scale_v(a, -1, h->grid, h->stream), "scaling");
       pred = it;
       h->last_iters = it;
+      if (st == IRLS_ERR_DEVICE) {
+        h->err = "CG kernels out of step with the host's iteration count in round " + std::to_string(l);
+        return IRLS_ERR_DEVICE;
+      }
       if (st == IRLS_ERR_CG_BREAKDOWN) {
         h->err = "CG breakdown in round " + std::to_string(l);
         result = IRLS_ERR_CG_BREAKDOWN;
@@ -1139,17 +1143,18 @@ irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *
 irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps, double *avg_ms) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (!avg_ms) { h->err = "avg_ms must not be NULL"; return IRLS_ERR_NULL; }
-  if (which < 0 || which > 1 || reps < 1) { h->err = "which must be 0 or 1, reps >= 1"; return IRLS_ERR_OPTIONS; }
+  if (which < 0 || which > 2 || reps < 1) { h->err = "which must be 0, 1 or 2, reps >= 1"; return IRLS_ERR_OPTIONS; }
   if (h->batch || h->solver != 1) { h->err = "kernel timing needs the multi-workgroup solver"; return IRLS_ERR_OPTIONS; }
   if (!h->solved) { h->err = "call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
   try {
     // The launches run on the live system of the last round with a private
-    // scalar block (iteration 1, done = 0, no stopping); the potentials are
-    // saved first and restored afterwards.
+    // scalar block (iteration 1, or 2 for which = 2; done = 0, no stopping);
+    // the potentials are saved first and restored afterwards.
+    const int64_t it = which == 2 ? 2 : 1;
     Scalars s;
     std::memset(&s, 0, sizeof(s));
     s.rho[0] = s.rho[1] = 1.0;
-    s.iter_a = s.iter_b = 1;
+    s.iter_a = s.iter_b = it;
     s.maxit = std::numeric_limits<int64_t>::max();
     HIPCHK(h, hipMemcpy(h->sc_bench, &s, sizeof(s), hipMemcpyHostToDevice), "upload");
     if (!h->vsave) HIPCHK(h, h->dalloc(&h->vsave, h->g.nt), "alloc");
@@ -1161,12 +1166,12 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
       if (h->opt.precision == 1) {
         CGArgs<float> a = make_args<float>(h);
         a.sc = h->sc_bench;
-        a.it_hint = 1;
+        a.it_hint = it;
         return which == 0 ? launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream) : launch_update(a, h->grid, h->stream);
       }
       CGArgs<double> a = make_args<double>(h);
       a.sc = h->sc_bench;
-      a.it_hint = 1;
+      a.it_hint = it;
       return which == 0 ? launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream) : launch_update(a, h->grid, h->stream);
     };
     hipError_t e = one();

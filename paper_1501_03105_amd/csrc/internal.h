@@ -25,6 +25,7 @@ struct Scalars {
   double bb;         // ||b||^2
   double rr;         // ||r||^2 of the last stopping test
   double alpha, beta, pq;
+  double alpha_par[2]; // alpha by iteration parity (the scaled form's paired potential update)
   int64_t iter_a;    // index of the last SpMV started (written by the SpMV)
   int64_t iter_b;    // CG iterations completed (written by the update)
   int64_t maxit;
@@ -126,6 +127,8 @@ struct SweepBufs {
 template <typename T> hipError_t launch_assemble(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st);
 // scaled form: wh from w and D (after the assembly), and v <- D^(dir/2) v
+// (dir < 0, after CG: first adds the potential step an even iteration left
+// pending)
 template <typename T> hipError_t launch_scale_w(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_scale_v(const CGArgs<T> &a, int dir, int grid, hipStream_t st);
 // SpMV grid and kernel choice for a system: sets a.grid_spmv and a.march_planes
