@@ -109,8 +109,10 @@ __device__ __forceinline__ void rows_pass(const ResRows &R, F f, Fin fin) {
 // row groups (light) or chunks (heavy) per wavefront in flight at once: their
 // index and value loads are issued together (out-of-range lanes read entry 0
 // and add nothing), so one workgroup keeps enough loads in flight for large
-// graphs.
-constexpr int kSpmvRows = 4;
+// graphs.  Two groups per pass measured faster than four on the 512-graph
+// R-MAT batch: four need more registers than a 1024-thread workgroup allows
+// and spill.
+constexpr int kSpmvRows = 2;
 
 __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, const double *p, const double *D,
                                           double *q, double &x1) {
@@ -121,19 +123,28 @@ __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, con
     const int L = bin_lanes(b), rpw = 64 / L, sub = lane / L, lid = lane % L;
     const int32_t hi = R.bin[b + 1];
     const int32_t step = kResWaves * rpw;
-#pragma unroll 1
-    for (int32_t j0 = R.bin[b] + wid * rpw; j0 < hi; j0 += U * step) {
-      int64_t i[U];
-      int32_t e0[U], e1[U];
+    // The next row groups' (row, entry range) triples are loaded one pass
+    // ahead, and each row's own D and p with its entries, so a pass waits for
+    // two dependent round trips (entries, then the gathered p) instead of four.
+    int64_t i[U], in[U];
+    int32_t e0[U], e1[U], e0n[U], e1n[U];
+    auto meta = [&](int32_t j0, int64_t *ii, int32_t *b0, int32_t *b1) {
 #pragma unroll
       for (int u = 0; u < U; u++) {
         const int32_t j = j0 + u * step + sub;
         const bool ok = j < hi;
-        i[u] = ok ? R.brow[j] : 0;
-        e0[u] = ok ? R.bbeg[j] : 0;
-        e1[u] = ok ? R.bend[j] : 0;
+        ii[u] = ok ? R.brow[j] : 0;
+        b0[u] = ok ? R.bbeg[j] : 0;
+        b1[u] = ok ? R.bend[j] : 0;
       }
-      double acc[U];
+    };
+    int32_t j0 = R.bin[b] + wid * rpw;
+    if (j0 < hi) meta(j0, in, e0n, e1n);
+#pragma unroll 1
+    for (; j0 < hi; j0 += U * step) {
+#pragma unroll
+      for (int u = 0; u < U; u++) { i[u] = in[u]; e0[u] = e0n[u]; e1[u] = e1n[u]; }
+      double acc[U], dii[U], pii[U];
 #pragma unroll
       for (int u = 0; u < U; u++) acc[u] = 0.0;
 #pragma unroll 1
@@ -149,19 +160,28 @@ __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, con
           c[u] = R.col[ee];
           wv[u] = w[ee];
         }
+        if (t == 0) {
+          if (j0 + U * step < hi) meta(j0 + U * step, in, e0n, e1n);
+#pragma unroll
+          for (int u = 0; u < U; u++) { dii[u] = D[i[u]]; pii[u] = p[i[u]]; }
+        }
 #pragma unroll
         for (int u = 0; u < U; u++) pv[u] = p[c[u]];
 #pragma unroll
         for (int u = 0; u < U; u++)
           if (ok[u]) acc[u] += wv[u] * pv[u];
       }
+      if (R.nnz == 0) {
+#pragma unroll
+        for (int u = 0; u < U; u++) { dii[u] = D[i[u]]; pii[u] = p[i[u]]; }
+      }
 #pragma unroll
       for (int u = 0; u < U; u++) {
         for (int o = L >> 1; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, 64);
         if (j0 + u * step + sub < hi && lid == 0) {
-          const double qi = D[i[u]] * p[i[u]] - acc[u];
+          const double qi = dii[u] * pii[u] - acc[u];
           q[i[u]] = qi;
-          x1 += p[i[u]] * qi;
+          x1 += pii[u] * qi;
         }
       }
     }
