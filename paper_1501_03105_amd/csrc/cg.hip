@@ -45,45 +45,64 @@ __device__ __forceinline__ double edge_g(const CGArgs<T> &a, double c, double d)
 // ----------------------------------------------------------------------------
 // reweight + assemble: conductances, D, b (= conductance to s), conductance to t
 // ----------------------------------------------------------------------------
-template <typename T, bool DIA>
+// Row u's terminal edges and totals, given the sum of its interior conductances.
+template <typename T>
+__device__ __forceinline__ void assemble_row_tail(const CGArgs<T> &a, int64_t u, double vu, double diag) {
+  const double cs = a.cs[u], ct = a.ct[u];
+  const double gs = cs > 0.0 ? edge_g(a, cs, 1.0 - vu) : 0.0;
+  const double gt = ct > 0.0 ? edge_g(a, ct, vu) : 0.0;
+  diag += gs + gt;
+  a.D[u] = (T)diag;
+  if (a.D64) a.D64[u] = diag;
+  a.b[u] = gs;
+  a.gt[u] = gt;
+}
+
+// diagonal format: a thread per row
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_assemble(CGArgs<T> a) {
   FOR_ROWS(u, a.nt) {
     const double vu = a.v[u];
     double diag = 0.0;
-    if constexpr (DIA) {
-      for (int k = 0; k < a.K; k++) {
-        int64_t j = u + a.off[k];
-        double g = 0.0;
-        if (j < a.nt) {
-          double c = a.dcap[k * a.nt + u];
-          if (c > 0.0) g = edge_g(a, c, vu - a.v[j]);
-        }
-        a.w[k * a.nt + u] = (T)g;
-        if (a.w64) a.w64[k * a.nt + u] = g;
-        diag += g;
-        j = u - a.off[k];
-        if (j >= 0) {
-          double c = a.dcap[k * a.nt + j];
-          if (c > 0.0) diag += edge_g(a, c, a.v[j] - vu);   // same value row j stores
-        }
+    for (int k = 0; k < a.K; k++) {
+      int64_t j = u + a.off[k];
+      double g = 0.0;
+      if (j < a.nt) {
+        double c = a.dcap[k * a.nt + u];
+        if (c > 0.0) g = edge_g(a, c, vu - a.v[j]);
       }
-    } else {
-      for (int32_t e = a.rowptr[u]; e < a.rowptr[u + 1]; e++) {
-        double g = edge_g(a, a.ccap[e], vu - a.v[a.col[e]]);
+      a.w[k * a.nt + u] = (T)g;
+      if (a.w64) a.w64[k * a.nt + u] = g;
+      diag += g;
+      j = u - a.off[k];
+      if (j >= 0) {
+        double c = a.dcap[k * a.nt + j];
+        if (c > 0.0) diag += edge_g(a, c, a.v[j] - vu);   // same value row j stores
+      }
+    }
+    assemble_row_tail(a, u, vu, diag);
+  }
+}
+
+// CSR: L lanes per row (the SpMV's), so rows with many entries (the hubs of
+// power-law graphs) are not left to one thread
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_assemble_csr(CGArgs<T> a) {
+  for_row_groups<L>(a.nt, [&](int64_t u, int lid) {
+    double diag = 0.0, vu = 0.0;
+    if (u >= 0) {
+      vu = a.v[u];
+      const int32_t e1 = a.rowptr[u + 1];
+      for (int32_t e = a.rowptr[u] + lid; e < e1; e += L) {
+        const double g = edge_g(a, a.ccap[e], vu - a.v[a.col[e]]);
         a.w[e] = (T)g;
         if (a.w64) a.w64[e] = g;
         diag += g;
       }
     }
-    double cs = a.cs[u], ct = a.ct[u];
-    double gs = cs > 0.0 ? edge_g(a, cs, 1.0 - vu) : 0.0;
-    double gt = ct > 0.0 ? edge_g(a, ct, vu) : 0.0;
-    diag += gs + gt;
-    a.D[u] = (T)diag;
-    if (a.D64) a.D64[u] = diag;
-    a.b[u] = gs;
-    a.gt[u] = gt;
-  }
+    diag = group_sum<L>(diag);
+    if (u >= 0 && lid == 0) assemble_row_tail(a, u, vu, diag);
+  });
 }
 
 // (L~ x)_u in FP64 with the FP64 copy of this round's conductances
@@ -111,41 +130,72 @@ __device__ __forceinline__ bool first_thread() { return threadIdx.x == 0 && bloc
 // CG start: r = b - L~ v0 (warm) or r = b, v = 0 (cold); partial sums of
 // r^T z, ||b||^2, ||r||^2 for the first direction kernel
 // ----------------------------------------------------------------------------
-template <typename T, bool DIA>
-__global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
-  __shared__ double lds[4 * (kBlock / 64)];
-  double x[3] = {0.0, 0.0, 0.0};   // rho, bb, rr
-  FOR_ROWS(u, a.nt) {
-    double bu = a.b[u];
-    double ru;
-    if (a.warm) {
-      ru = bu - row_apply64<DIA>(a, u, a.v);
-    } else {
-      a.v[u] = 0.0;
-      ru = bu;
-    }
-    T rt = (T)ru;
-    if (a.bj_block > 0) {                      // block-Jacobi: z and r^T z come from k_bj_apply
-      a.rbuf[u] = ru;
-    } else if (a.scaled) {                     // scaled form: z = D^-1/2 r, r^T M^-1 r = z^T z
-      const T zt = (T)(ru / sqrt((double)a.D[u]));
-      a.z[u] = zt;
-      x[0] += (double)zt * (double)zt;
-    } else {
-      T zt = rt / a.D[u];
-      a.z[u] = zt;                             // z = M^-1 r is what CG keeps
-      x[0] += (double)rt * (double)zt;
-    }
-    x[1] += bu * bu;
-    x[2] += (double)rt * (double)rt;
+template <typename T>
+__device__ __forceinline__ void cginit_row(const CGArgs<T> &a, int64_t u, double bu, double ru, double (&x)[3]) {
+  const T rt = (T)ru;
+  if (a.bj_block > 0) {                        // block-Jacobi: z and r^T z come from k_bj_apply
+    a.rbuf[u] = ru;
+  } else if (a.scaled) {                       // scaled form: z = D^-1/2 r, r^T M^-1 r = z^T z
+    const T zt = (T)(ru / sqrt((double)a.D[u]));
+    a.z[u] = zt;
+    x[0] += (double)zt * (double)zt;
+  } else {
+    const T zt = rt / a.D[u];
+    a.z[u] = zt;                               // z = M^-1 r is what CG keeps
+    x[0] += (double)rt * (double)zt;
   }
-  write_partials<3>(x, a.partials, kPInit, lds);
+  x[1] += bu * bu;
+  x[2] += (double)rt * (double)rt;
+}
+
+template <typename T>
+__device__ __forceinline__ void cginit_publish(const CGArgs<T> &a) {
   if (first_thread()) {
     a.sc->iter_b = 0;
     a.sc->iter_a = 0;
     a.sc->done = 0;
     a.sc->status = IRLS_OK;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cginit(CGArgs<T> a) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  double x[3] = {0.0, 0.0, 0.0};   // rho, bb, rr
+  FOR_ROWS(u, a.nt) {
+    const double bu = a.b[u];
+    double ru = bu;
+    if (a.warm) ru = bu - row_apply64<true>(a, u, a.v);
+    else a.v[u] = 0.0;
+    cginit_row(a, u, bu, ru, x);
+  }
+  write_partials<3>(x, a.partials, kPInit, lds);
+  cginit_publish(a);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_cginit_csr(CGArgs<T> a) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  double x[3] = {0.0, 0.0, 0.0};
+  const double *w = a.w64 ? a.w64 : (const double *)a.w;
+  const double *D = a.D64 ? a.D64 : (const double *)a.D;
+  for_row_groups<L>(a.nt, [&](int64_t u, int lid) {
+    double off = 0.0;                          // sum of w_uj v_j over row u's entries
+    if (u >= 0 && a.warm) {
+      const int32_t e1 = a.rowptr[u + 1];
+      for (int32_t e = a.rowptr[u] + lid; e < e1; e += L) off += w[e] * a.v[a.col[e]];
+    }
+    off = group_sum<L>(off);
+    if (u >= 0 && lid == 0) {
+      const double bu = a.b[u];
+      double ru = bu;
+      if (a.warm) ru = bu - (D[u] * a.v[u] - off);
+      else a.v[u] = 0.0;
+      cginit_row(a, u, bu, ru, x);
+    }
+  });
+  write_partials<3>(x, a.partials, kPInit, lds);
+  cginit_publish(a);
 }
 
 // Scaled form (Jacobi as symmetric scaling, diagonal layout): the scaled
@@ -1058,41 +1108,70 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
 // flow value x^T L x and the flows at s and t (Proposition 3), the range of v
 // (Proposition 2) and the true residual; k_stats_final adds the partials.
 // ----------------------------------------------------------------------------
-template <typename T, bool DIA>
+// Diagnostics of one row: its interior edges' terms are added by the caller
+// (each edge once, from its lower endpoint); this adds the terminal edges'
+// terms, the squared true residual b_u - (L~ v)_u and the range of v.
+// slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v)
+template <typename T>
+__device__ __forceinline__ void stats_edge(const CGArgs<T> &a, double c, double g, double d, double (&x)[8]) {
+  x[0] += a.form == 0 ? c * sqrt(d * d + a.eps_next) : sqrt((c * d) * (c * d) + a.eps_next);
+  x[1] += c * fabs(d);
+  x[2] += g * d * d;
+}
+
+template <typename T>
+__device__ __forceinline__ void stats_row_tail(const CGArgs<T> &a, int64_t u, double vu, double lv, double (&x)[8]) {
+  const double cs = a.cs[u], ct = a.ct[u];
+  if (cs > 0.0) {
+    stats_edge(a, cs, a.b[u], 1.0 - vu, x);
+    x[3] += a.b[u] * (1.0 - vu);
+  }
+  if (ct > 0.0) {
+    stats_edge(a, ct, a.gt[u], vu, x);
+    x[4] += a.gt[u] * vu;
+  }
+  const double res = a.b[u] - lv;
+  x[5] += res * res;
+  x[6] = fmax(x[6], -vu);
+  x[7] = fmax(x[7], vu);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_stats(CGArgs<T> a) {
   __shared__ double lds[8 * (kBlock / 64)];
   const double *w = a.w64 ? a.w64 : (const double *)a.w;
-  // slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v)
   double x[8] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY};
   FOR_ROWS(u, a.nt) {
     const double vu = a.v[u];
-    for_each_nb<DIA>(a, u, [&](int64_t j, double c, int64_t wi) {
-      if (j <= u) return;                       // each interior edge once
-      double d = vu - a.v[j];
-      x[0] += a.form == 0 ? c * sqrt(d * d + a.eps_next) : sqrt((c * d) * (c * d) + a.eps_next);
-      x[1] += c * fabs(d);
-      x[2] += w[wi] * d * d;
+    for_each_nb<true>(a, u, [&](int64_t j, double c, int64_t wi) {
+      if (j > u) stats_edge(a, c, w[wi], vu - a.v[j], x);    // each interior edge once
     });
-    double cs = a.cs[u], ct = a.ct[u];
-    if (cs > 0.0) {
-      double d = 1.0 - vu;
-      x[0] += a.form == 0 ? cs * sqrt(d * d + a.eps_next) : sqrt((cs * d) * (cs * d) + a.eps_next);
-      x[1] += cs * fabs(d);
-      x[2] += a.b[u] * d * d;
-      x[3] += a.b[u] * d;
-    }
-    if (ct > 0.0) {
-      double d = vu;
-      x[0] += a.form == 0 ? ct * sqrt(d * d + a.eps_next) : sqrt((ct * d) * (ct * d) + a.eps_next);
-      x[1] += ct * fabs(d);
-      x[2] += a.gt[u] * d * d;
-      x[4] += a.gt[u] * d;
-    }
-    double res = a.b[u] - row_apply64<DIA>(a, u, a.v);
-    x[5] += res * res;
-    x[6] = fmax(x[6], -vu);
-    x[7] = fmax(x[7], vu);
+    stats_row_tail(a, u, vu, row_apply64<true>(a, u, a.v), x);
   }
+  write_partials<8, 0xC0u>(x, a.partials, kPStats, lds);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(kBlock) void k_stats_csr(CGArgs<T> a) {
+  __shared__ double lds[8 * (kBlock / 64)];
+  const double *w = a.w64 ? a.w64 : (const double *)a.w;
+  const double *D = a.D64 ? a.D64 : (const double *)a.D;
+  double x[8] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY};
+  for_row_groups<L>(a.nt, [&](int64_t u, int lid) {
+    double off = 0.0, vu = 0.0;                // off: sum of w_uj v_j over row u's entries
+    if (u >= 0) {
+      vu = a.v[u];
+      const int32_t e1 = a.rowptr[u + 1];
+      for (int32_t e = a.rowptr[u] + lid; e < e1; e += L) {
+        const int64_t j = a.col[e];
+        const double vj = a.v[j];
+        off += w[e] * vj;
+        if (j > u) stats_edge(a, a.ccap[e], w[e], vu - vj, x);
+      }
+    }
+    off = group_sum<L>(off);
+    if (u >= 0 && lid == 0) stats_row_tail(a, u, vu, D[u] * vu - off, x);
+  });
   write_partials<8, 0xC0u>(x, a.partials, kPStats, lds);
 }
 
@@ -1145,17 +1224,29 @@ __global__ void k_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
 // ----------------------------------------------------------------------------
 // launchers
 // ----------------------------------------------------------------------------
+// launch KERNEL<T, lanes> for a CSR kernel with `lanes` lanes per row
+#define CSR_LANES(lanes, KERNEL, grid, st, a)                                                 \
+  switch (lanes) {                                                                            \
+    case 1: hipLaunchKernelGGL((KERNEL<T, 1>), dim3(grid), dim3(kBlock), 0, st, a); break;    \
+    case 2: hipLaunchKernelGGL((KERNEL<T, 2>), dim3(grid), dim3(kBlock), 0, st, a); break;    \
+    case 4: hipLaunchKernelGGL((KERNEL<T, 4>), dim3(grid), dim3(kBlock), 0, st, a); break;    \
+    case 8: hipLaunchKernelGGL((KERNEL<T, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;    \
+    case 16: hipLaunchKernelGGL((KERNEL<T, 16>), dim3(grid), dim3(kBlock), 0, st, a); break;  \
+    case 32: hipLaunchKernelGGL((KERNEL<T, 32>), dim3(grid), dim3(kBlock), 0, st, a); break;  \
+    default: hipLaunchKernelGGL((KERNEL<T, 64>), dim3(grid), dim3(kBlock), 0, st, a); break;  \
+  }
+
 template <typename T>
 hipError_t launch_assemble(const CGArgs<T> &a, int grid, hipStream_t st) {
-  if (a.K > 0) hipLaunchKernelGGL((k_assemble<T, true>), dim3(grid), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_assemble<T, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  if (a.K > 0) hipLaunchKernelGGL((k_assemble<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  else CSR_LANES(a.csr_lanes, k_assemble_csr, grid, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cginit(const CGArgs<T> &a, int grid, hipStream_t st) {
-  if (a.K > 0) hipLaunchKernelGGL((k_cginit<T, true>), dim3(grid), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_cginit<T, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  if (a.K > 0) hipLaunchKernelGGL((k_cginit<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  else CSR_LANES(a.csr_lanes, k_cginit_csr, grid, st, a);
   return hipGetLastError();
 }
 
@@ -1309,8 +1400,8 @@ hipError_t launch_replace_residual(const CGArgs<T> &a, int grid, hipStream_t st)
 
 template <typename T>
 hipError_t launch_stats(const CGArgs<T> &a, int grid, hipStream_t st) {
-  if (a.K > 0) hipLaunchKernelGGL((k_stats<T, true>), dim3(grid), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_stats<T, false>), dim3(grid), dim3(kBlock), 0, st, a);
+  if (a.K > 0) hipLaunchKernelGGL((k_stats<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  else CSR_LANES(a.csr_lanes, k_stats_csr, grid, st, a);
   hipLaunchKernelGGL((k_stats_final<T>), dim3(1), dim3(kBlock), 0, st, a, grid);
   return hipGetLastError();
 }

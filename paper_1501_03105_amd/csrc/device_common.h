@@ -186,6 +186,42 @@ __device__ __forceinline__ void slab_rows(int64_t n, int64_t &begin, int64_t &en
   step = nb * blockDim.x;
 }
 
+// CSR rows with L lanes each (L a power of two <= 64): every wavefront takes
+// 64 / L consecutive rows at a time, in XCD slabs of row groups as slab_rows
+// forms them for single rows.  f(u, lid) runs on every lane, with u = -1 on
+// lanes past the last row, so that shuffles inside f see the whole
+// wavefront; lid is the lane's index within its row's group.
+template <int L, typename F>
+__device__ __forceinline__ void for_row_groups(int64_t n, F f) {
+  constexpr int RPW = 64 / L;
+  const int lane = threadIdx.x & 63, sub = lane / L, lid = lane % L;
+  const int64_t ng = (n + RPW - 1) / RPW, wpb = blockDim.x >> 6, w = threadIdx.x >> 6;
+  int64_t gb, ge, gs;
+  if (gridDim.x < kXcds || gridDim.x % kXcds != 0) {
+    gb = (int64_t)blockIdx.x * wpb + w;
+    ge = ng;
+    gs = (int64_t)gridDim.x * wpb;
+  } else {
+    const int64_t x = blockIdx.x % kXcds, lb = blockIdx.x / kXcds, nb = gridDim.x / kXcds;
+    const int64_t slab = (ng + kXcds - 1) / kXcds, lo = x * slab;
+    ge = lo + slab < ng ? lo + slab : ng;
+    gb = lo + lb * wpb + w;
+    gs = nb * wpb;
+  }
+  for (int64_t g = gb; g < ge; g += gs) {            // the same trip count on every lane
+    const int64_t u = g * RPW + sub;
+    f(u < n ? u : (int64_t)-1, lid);
+  }
+}
+
+// Sum over the L lanes of a row group (L a power of two).
+template <int L>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
 #define FOR_ROWS(u, n)                                   \
   int64_t u##_b_, u##_e_, u##_s_;                        \
   slab_rows((n), u##_b_, u##_e_, u##_s_);                \

@@ -471,6 +471,7 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.rtol = h->opt.cg_rtol;
   a.weights_fp64 = 1;
   a.grid_main = h->grid;
+  a.csr_lanes = h->rpw > 0 ? 64 / h->rpw : 64;
   spmv_layout(a, h->grid);
   a.bj_block = h->bj_block;
   a.rbuf = h->bj_r;

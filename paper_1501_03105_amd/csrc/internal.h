@@ -84,6 +84,7 @@ struct CGArgs {
   int32_t bj_block;
   int32_t grid_main;              // workgroups of the init / update / replacement kernels
   int32_t grid_spmv;              // workgroups of the SpMV kernel (its partial-sum count)
+  int32_t csr_lanes;              // CSR per-round kernels: lanes per row (the SpMV's)
   int32_t march_planes;           // diagonal SpMV marching along off[K-1]: planes per
                                   // workgroup (0: the row-slab kernels)
   int64_t it_hint;                // CG iteration the host expects this launch to run: picks
