@@ -84,7 +84,7 @@ typedef struct {
   int32_t block_size;         /* precond 1: rows per block, even, 2..128 and at most
                                  off[1]; 0 = min(off[1], 128) rounded down to even */
   int32_t unscaled_cg;        /* 0 (default): where the marching SpMV runs (3-D grids) with
-                                 Jacobi in FP64, CG runs on the symmetrically scaled system
+                                 point Jacobi, CG runs on the symmetrically scaled system
                                  D^-1/2 L~ D^-1/2 -- in exact arithmetic the same iterates as
                                  Jacobi PCG (Section 3.1), but the SpMV reads no diagonal;
                                  1: always the z = D^-1 r form */

@@ -136,7 +136,7 @@ __device__ __forceinline__ void cginit_row(const CGArgs<T> &a, int64_t u, double
   if (a.bj_block > 0) {                        // block-Jacobi: z and r^T z come from k_bj_apply
     a.rbuf[u] = ru;
   } else if (a.scaled) {                       // scaled form: z = D^-1/2 r, r^T M^-1 r = z^T z
-    const T zt = (T)(ru / sqrt((double)a.D[u]));
+    const T zt = (T)(ru / sqrt(a.D64 ? a.D64[u] : (double)a.D[u]));
     a.z[u] = zt;
     x[0] += (double)zt * (double)zt;
   } else {
@@ -202,14 +202,21 @@ __global__ __launch_bounds__(kBlock) void k_cginit_csr(CGArgs<T> a) {
 // conductances w_uj / sqrt(D_u D_j), 0 where the edge does not exist, and the
 // change of variables of the potentials, v <- D^1/2 v before CG and
 // v <- D^-1/2 v after it.
+// In the FP32 form the scaling uses the FP64 copies of w and D; the scaled
+// conductances are then rounded to FP32 once.
+template <typename T>
+__device__ __forceinline__ double diag64(const CGArgs<T> &a, int64_t u) {
+  return a.D64 ? a.D64[u] : (double)a.D[u];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale_w(CGArgs<T> a) {
   FOR_ROWS(u, a.nt) {
-    const double du = (double)a.D[u];
+    const double du = diag64(a, u);
     for (int k = 0; k < a.K; k++) {
       const int64_t j = u + a.off[k];
-      const double wv = j < a.nt ? (double)a.w[k * a.nt + u] : 0.0;
-      a.wh[k * a.nt + u] = (T)(wv != 0.0 ? wv / sqrt(du * (double)a.D[j]) : 0.0);
+      const double wv = j < a.nt ? (a.w64 ? a.w64[k * a.nt + u] : (double)a.w[k * a.nt + u]) : 0.0;
+      a.wh[k * a.nt + u] = (T)(wv != 0.0 ? wv / sqrt(du * diag64(a, j)) : 0.0);
     }
   }
 }
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_w(CGArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale_v(CGArgs<T> a, int dir) {
   FOR_ROWS(u, a.nt) {
-    const double sd = sqrt((double)a.D[u]);
+    const double sd = sqrt(diag64(a, u));
     a.v[u] = dir > 0 ? a.v[u] * sd : a.v[u] / sd;
   }
 }
@@ -1092,13 +1099,34 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
   const bool conv_rec = sqrt(t[1]) <= a.rtol * sqrt(bb);
   if (!(conv_rec || i % refine == 0)) return;
   double x[2] = {0.0, 0.0};
-  FOR_ROWS(u, a.nt) {
-    double ru64 = a.b[u] - row_apply64<DIA>(a, u, a.v);
-    T ru = (T)ru64;
-    T zu = ru / a.D[u];
-    a.z[u] = zu;
-    x[0] += (double)ru * (double)zu;
-    x[1] += (double)ru * (double)ru;
+  if (a.scaled) {
+    // v holds D^1/2 v, and when the last update was an even iteration its
+    // step alpha p (in p1) is still pending: both enter the true potentials.
+    const bool pending = (i & 1) != 0;
+    const double ap = pending ? sc->alpha_par[0] : 0.0;
+    auto vtrue = [&](int64_t j) {
+      const double vh = a.v[j] + (pending ? ap * (double)a.p1[j] : 0.0);
+      return vh / sqrt(diag64(a, j));
+    };
+    const double *w = a.w64 ? a.w64 : (const double *)a.w;
+    FOR_ROWS(u, a.nt) {
+      double acc = diag64(a, u) * vtrue(u);
+      for_each_nb<DIA>(a, u, [&](int64_t j, double, int64_t wi) { acc -= w[wi] * vtrue(j); });
+      const double ru64 = a.b[u] - acc;
+      const T zu = (T)(ru64 / sqrt(diag64(a, u)));
+      a.z[u] = zu;
+      x[0] += (double)zu * (double)zu;
+      x[1] += ru64 * ru64;
+    }
+  } else {
+    FOR_ROWS(u, a.nt) {
+      double ru64 = a.b[u] - row_apply64<DIA>(a, u, a.v);
+      T ru = (T)ru64;
+      T zu = ru / a.D[u];
+      a.z[u] = zu;
+      x[0] += (double)ru * (double)zu;
+      x[1] += (double)ru * (double)ru;
+    }
   }
   write_partials<2>(x, a.partials, kPRep, lds);
 }

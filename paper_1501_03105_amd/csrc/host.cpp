@@ -907,9 +907,9 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
     }
     h->grid = grid_for(hg.nt);
     // Jacobi as symmetric scaling wherever the marching SpMV runs with point
-    // Jacobi in FP64: that SpMV then reads no diagonal
-    if (use_dia && o.precision == 0 && o.precond == 0 && !o.unscaled_cg)
-      h->scaled = make_args<double>(h).march_planes > 0;
+    // Jacobi: that SpMV then reads no diagonal
+    if (use_dia && o.precond == 0 && !o.unscaled_cg)
+      h->scaled = (o.precision == 1 ? make_args<float>(h).march_planes : make_args<double>(h).march_planes) > 0;
     {
       double avg = hg.nt > 0 ? (double)hg.col.size() / (double)hg.nt : 1.0;
       int L = 1;

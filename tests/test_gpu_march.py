@@ -1,8 +1,8 @@
 """The diagonal SpMV that marches along the plane offset, against the CPU
 oracle.  Layouts chosen to hit its edge cases: a 2-D grid whose rows (the
 planes of two offsets) fill one and a fraction of a tile, and a 3-D box whose
-last plane is partial, in FP64 (on the symmetrically scaled system, the
-default, and in the z = D^-1 r form) and in the FP32 form."""
+last plane is partial, in FP64 and in the FP32 form, each on the
+symmetrically scaled system (the default) and in the z = D^-1 r form."""
 import numpy as np
 import pytest
 
@@ -36,7 +36,8 @@ def cases():
 
 FORMS = {"fp64": (dict(precision=0), 4),                       # scaled system (default)
          "fp64-unscaled": (dict(precision=0, unscaled_cg=1), 3),  # z = D^-1 r form
-         "fp32": (dict(precision=1), 3)}
+         "fp32": (dict(precision=1), 4),
+         "fp32-unscaled": (dict(precision=1, unscaled_cg=1), 3)}
 
 
 @pytest.mark.parametrize("case", range(3))
