@@ -77,3 +77,32 @@ def test_small_planes_use_the_vector_kernel(P):
         assert mc.spmv_kernel()[0] == "k_spmv_dia_vec"
     with P.MinCut.from_graph(gen.grid2d(64, 64, seed=0), solver=1, format=1) as mc:
         assert mc.spmv_kernel()[0] == "k_spmv_csr"
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 3, 4])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_scaled_form_at_fixed_iteration_counts(P, oracle_mod, maxit, precision):
+    """CG stopped after a fixed number of iterations in every round: the
+    scaled form moves the potentials every second iteration, so an odd count
+    leaves a step pending that must be added after CG (and, in the FP32 form,
+    seen by the residual replacement).  The potentials after 1..4 iterations
+    per round match the oracle's Jacobi PCG run with the same cap."""
+    name, g = cases()[1]
+    say(f"scaled form, cg_maxit {maxit}, precision {precision}: {name}")
+    kw = dict(rounds=3, cg_rtol=1e-12, cg_maxit=maxit)
+    xo, so, rco = oracle_mod.irls(g, allow_maxit=True, **kw)
+    extra = dict(refine_every=1) if precision == 1 else {}   # a replacement after every update
+    with P.MinCut.from_graph(g, solver=1, precision=precision, **extra, **kw) as mc:
+        assert mc.spmv_variant()[0] == 4
+        rc, st = mc.solve(allow_maxit=True)
+        x = mc.potentials()
+        if precision == 0:
+            t_odd, t_even = mc.time_kernel(1, 3), mc.time_kernel(2, 3)
+            assert t_odd > 0 and t_even > 0
+            with pytest.raises(P.IrlsError):
+                mc.time_kernel(3, 3)
+    assert rc == P.WARN_CG_MAXIT and rco == 100
+    assert [r["cg_iters"] for r in st] == [r["cg_iters"] for r in so] == [maxit] * 4
+    err = max_pot_err(x, xo)
+    say(f"  potential error {err:.2e}")
+    assert err <= (1e-10 if precision == 0 else 1e-5)
