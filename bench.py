@@ -76,10 +76,22 @@ def spmv_bytes(info, precision, variant):
     return nnz * (ts + 4) + (nt + 1) * 4 + nt * 3 * ts
 
 
+def code_sha(path):
+    """SHA-256 prefix of a source file's code: // comments, trailing blanks and
+    blank lines removed, so that editing a comment keeps a profile valid."""
+    import hashlib
+    import re
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        line = re.sub(r"//.*", "", line).rstrip()
+        if line:
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def profiled_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 summary, if the kernel
-    source is still the one that was profiled (else None)."""
-    import hashlib
+    code is still the one that was profiled (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -88,9 +100,8 @@ def profiled_traffic(kernel, workload):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1501_03105_amd", "csrc", "cg.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if fields.get("source_sha256_prefix") != sha or "traffic_bytes_per_launch" not in fields:
+    sha = code_sha(os.path.join(ROOT, "paper_1501_03105_amd", "csrc", "cg.hip"))
+    if fields.get("code_sha256_prefix") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
 

@@ -8,6 +8,9 @@
 //     indices are stored and every access is unit-stride.
 //   * CSR: any graph; rows-per-wavefront chosen per graph.
 // Vectors are FP64 (precision 0) or FP32 with FP64 potentials (precision 1).
+// Where the marching SpMV runs, Jacobi PCG is run as CG on the symmetrically
+// scaled system D^-1/2 L~ D^-1/2 (the same iterates in exact arithmetic), so
+// the SpMV reads no diagonal and the potentials move every second iteration.
 #include "device_common.h"
 
 namespace irls {
@@ -593,8 +596,8 @@ __device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int
 // thread keeps the direction values of planes k-1 and k and the conductance
 // of its edge to plane k-1 in registers, so the +-P neighbours, which lie a
 // whole plane away in memory, are never reloaded.  Offsets below P are read
-// as in k_spmv_dia_vec.  All loads of the first step are issued before the
-// start-of-iteration reduction, so they are in flight while it runs.
+// as in k_spmv_dia_vec.  All loads of the first two steps are issued before
+// the start-of-iteration reduction, so they are in flight while it runs.
 // Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of chunks,
 // so the planes at chunk seams are shared in its L2.  The summation order per
 // row is that of k_spmv_dia_vec.
