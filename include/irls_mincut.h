@@ -154,6 +154,41 @@ irls_status irls_mincut_solve_range(irls_mincut_t h, int32_t start, const double
 irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
                             int64_t *k_star);
 
+/* Two-level rounding of the current potentials (Section 3.4, the two-level
+ * rounding procedure, and its proposition):
+ *   1. K-means with two centres on all n potentials (x_s = 1, x_t = 0
+ *      included), started at 0.1 and 0.9: a value joins the upper cluster
+ *      when it lies strictly above the midpoint of the centres, a centre is
+ *      its cluster's mean (kept if the cluster is empty), and the iteration
+ *      stops when an assignment repeats (at most 100 updates);
+ *   2. gamma0 = c0 + 0.05, gamma1 = c1 - 0.05; S0 = {x <= gamma0} is
+ *      coalesced with t, S1 = {x >= gamma1} with s, Sc is the rest;
+ *   3. the coarse graph on {s_c, t_c} and Sc: edges inside Sc, {s_c, u} with
+ *      u's summed capacity to S1, {t_c, u} to S0, {s_c, t_c} between S1 and
+ *      S0, all as exact fixed-point sums (the sweep's scale);
+ *   4. an exact minimum s_c-t_c cut of the coarse graph (on the host; its
+ *      source side is the largest one: the nodes that cannot reach t_c in
+ *      the residual graph of a maximum flow), lifted to S = S1 + its Sc part.
+ * If some minimum cut of G keeps S1 on the source side and S0 on the sink
+ * side, the result is a minimum cut of G.
+ *   in_source_side  NULL or n bytes (host): 1 for nodes in S (s included)
+ *   cut_value       NULL or 1 double (host): the exact cut value rounded once
+ *   info            NULL or the centres, thresholds and coarse graph size
+ * Errors: IRLS_ERR_NOT_SOLVED before a solve; IRLS_ERR_OPTIONS for a batch
+ * handle; IRLS_ERR_RANGE if the potentials leave s or t out of S1 / S0
+ * (potentials far outside [0, 1]). */
+typedef struct {
+  double  c0, c1;             /* K-means centres */
+  double  gamma0, gamma1;     /* split thresholds */
+  int32_t kmeans_updates;     /* centre updates before an assignment repeated */
+  int64_t n_s0, n_s1, n_sc;   /* class sizes over all n nodes (t in S0, s in S1) */
+  int64_t coarse_edges;       /* edges of the coarse graph (parallel edges merged) */
+  double  coarse_value;       /* minimum cut value of the coarse graph (= cut_value) */
+} irls_two_level_info;
+
+irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
+                                      irls_two_level_info *info);
+
 /* Copy the current potentials (host; x_s = 1, x_t = 0): n doubles, or for a
  * batch handle sum(n_g) doubles laid out like node_off. */
 irls_status irls_mincut_potentials(irls_mincut_t h, double *x);

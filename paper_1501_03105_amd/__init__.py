@@ -39,6 +39,12 @@ class RoundStats(C.Structure):
 STAT_FIELDS = [f for f, _ in RoundStats._fields_]
 
 
+class TwoLevelInfo(C.Structure):
+    _fields_ = [("c0", C.c_double), ("c1", C.c_double), ("gamma0", C.c_double), ("gamma1", C.c_double),
+                ("kmeans_updates", C.c_int32), ("n_s0", C.c_int64), ("n_s1", C.c_int64),
+                ("n_sc", C.c_int64), ("coarse_edges", C.c_int64), ("coarse_value", C.c_double)]
+
+
 class IrlsError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"irls_mincut error {code}: {msg}")
@@ -65,6 +71,7 @@ def lib():
         L.irls_mincut_solve_range.argtypes = [H, C.c_int32, C.c_void_p, C.c_double, C.c_int32,
                                               C.POINTER(RoundStats)]
         L.irls_mincut_cut.argtypes = [H, PU8, PF64, P64]
+        L.irls_mincut_cut_two_level.argtypes = [H, PU8, PF64, C.POINTER(TwoLevelInfo)]
         L.irls_mincut_potentials.argtypes = [H, PF64]
         L.irls_mincut_set_potentials.argtypes = [H, C.c_void_p]
         L.irls_mincut_info.argtypes = [H, P64, P64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -79,8 +86,8 @@ def lib():
                                                P64, P64, C.POINTER(Options), C.c_void_p]
         L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
         L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
-        for f in ("create", "solve", "solve_range", "cut", "potentials", "set_potentials", "info",
-                  "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch"):
+        for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "potentials", "set_potentials",
+                  "info", "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
         PF32 = C.POINTER(C.c_float)
         L.irls_gnn_create.argtypes = [C.POINTER(H), C.c_int32, C.c_int32, C.c_uint64, C.c_void_p]
@@ -200,6 +207,18 @@ class MinCut:
         if rc != OK:
             raise self._err(rc)
         return mask.astype(bool), val.value, ks.value
+
+    def cut_two_level(self):
+        """Two-level rounding (irls_mincut_cut_two_level). Returns (in_S bool [n],
+        value, info dict)."""
+        mask = np.zeros(self.n, np.uint8)
+        val = C.c_double(0)
+        info = TwoLevelInfo()
+        rc = lib().irls_mincut_cut_two_level(self.h, mask.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                             C.byref(val), C.byref(info))
+        if rc != OK:
+            raise self._err(rc)
+        return mask.astype(bool), val.value, {f: getattr(info, f) for f, _ in TwoLevelInfo._fields_}
 
     def potentials(self):
         x = np.zeros(self.n)

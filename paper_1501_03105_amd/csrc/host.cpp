@@ -1,6 +1,8 @@
 // Host side of libirls_mincut: the C ABI, argument validation, graph set-up
-// (merging, connectivity, storage format), the IRLS round driver and the
-// sweep-cut driver.  All arithmetic of the method runs in the HIP kernels.
+// (merging, connectivity, storage format), the IRLS round driver, the
+// sweep-cut driver and the two-level rounding driver.  All arithmetic of the
+// method runs in the HIP kernels, except the exact minimum cut of the small
+// coarse graph of the two-level rounding (a max-flow, below).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -247,6 +249,100 @@ irls_status build_host_graph(HostGraph &g, int64_t n, int64_t m, const int64_t *
   return IRLS_OK;
 }
 
+// ----------------------------------------------------------------------------
+// Exact maximum flow / minimum cut of a small undirected graph with 128-bit
+// integer capacities (the coarse graph of the two-level rounding): Dinic's
+// blocking flows on the level graph of residual arcs.  The returned source
+// side is the set of nodes that cannot reach t in the final residual graph,
+// which is the same for every maximum flow (the largest minimum-cut source
+// side).
+// ----------------------------------------------------------------------------
+struct FlowGraph {
+  int64_t n = 0;
+  std::vector<int64_t> first;     // [n+1] arcs of node v
+  std::vector<int64_t> to, mate;  // [arcs]
+  std::vector<i128> res;          // residual capacity
+};
+
+FlowGraph flow_graph(int64_t n, const std::vector<int64_t> &a, const std::vector<int64_t> &b,
+                     const std::vector<i128> &c) {
+  FlowGraph F;
+  F.n = n;
+  F.first.assign(n + 1, 0);
+  for (size_t e = 0; e < a.size(); e++) { F.first[a[e] + 1]++; F.first[b[e] + 1]++; }
+  for (int64_t v = 0; v < n; v++) F.first[v + 1] += F.first[v];
+  const int64_t na = F.first[n];
+  F.to.resize(na);
+  F.mate.resize(na);
+  F.res.resize(na);
+  std::vector<int64_t> fill(F.first.begin(), F.first.end() - 1);
+  for (size_t e = 0; e < a.size(); e++) {           // an undirected edge: two arcs of capacity c
+    const int64_t x = fill[a[e]]++, y = fill[b[e]]++;
+    F.to[x] = b[e]; F.res[x] = c[e]; F.mate[x] = y;
+    F.to[y] = a[e]; F.res[y] = c[e]; F.mate[y] = x;
+  }
+  return F;
+}
+
+i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_side) {
+  const int64_t n = F.n;
+  std::vector<int64_t> level(n), it(n), queue(n), path;
+  i128 flow = 0;
+  for (;;) {
+    std::fill(level.begin(), level.end(), -1);
+    int64_t qh = 0, qt = 0;
+    level[s] = 0;
+    queue[qt++] = s;
+    while (qh < qt) {
+      const int64_t v = queue[qh++];
+      for (int64_t a = F.first[v]; a < F.first[v + 1]; a++)
+        if (F.res[a] > 0 && level[F.to[a]] < 0) { level[F.to[a]] = level[v] + 1; queue[qt++] = F.to[a]; }
+    }
+    if (level[t] < 0) break;
+    for (int64_t v = 0; v < n; v++) it[v] = F.first[v];
+    for (;;) {                                          // augmenting paths in the level graph
+      path.clear();
+      int64_t v = s;
+      while (v != t) {
+        int64_t a = it[v];
+        for (; a < F.first[v + 1]; a++)
+          if (F.res[a] > 0 && level[F.to[a]] == level[v] + 1) break;
+        it[v] = a;
+        if (a < F.first[v + 1]) {
+          path.push_back(a);
+          v = F.to[a];
+        } else {                                        // dead end: leave it out of this phase
+          level[v] = -1;
+          if (path.empty()) break;
+          v = F.to[F.mate[path.back()]];
+          path.pop_back();
+          it[v]++;
+        }
+      }
+      if (v != t) break;
+      i128 d = F.res[path[0]];
+      for (int64_t a : path) d = std::min(d, F.res[a]);
+      for (int64_t a : path) { F.res[a] -= d; F.res[F.mate[a]] += d; }
+      flow += d;
+    }
+  }
+  // nodes that reach t through residual arcs form the sink side
+  std::vector<uint8_t> reach(n, 0);
+  int64_t qh = 0, qt = 0;
+  reach[t] = 1;
+  queue[qt++] = t;
+  while (qh < qt) {
+    const int64_t y = queue[qh++];
+    for (int64_t a = F.first[y]; a < F.first[y + 1]; a++) {
+      const int64_t x = F.to[a];
+      if (!reach[x] && F.res[F.mate[a]] > 0) { reach[x] = 1; queue[qt++] = x; }
+    }
+  }
+  source_side.assign(n, 0);
+  for (int64_t v = 0; v < n; v++) source_side[v] = reach[v] ? 0 : 1;
+  return flow;
+}
+
 irls_status check_options(const irls_options &o, std::string &err) {
   if (o.struct_size != (int32_t)sizeof(irls_options)) { err = "irls_options.struct_size mismatch"; return IRLS_ERR_OPTIONS; }
   if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
@@ -403,6 +499,7 @@ struct irls_mincut_s {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
   SweepBufs sw;
+  TwoLevelBufs tl;
   std::vector<void *> allocs;
 
   template <typename T>
@@ -1065,6 +1162,158 @@ irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cu
     if (cut_value) *cut_value = fx_to_double(h->D0 + best, g.fx_k);
     if (k_star) *k_star = ks;
     return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
+                                      irls_two_level_info *info) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "two-level rounding runs on single-graph handles"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "no potentials yet: call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
+  try {
+    GraphDev &g = h->g;
+    const int64_t nt = g.nt, n = g.n;
+    TwoLevelBufs &b = h->tl;
+    if (!b.cls && nt > 0) {
+      b.grid = (int)std::min<int64_t>(kMaxGrid, std::max<int64_t>(1, (nt + kBlock - 1) / kBlock));
+      b.chunk = (nt + b.grid - 1) / b.grid;
+      const int64_t ni = std::max<int64_t>(1, g.nnz / 2);
+      HIPCHK(h, h->dalloc(&b.cls, nt), "alloc");
+      HIPCHK(h, h->dalloc(&b.cid, nt), "alloc");
+      HIPCHK(h, h->dalloc(&b.part, 3 * b.grid), "alloc");
+      HIPCHK(h, h->dalloc(&b.bnodes, b.grid), "alloc");
+      HIPCHK(h, h->dalloc(&b.bedges, b.grid), "alloc");
+      HIPCHK(h, h->dalloc(&b.boff, b.grid), "alloc");
+      HIPCHK(h, h->dalloc(&b.eoff, b.grid), "alloc");
+      HIPCHK(h, h->dalloc(&b.bst, b.grid), "alloc");
+      HIPCHK(h, h->dalloc(&b.eu, ni), "alloc");
+      HIPCHK(h, h->dalloc(&b.ev, ni), "alloc");
+      HIPCHK(h, h->dalloc(&b.ecap, ni), "alloc");
+      HIPCHK(h, h->dalloc(&b.ws, nt), "alloc");
+      HIPCHK(h, h->dalloc(&b.wt, nt), "alloc");
+      HIPCHK(h, h->dalloc(&b.side, nt + 2), "alloc");
+      HIPCHK(h, h->dalloc(&b.mask, n), "alloc");
+    }
+    hipStream_t st = h->stream;
+    // 1. K-means with two centres on all n potentials (x_s = 1, x_t = 0)
+    double c0 = 0.1, c1 = 0.9;
+    double prev = -1.0;
+    int32_t updates = 0;
+    std::vector<double> part(3 * (size_t)std::max(b.grid, 1));
+    while (updates < 100) {
+      const double m = 0.5 * (c0 + c1);
+      double cnt_hi = 0.0, sum_hi = 0.0, sum_lo = 0.0;
+      if (nt > 0) {
+        HIPCHK(h, launch_tl_kmeans(h->v, nt, m, b.part, b.grid, st), "K-means");
+        HIPCHK(h, hipMemcpyAsync(part.data(), b.part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+               "readback");
+        HIPCHK(h, hipStreamSynchronize(st), "sync");
+        for (int w = 0; w < b.grid; w++) { cnt_hi += part[3 * w]; sum_hi += part[3 * w + 1]; sum_lo += part[3 * w + 2]; }
+      }
+      for (double xt : {1.0, 0.0}) {                   // s and t
+        if (xt > m) { cnt_hi += 1.0; sum_hi += xt; }
+        else sum_lo += xt;
+      }
+      if (cnt_hi == prev) break;
+      const double cnt_lo = (double)n - cnt_hi;
+      if (cnt_lo > 0.0) c0 = sum_lo / cnt_lo;
+      if (cnt_hi > 0.0) c1 = sum_hi / cnt_hi;
+      prev = cnt_hi;
+      updates++;
+    }
+    const double g0 = c0 + 0.05, g1 = c1 - 0.05;
+    if (!(1.0 >= g1) || !(0.0 <= g0)) {
+      h->err = "potentials outside [0, 1]: s or t would not be coalesced";
+      return IRLS_ERR_RANGE;
+    }
+    // 2. split and compaction, 3. coarse capacities (exact fixed point)
+    int64_t nc = 0, ne = 0, n_s1 = 1, n_s0 = 1;
+    std::vector<int32_t> eu, ev;
+    std::vector<i128> ecap, ws, wt;
+    i128 st_cap = fx_round_host(g.cst, g.fx_k);
+    if (nt > 0) {
+      const int G = b.grid;
+      HIPCHK(h, launch_tl_classify(h->v, nt, g0, g1, b.cls, G, st), "classify");
+      HIPCHK(h, launch_tl_count(b.cls, g.rowptr, g.col, nt, b.chunk, b.bnodes, b.bedges, G, st), "count");
+      std::vector<int64_t> bn(G), be(G), bo(G), eo(G);
+      HIPCHK(h, hipMemcpyAsync(bn.data(), b.bnodes, G * sizeof(int64_t), hipMemcpyDeviceToHost, st), "readback");
+      HIPCHK(h, hipMemcpyAsync(be.data(), b.bedges, G * sizeof(int64_t), hipMemcpyDeviceToHost, st), "readback");
+      HIPCHK(h, hipStreamSynchronize(st), "sync");
+      for (int w = 0; w < G; w++) { bo[w] = nc; eo[w] = ne; nc += bn[w]; ne += be[w]; }
+      HIPCHK(h, hipMemcpyAsync(b.boff, bo.data(), G * sizeof(int64_t), hipMemcpyHostToDevice, st), "upload");
+      HIPCHK(h, hipMemcpyAsync(b.eoff, eo.data(), G * sizeof(int64_t), hipMemcpyHostToDevice, st), "upload");
+      HIPCHK(h, launch_tl_ids(b.cls, nt, b.chunk, b.boff, nc, b.cid, G, st), "ids");
+      HIPCHK(h, launch_tl_edges(b.cls, b.cid, g.rowptr, g.col, g.ccap, g.cs, g.ct, nt, b.chunk, g.fx_k, b.eoff,
+                                b.eu, b.ev, b.ecap, b.ws, b.wt, b.bst, G, st), "coarse edges");
+      eu.resize(ne); ev.resize(ne); ecap.resize(ne); ws.resize(nc); wt.resize(nc);
+      std::vector<i128> bst(G);
+      if (ne > 0) {
+        HIPCHK(h, hipMemcpyAsync(eu.data(), b.eu, ne * sizeof(int32_t), hipMemcpyDeviceToHost, st), "readback");
+        HIPCHK(h, hipMemcpyAsync(ev.data(), b.ev, ne * sizeof(int32_t), hipMemcpyDeviceToHost, st), "readback");
+        HIPCHK(h, hipMemcpyAsync(ecap.data(), b.ecap, ne * sizeof(i128), hipMemcpyDeviceToHost, st), "readback");
+      }
+      if (nc > 0) {
+        HIPCHK(h, hipMemcpyAsync(ws.data(), b.ws, nc * sizeof(i128), hipMemcpyDeviceToHost, st), "readback");
+        HIPCHK(h, hipMemcpyAsync(wt.data(), b.wt, nc * sizeof(i128), hipMemcpyDeviceToHost, st), "readback");
+      }
+      HIPCHK(h, hipMemcpyAsync(bst.data(), b.bst, G * sizeof(i128), hipMemcpyDeviceToHost, st), "readback");
+      HIPCHK(h, hipStreamSynchronize(st), "sync");
+      for (int w = 0; w < G; w++) st_cap += bst[w];
+    }
+    // 4. exact minimum cut of G_c: Sc = 0..nc-1, s_c = nc, t_c = nc + 1;
+    //    parallel coarse edges are merged by the flow graph's arcs
+    std::vector<int64_t> fa, fb;
+    std::vector<i128> fc;
+    fa.reserve(ne + 2 * nc + 1); fb.reserve(ne + 2 * nc + 1); fc.reserve(ne + 2 * nc + 1);
+    for (int64_t e = 0; e < ne; e++) { fa.push_back(eu[e]); fb.push_back(ev[e]); fc.push_back(ecap[e]); }
+    int64_t merged_edges = ne;
+    for (int64_t u = 0; u < nc; u++) {
+      if (ws[u] > 0) { fa.push_back(nc); fb.push_back(u); fc.push_back(ws[u]); merged_edges++; }
+      if (wt[u] > 0) { fa.push_back(u); fb.push_back(nc + 1); fc.push_back(wt[u]); merged_edges++; }
+    }
+    if (st_cap > 0) { fa.push_back(nc); fb.push_back(nc + 1); fc.push_back(st_cap); merged_edges++; }
+    FlowGraph F = flow_graph(nc + 2, fa, fb, fc);
+    std::vector<uint8_t> side;
+    const i128 flow = max_flow(F, nc, nc + 1, side);
+    // lift: S1 and the source side's part of Sc, in original node ids
+    if (in_source_side) {
+      if (nt > 0) {
+        HIPCHK(h, hipMemcpyAsync(b.side, side.data(), nc + 2, hipMemcpyHostToDevice, st), "upload");
+        HIPCHK(h, launch_tl_lift(b.cls, b.cid, b.side, nt, std::min(g.s, g.t), std::max(g.s, g.t), b.mask, b.grid, st),
+               "lift");
+        HIPCHK(h, hipMemcpyAsync(in_source_side, b.mask, n, hipMemcpyDeviceToHost, st), "readback");
+        HIPCHK(h, hipStreamSynchronize(st), "sync");
+      }
+      in_source_side[g.s] = 1;
+      in_source_side[g.t] = 0;
+    }
+    if (nt > 0) {
+      std::vector<int8_t> cls(nt);
+      HIPCHK(h, hipMemcpyAsync(cls.data(), b.cls, nt, hipMemcpyDeviceToHost, st), "readback");
+      HIPCHK(h, hipStreamSynchronize(st), "sync");
+      for (int64_t u = 0; u < nt; u++) { n_s0 += cls[u] == 0; n_s1 += cls[u] == 1; }
+    }
+    const double value = fx_to_double(flow, g.fx_k);
+    if (cut_value) *cut_value = value;
+    if (info) {
+      info->c0 = c0;
+      info->c1 = c1;
+      info->gamma0 = g0;
+      info->gamma1 = g1;
+      info->kmeans_updates = updates;
+      info->n_s0 = n_s0;
+      info->n_s1 = n_s1;
+      info->n_sc = nc;
+      info->coarse_edges = merged_edges;
+      info->coarse_value = value;
+    }
+    return IRLS_OK;
+  } catch (const std::bad_alloc &) {
+    h->err = "host allocation failed";
+    return IRLS_ERR_OOM;
   } catch (...) {
     h->err = "unexpected host exception";
     return IRLS_ERR_DEVICE;

@@ -147,6 +147,35 @@ template <typename T> hipError_t launch_replace_residual(const CGArgs<T> &a, int
                                                          hipStream_t st);
 template <typename T> hipError_t launch_stats(const CGArgs<T> &a, int grid, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double value, hipStream_t st);
+
+// two-level rounding (twolevel.hip)
+struct TwoLevelBufs {
+  int grid = 0;
+  int64_t chunk = 0;
+  int8_t *cls = nullptr;          // [nt] 0: S0, 1: S1, 2: Sc
+  int32_t *cid = nullptr;         // [nt] coarse id
+  double *part = nullptr;         // [3 grid] K-means partial sums
+  int64_t *bnodes = nullptr, *bedges = nullptr, *boff = nullptr, *eoff = nullptr;   // [grid]
+  __int128 *bst = nullptr;        // [grid] S1-S0 capacity per workgroup
+  int32_t *eu = nullptr, *ev = nullptr;   // [interior edges] coarse Sc-Sc edges
+  __int128 *ecap = nullptr;
+  __int128 *ws = nullptr, *wt = nullptr;  // [nt] capacity of each coarse node to s_c / t_c
+  uint8_t *side = nullptr;        // [nt + 2] source side of the coarse cut
+  uint8_t *mask = nullptr;        // [n] lifted cut
+};
+hipError_t launch_tl_kmeans(const double *v, int64_t nt, double m, double *part, int grid, hipStream_t st);
+hipError_t launch_tl_classify(const double *v, int64_t nt, double g0, double g1, int8_t *cls, int grid,
+                              hipStream_t st);
+hipError_t launch_tl_count(const int8_t *cls, const int32_t *rowptr, const int32_t *col, int64_t nt, int64_t chunk,
+                           int64_t *bnodes, int64_t *bedges, int grid, hipStream_t st);
+hipError_t launch_tl_ids(const int8_t *cls, int64_t nt, int64_t chunk, const int64_t *boff, int64_t nc,
+                         int32_t *cid, int grid, hipStream_t st);
+hipError_t launch_tl_edges(const int8_t *cls, const int32_t *cid, const int32_t *rowptr, const int32_t *col,
+                           const double *ccap, const double *cs, const double *ct, int64_t nt, int64_t chunk,
+                           int fx_k, const int64_t *eoff, int32_t *eu, int32_t *ev, __int128 *ecap, __int128 *ws,
+                           __int128 *wt, __int128 *bst, int grid, hipStream_t st);
+hipError_t launch_tl_lift(const int8_t *cls, const int32_t *cid, const uint8_t *side, int64_t nt, int64_t lo,
+                          int64_t hi, uint8_t *mask, int grid, hipStream_t st);
 hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every,
                                 hipStream_t st);
 

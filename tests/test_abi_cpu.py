@@ -28,6 +28,7 @@ def P():
 def test_header_symbols_exported(P):
     names = declared_functions()
     assert "irls_mincut_create" in names and "irls_mincut_cut_batch" in names
+    assert "irls_mincut_cut_two_level" in names
     lib = C.CDLL(P.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -71,6 +72,7 @@ def test_null_handle_calls(P):
     L = P.lib()
     assert L.irls_mincut_solve(None, None, None) == P.ERR_NULL
     assert L.irls_mincut_cut(None, None, None, None) == P.ERR_NULL
+    assert L.irls_mincut_cut_two_level(None, None, None, None) == P.ERR_NULL
     assert L.irls_mincut_potentials(None, None) == P.ERR_NULL
     L.irls_mincut_destroy(None)
     assert L.irls_mincut_last_error(None)

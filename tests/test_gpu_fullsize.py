@@ -37,6 +37,7 @@ def test_fullsize_sweep_and_invariants(P, oracle_mod, seg128):
         rc, st = mc.solve()
         x = mc.potentials()
         inS, val, k = mc.cut()
+        S2, val2, info2 = mc.cut_two_level()
     assert rc == P.OK
     So, vo, ko, _ = oracle_mod.sweep(g, x)
     say(f"128^3: cut {val!r} k {k}; oracle sweep of the same x {vo!r} k {ko}")
@@ -60,6 +61,14 @@ def test_fullsize_sweep_and_invariants(P, oracle_mod, seg128):
     say(f"128^3: exact minimum cut {mu!r}, delta {delta:.2e}")
     assert val >= mu * (1 - 1e-12)
     assert delta < 1e-3
+    # two-level rounding of the same potentials: its exact value, never below
+    # the minimum and, with these polarised potentials, no worse than the sweep
+    delta2 = (val2 - mu) / mu
+    say(f"128^3: two-level cut {val2!r} (Sc {info2['n_sc']} nodes, {info2['coarse_edges']} coarse edges), "
+        f"delta {delta2:.2e}")
+    assert val2 == oracle_mod.cut_value(g, S2)
+    assert val2 >= mu * (1 - 1e-12) and val2 <= val
+    assert info2["n_sc"] < g.n // 10
 
 
 @pytest.mark.parametrize("l", [1, 25])
