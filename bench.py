@@ -361,6 +361,16 @@ def main():
     dt = time.perf_counter() - t0
     iters = sum(r["cg_iters"] for r in st)
     ms_step = 1000.0 * dt / args.steps
+    # the two-level rounding of the same potentials, timed on its own (it is
+    # the paper's alternative to the sweep, not part of the step)
+    t0 = time.perf_counter()
+    _, val2, info2 = mc.cut_two_level()
+    torch.cuda.synchronize()
+    two = {"cut_value": val2, "seconds": round(time.perf_counter() - t0, 4),
+           "relative_to_sweep": (val2 - val) / val, "coarse_nodes": info2["n_sc"] + 2,
+           "coarse_edges": info2["coarse_edges"], "gamma": [info2["gamma0"], info2["gamma1"]]}
+    print(f"[bench] two-level rounding: cut {val2:.10g} ({two['relative_to_sweep']:.2e} vs the sweep) "
+          f"in {two['seconds']:.3f} s, coarse graph {two['coarse_nodes']} nodes", file=sys.stderr, flush=True)
 
     roof = None
     if info["solver"] == 1:
@@ -407,7 +417,7 @@ def main():
         "config": {"workload": desc, "name": args.workload, "n_nonterminal": info["n_nonterminal"],
                    "interior_edges": info["nnz_offdiag"] // 2, "format": info["format"],
                    "solver": info["solver"], "cg_iters_per_cut": iters, "cut_value": val,
-                   "setup_s": round(t_setup, 3)},
+                   "setup_s": round(t_setup, 3), "two_level": two},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
