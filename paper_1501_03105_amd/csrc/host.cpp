@@ -300,9 +300,9 @@ i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_s
     }
     if (level[t] < 0) break;
     for (int64_t v = 0; v < n; v++) it[v] = F.first[v];
+    path.clear();
+    int64_t v = s;
     for (;;) {                                          // augmenting paths in the level graph
-      path.clear();
-      int64_t v = s;
       while (v != t) {
         int64_t a = it[v];
         for (; a < F.first[v + 1]; a++)
@@ -322,8 +322,17 @@ i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_s
       if (v != t) break;
       i128 d = F.res[path[0]];
       for (int64_t a : path) d = std::min(d, F.res[a]);
-      for (int64_t a : path) { F.res[a] -= d; F.res[F.mate[a]] += d; }
+      size_t keep = path.size();
+      for (size_t i = 0; i < path.size(); i++) {
+        const int64_t a = path[i];
+        F.res[a] -= d;
+        F.res[F.mate[a]] += d;
+        if (F.res[a] == 0 && i < keep) keep = i;        // the first arc the path saturated
+      }
       flow += d;
+      // continue from the tail of the first saturated arc
+      v = F.to[F.mate[path[keep]]];
+      path.resize(keep);
     }
   }
   // nodes that reach t through residual arcs form the sink side
@@ -341,6 +350,32 @@ i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_s
   source_side.assign(n, 0);
   for (int64_t v = 0; v < n; v++) source_side[v] = reach[v] ? 0 : 1;
   return flow;
+}
+
+// Minimum s_c-t_c cut of the coarse graph: nodes 0..nc-1 with capacity ws[u]
+// to s_c = nc and wt[u] to t_c = nc + 1, edges (eu, ev, ecap) among them, and
+// st between s_c and t_c.  The flow along s_c - u - t_c (min(ws, wt) per node)
+// and along s_c - t_c is taken first, so the max-flow sees each node joined
+// to at most one terminal; the arcs into s_c and out of t_c this leaves out
+// lie on no augmenting path, and a node that reached t_c through s_c would
+// contradict maximality.  Returns the flow (= the cut value) and the largest
+// source side (nc + 2 entries).
+i128 coarse_min_cut(int64_t nc, const std::vector<int32_t> &eu, const std::vector<int32_t> &ev,
+                    const std::vector<i128> &ecap, const std::vector<i128> &ws, const std::vector<i128> &wt,
+                    i128 st, std::vector<uint8_t> &side) {
+  i128 flow = st;
+  std::vector<int64_t> fa, fb;
+  std::vector<i128> fc;
+  fa.reserve(eu.size() + nc); fb.reserve(eu.size() + nc); fc.reserve(eu.size() + nc);
+  for (size_t e = 0; e < eu.size(); e++) { fa.push_back(eu[e]); fb.push_back(ev[e]); fc.push_back(ecap[e]); }
+  for (int64_t u = 0; u < nc; u++) {
+    const i128 d = std::min(ws[u], wt[u]);
+    flow += d;
+    if (ws[u] > d) { fa.push_back(nc); fb.push_back(u); fc.push_back(ws[u] - d); }
+    if (wt[u] > d) { fa.push_back(u); fb.push_back(nc + 1); fc.push_back(wt[u] - d); }
+  }
+  FlowGraph F = flow_graph(nc + 2, fa, fb, fc);
+  return flow + max_flow(F, nc, nc + 1, side);
 }
 
 irls_status check_options(const irls_options &o, std::string &err) {
@@ -1263,21 +1298,11 @@ irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, 
       HIPCHK(h, hipStreamSynchronize(st), "sync");
       for (int w = 0; w < G; w++) st_cap += bst[w];
     }
-    // 4. exact minimum cut of G_c: Sc = 0..nc-1, s_c = nc, t_c = nc + 1;
-    //    parallel coarse edges are merged by the flow graph's arcs
-    std::vector<int64_t> fa, fb;
-    std::vector<i128> fc;
-    fa.reserve(ne + 2 * nc + 1); fb.reserve(ne + 2 * nc + 1); fc.reserve(ne + 2 * nc + 1);
-    for (int64_t e = 0; e < ne; e++) { fa.push_back(eu[e]); fb.push_back(ev[e]); fc.push_back(ecap[e]); }
-    int64_t merged_edges = ne;
-    for (int64_t u = 0; u < nc; u++) {
-      if (ws[u] > 0) { fa.push_back(nc); fb.push_back(u); fc.push_back(ws[u]); merged_edges++; }
-      if (wt[u] > 0) { fa.push_back(u); fb.push_back(nc + 1); fc.push_back(wt[u]); merged_edges++; }
-    }
-    if (st_cap > 0) { fa.push_back(nc); fb.push_back(nc + 1); fc.push_back(st_cap); merged_edges++; }
-    FlowGraph F = flow_graph(nc + 2, fa, fb, fc);
+    // 4. exact minimum cut of G_c: Sc = 0..nc-1, s_c = nc, t_c = nc + 1
+    int64_t merged_edges = ne + (st_cap > 0);
+    for (int64_t u = 0; u < nc; u++) merged_edges += (ws[u] > 0) + (wt[u] > 0);
     std::vector<uint8_t> side;
-    const i128 flow = max_flow(F, nc, nc + 1, side);
+    const i128 flow = coarse_min_cut(nc, eu, ev, ecap, ws, wt, st_cap, side);
     // lift: S1 and the source side's part of Sc, in original node ids
     if (in_source_side) {
       if (nt > 0) {
