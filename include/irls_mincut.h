@@ -189,6 +189,19 @@ typedef struct {
 irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
                                       irls_two_level_info *info);
 
+/* New capacities for the graph of a single-graph handle, for sequences of
+ * related min-cut problems (the paper's stated application and future work,
+ * Section 6: FlowImprove and graph-cut loops).  The edge list follows
+ * irls_mincut_create's rules and must merge to the handle's structure (the
+ * same nodes, s, t and neighbour pairs); only capacities change.  The
+ * potentials are kept: irls_mincut_solve_range with start 1 continues from
+ * them, irls_mincut_solve starts over per the options.  Arrays are read
+ * during the call (device arrays when inputs_on_device).
+ * Errors: as irls_mincut_create for the arrays; IRLS_ERR_OPTIONS when the
+ * structure differs or for a batch handle. */
+irls_status irls_mincut_update_capacities(irls_mincut_t h, int64_t m, const int64_t *edge_u,
+                                          const int64_t *edge_v, const double *cap);
+
 /* Copy the current potentials (host; x_s = 1, x_t = 0): n doubles, or for a
  * batch handle sum(n_g) doubles laid out like node_off. */
 irls_status irls_mincut_potentials(irls_mincut_t h, double *x);

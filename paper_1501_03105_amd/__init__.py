@@ -72,6 +72,7 @@ def lib():
                                               C.POINTER(RoundStats)]
         L.irls_mincut_cut.argtypes = [H, PU8, PF64, P64]
         L.irls_mincut_cut_two_level.argtypes = [H, PU8, PF64, C.POINTER(TwoLevelInfo)]
+        L.irls_mincut_update_capacities.argtypes = [H, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.irls_mincut_potentials.argtypes = [H, PF64]
         L.irls_mincut_set_potentials.argtypes = [H, C.c_void_p]
         L.irls_mincut_info.argtypes = [H, P64, P64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -86,7 +87,8 @@ def lib():
                                                P64, P64, C.POINTER(Options), C.c_void_p]
         L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
         L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
-        for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "potentials", "set_potentials",
+        for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "update_capacities", "potentials",
+                  "set_potentials",
                   "info", "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
         PF32 = C.POINTER(C.c_float)
@@ -207,6 +209,16 @@ class MinCut:
         if rc != OK:
             raise self._err(rc)
         return mask.astype(bool), val.value, ks.value
+
+    def update_capacities(self, eu, ev, cap):
+        """irls_mincut_update_capacities: same structure, new capacities."""
+        pu, ku, _ = _ptr(eu, np.int64)
+        pv, kv, _ = _ptr(ev, np.int64)
+        pc, kc, _ = _ptr(cap, np.float64)
+        m = 0 if ku is None else int(ku.shape[0] if hasattr(ku, "shape") else len(ku))
+        rc = lib().irls_mincut_update_capacities(self.h, m, pu, pv, pc)
+        if rc != OK:
+            raise self._err(rc)
 
     def cut_two_level(self):
         """Two-level rounding (irls_mincut_cut_two_level). Returns (in_S bool [n],

@@ -840,6 +840,23 @@ irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
   return result;
 }
 
+// The graph record of a single-graph resident handle (heavy-row counts and
+// lanes from create; the capacity-dependent fields from the graph).
+irls_status upload_res_record(irls_mincut_t h) {
+  BatchGraph rg = h->res_graph;
+  rg.node0 = 0;
+  rg.nnz0 = 0;
+  rg.node_off = 0;
+  rg.nt = h->g.nt;
+  rg.s = h->g.s;
+  rg.t = h->g.t;
+  rg.cst = h->g.cst;
+  rg.fx_k = h->g.fx_k;
+  rg.no_source_edges = h->g.no_source_edges ? 1 : 0;
+  HIPCHK(h, hipMemcpy(h->rgraphs, &rg, sizeof(rg), hipMemcpyHostToDevice), "upload");
+  return IRLS_OK;
+}
+
 irls_status alloc_state(irls_mincut_t h) {
   const int64_t nt = h->g.nt;
   const bool f32 = h->opt.precision == 1;
@@ -886,20 +903,11 @@ irls_status alloc_state(irls_mincut_t h) {
     HIPCHK(h, h->dalloc(&h->rgraphs, 1), "alloc");
     HIPCHK(h, h->dalloc(&h->rorder, 1), "alloc");
     HIPCHK(h, h->dalloc(&h->rnext, 1), "alloc");
-    BatchGraph rg = h->res_graph;      // heavy-row counts and lanes from create
-    rg.node0 = 0;
-    rg.nnz0 = 0;
-    rg.node_off = 0;
-    rg.nt = nt;
-    rg.s = h->g.s;
-    rg.t = h->g.t;
-    rg.cst = h->g.cst;
-    rg.fx_k = h->g.fx_k;
-    rg.no_source_edges = h->g.no_source_edges ? 1 : 0;
     int32_t zero = 0;
-    HIPCHK(h, hipMemcpy(h->rgraphs, &rg, sizeof(rg), hipMemcpyHostToDevice), "upload");
     HIPCHK(h, hipMemcpy(h->rorder, &zero, sizeof(zero), hipMemcpyHostToDevice), "upload");
-    h->rpw = 64 / rg.lanes;
+    irls_status rc = upload_res_record(h);
+    if (rc != IRLS_OK) return rc;
+    h->rpw = 64 / h->res_graph.lanes;
   }
   return IRLS_OK;
 }
@@ -1334,6 +1342,73 @@ irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, 
       info->n_sc = nc;
       info->coarse_edges = merged_edges;
       info->coarse_value = value;
+    }
+    return IRLS_OK;
+  } catch (const std::bad_alloc &) {
+    h->err = "host allocation failed";
+    return IRLS_ERR_OOM;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_update_capacities(irls_mincut_t h, int64_t m, const int64_t *edge_u,
+                                          const int64_t *edge_v, const double *cap) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "capacity updates run on single-graph handles"; return IRLS_ERR_OPTIONS; }
+  if (m > 0 && (!edge_u || !edge_v || !cap)) { h->err = "edge arrays must not be NULL"; return IRLS_ERR_NULL; }
+  try {
+    GraphDev &g = h->g;
+    std::vector<int64_t> hu, hv;
+    std::vector<double> hc;
+    if (h->opt.inputs_on_device && m > 0) {
+      hu.resize(m); hv.resize(m); hc.resize(m);
+      if (hipMemcpy(hu.data(), edge_u, m * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hv.data(), edge_v, m * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hc.data(), cap, m * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+        h->err = "cannot read the device edge arrays";
+        return IRLS_ERR_DEVICE;
+      }
+      edge_u = hu.data(); edge_v = hv.data(); cap = hc.data();
+    }
+    HostGraph hg;
+    std::string err;
+    irls_status rc = build_host_graph(hg, g.n, m, edge_u, edge_v, cap, g.s, g.t, err);
+    if (rc != IRLS_OK) { h->err = err; return rc; }
+    // the merged structure must be the handle's: same rows and neighbours
+    bool same = hg.nt == g.nt && (int64_t)hg.col.size() == g.nnz;
+    if (same && g.format == 2) {
+      same = hg.dia_ok && hg.K == g.K;
+      for (int k = 0; same && k < g.K; k++) same = hg.off[k] == g.off[k];
+    }
+    if (same && g.nt > 0) {
+      std::vector<int32_t> rp(g.nt + 1), cl(g.nnz);
+      HIPCHK(h, hipMemcpy(rp.data(), g.rowptr, rp.size() * sizeof(int32_t), hipMemcpyDeviceToHost), "readback");
+      if (g.nnz > 0)
+        HIPCHK(h, hipMemcpy(cl.data(), g.col, cl.size() * sizeof(int32_t), hipMemcpyDeviceToHost), "readback");
+      same = rp == hg.rowptr && cl == hg.col;
+    }
+    if (!same) {
+      h->err = "the edges do not have the handle's structure (create a new handle)";
+      return IRLS_ERR_OPTIONS;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+    auto put = [&](double *dst, const std::vector<double> &src) -> hipError_t {
+      return src.empty() ? hipSuccess : hipMemcpy(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);
+    };
+    HIPCHK(h, put(g.ccap, hg.ccap), "upload");
+    HIPCHK(h, put(g.cs, hg.cs), "upload");
+    HIPCHK(h, put(g.ct, hg.ct), "upload");
+    if (g.format == 2) HIPCHK(h, put(g.dcap, hg.dcap), "upload");
+    g.cst = hg.cst;
+    g.cmax = hg.cmax;
+    g.fx_k = hg.fx_k;
+    g.no_source_edges = hg.no_source_edges;
+    h->D0 = hg.D0;
+    if (h->solver == 2) {
+      rc = upload_res_record(h);
+      if (rc != IRLS_OK) return rc;
     }
     return IRLS_OK;
   } catch (const std::bad_alloc &) {

@@ -1,0 +1,111 @@
+"""Sequences of related min-cut problems (irls_mincut_update_capacities):
+new capacities on a kept handle give the same results as a new handle with
+those capacities, for a fresh solve and for a continuation from the
+previous potentials, on the multi-workgroup (scaled marching, CSR) and the
+resident solvers; structure changes are refused."""
+import numpy as np
+import pytest
+
+import gen
+from gen.graphs import Graph
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1501_03105_amd as P
+    P.lib()
+    return P
+
+
+def perturbed(g, seed, spread=0.2):
+    """The same edges with capacities scaled by seeded factors in [1-spread, 1+spread]."""
+    f = 1.0 + spread * (2.0 * np.random.default_rng(seed).random(g.cap.shape[0]) - 1.0)
+    return Graph(g.n, g.s, g.t, g.eu, g.ev, g.cap * f, meta=dict(g.meta))
+
+
+CASES = [("seg 24^3 (scaled marching SpMV)", lambda: gen.grid3d_seg(24, seed=2), dict(solver=1)),
+         ("grid2d 64x64 as CSR", lambda: gen.grid2d(64, 64, seed=0), dict(solver=1, format=1)),
+         ("G(16,0.3) (resident)", lambda: gen.gnp(16, 0.3, seed=5), dict(solver=2))]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_update_equals_new_handle(P, case):
+    name, make, kw = CASES[case]
+    g1 = make()
+    g2 = perturbed(g1, seed=17)
+    opts = dict(rounds=20, cg_rtol=1e-10, **kw)
+    say(f"capacity update: {name}")
+    with P.MinCut.from_graph(g1, **opts) as a, P.MinCut.from_graph(g2, **opts) as b:
+        a.solve()
+        x1 = a.potentials()
+        a.update_capacities(g2.eu, g2.ev, g2.cap)
+        # a fresh solve after the update
+        _, sa = a.solve()
+        _, sb = b.solve()
+        xa, xb = a.potentials(), b.potentials()
+        assert np.array_equal(xa, xb)
+        assert [r["cg_iters"] for r in sa] == [r["cg_iters"] for r in sb]
+        Sa, va, ka = a.cut()
+        Sb, vb, kb = b.cut()
+        assert va == vb and ka == kb and np.array_equal(Sa, Sb)
+        # a continuation from the potentials of the old capacities
+        a.set_potentials(x1)
+        b.set_potentials(x1)
+        _, ca = a.solve_range(1, 8, eps_first=1e-3)
+        _, cb = b.solve_range(1, 8, eps_first=1e-3)
+        assert np.array_equal(a.potentials(), b.potentials())
+        assert [r["cg_iters"] for r in ca] == [r["cg_iters"] for r in cb]
+        assert a.cut()[1] == b.cut()[1]
+
+
+def test_update_refuses_structure_changes(P):
+    g = gen.grid2d(16, 16, seed=1)
+    with P.MinCut.from_graph(g, solver=1) as mc:
+        # an interior edge less changes the structure (a terminal edge less
+        # would not: its node just loses its capacity to s or t)
+        for eu, ev, cap, code in [(g.eu[1:], g.ev[1:], g.cap[1:], P.ERR_OPTIONS),
+                                  (g.eu, g.ev, np.where(np.arange(g.m) == 3, 0.0, g.cap), P.ERR_CAPACITY)]:
+            with pytest.raises(P.IrlsError) as e:
+                mc.update_capacities(eu, ev, cap)
+            assert e.value.code == code
+        # parallel copies and reordering merge to the same structure: accepted
+        order = np.random.default_rng(3).permutation(g.m)
+        eu = np.concatenate([g.eu[order], g.eu[:5]])
+        ev = np.concatenate([g.ev[order], g.ev[:5]])
+        cap = np.concatenate([g.cap[order], 0.5 * g.cap[:5]])
+        mc.update_capacities(eu, ev, cap)
+    b = P.MinCutBatch([gen.gnp(16, 0.3, seed=2)])
+    import ctypes as C
+    assert P.lib().irls_mincut_update_capacities(b.h, 0, None, None, None) == P.ERR_OPTIONS
+    b.close()
+
+
+def test_sequence_warm_continuation(P, oracle_mod):
+    """Measured: after a 20 % capacity change on a 32^3 segmentation grid, the
+    kept handle continues from the old potentials; the continuation's cut is
+    a valid cut (at least the exact minimum), and both CG counts are shown."""
+    g1 = gen.grid3d_seg(32, seed=4)
+    g2 = perturbed(g1, seed=23)
+    opts = dict(rounds=30, cg_rtol=1e-8, solver=1)
+    with P.MinCut.from_graph(g1, **opts) as mc:
+        mc.solve()
+        mc.update_capacities(g2.eu, g2.ev, g2.cap)
+        _, sw = mc.solve_range(1, 12, eps_first=1e-3)
+        _, vw, _ = mc.cut()
+        _, vw2, _ = mc.cut_two_level()
+        _, sf = mc.solve()
+        _, vf, _ = mc.cut()
+        _, vf2, _ = mc.cut_two_level()
+    _, mu = oracle_mod.maxflow(g2)
+    itw = sum(r["cg_iters"] for r in sw)
+    itf = sum(r["cg_iters"] for r in sf)
+    say(f"32^3 after a 20% capacity change: continuation {itw} CG iterations, sweep {(vw - mu) / mu:.2e} / "
+        f"two-level {(vw2 - mu) / mu:.2e} above the minimum; full solve {itf} CG iterations, "
+        f"{(vf - mu) / mu:.2e} / {(vf2 - mu) / mu:.2e}")
+    for v in (vw, vw2, vf, vf2):
+        assert v >= mu * (1 - 1e-12)
