@@ -13,6 +13,8 @@
 #include <numeric>
 #include <string>
 #include <vector>
+#include <atomic>
+#include <thread>
 
 #include "internal.h"
 
@@ -354,28 +356,95 @@ i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_s
 
 // Minimum s_c-t_c cut of the coarse graph: nodes 0..nc-1 with capacity ws[u]
 // to s_c = nc and wt[u] to t_c = nc + 1, edges (eu, ev, ecap) among them, and
-// st between s_c and t_c.  The flow along s_c - u - t_c (min(ws, wt) per node)
-// and along s_c - t_c is taken first, so the max-flow sees each node joined
-// to at most one terminal; the arcs into s_c and out of t_c this leaves out
-// lie on no augmenting path, and a node that reached t_c through s_c would
-// contradict maximality.  Returns the flow (= the cut value) and the largest
-// source side (nc + 2 entries).
+// st between s_c and t_c.
+//   * The flow along s_c - u - t_c (min(ws, wt) per node) and along s_c - t_c
+//     is taken first, so each node keeps at most one terminal edge.  The arcs
+//     into s_c and out of t_c this leaves out lie on no augmenting path.
+//   * The rest splits into the connected components of the Sc-Sc edges:
+//     they share only s_c and t_c, so each is a max-flow problem of its own
+//     (a node reaching t_c through s_c would contradict maximality).  The
+//     components run on host threads, largest first.
+// Returns the flow (= the cut value) and the largest source side (nc + 2
+// entries): the nodes that cannot reach t_c in the residual graph.
 i128 coarse_min_cut(int64_t nc, const std::vector<int32_t> &eu, const std::vector<int32_t> &ev,
                     const std::vector<i128> &ecap, const std::vector<i128> &ws, const std::vector<i128> &wt,
                     i128 st, std::vector<uint8_t> &side) {
   i128 flow = st;
-  std::vector<int64_t> fa, fb;
-  std::vector<i128> fc;
-  fa.reserve(eu.size() + nc); fb.reserve(eu.size() + nc); fc.reserve(eu.size() + nc);
-  for (size_t e = 0; e < eu.size(); e++) { fa.push_back(eu[e]); fb.push_back(ev[e]); fc.push_back(ecap[e]); }
+  std::vector<i128> rs(nc), rt(nc);
   for (int64_t u = 0; u < nc; u++) {
     const i128 d = std::min(ws[u], wt[u]);
     flow += d;
-    if (ws[u] > d) { fa.push_back(nc); fb.push_back(u); fc.push_back(ws[u] - d); }
-    if (wt[u] > d) { fa.push_back(u); fb.push_back(nc + 1); fc.push_back(wt[u] - d); }
+    rs[u] = ws[u] - d;
+    rt[u] = wt[u] - d;
   }
-  FlowGraph F = flow_graph(nc + 2, fa, fb, fc);
-  return flow + max_flow(F, nc, nc + 1, side);
+  side.assign(nc + 2, 0);
+  side[nc] = 1;
+  if (nc == 0) return flow;
+  UnionFind uf(nc);
+  for (size_t e = 0; e < eu.size(); e++) uf.unite(eu[e], ev[e]);
+  // components: dense ids, members in ascending order, edges grouped
+  std::vector<int64_t> comp(nc), cstart, pos(nc);
+  int64_t ncomp = 0;
+  {
+    std::vector<int64_t> id_of_root(nc, -1);
+    for (int64_t u = 0; u < nc; u++) {
+      const int64_t r = uf.find(u);
+      if (id_of_root[r] < 0) id_of_root[r] = ncomp++;
+      comp[u] = id_of_root[r];
+    }
+  }
+  cstart.assign(ncomp + 1, 0);
+  for (int64_t u = 0; u < nc; u++) cstart[comp[u] + 1]++;
+  for (int64_t c = 0; c < ncomp; c++) cstart[c + 1] += cstart[c];
+  std::vector<int64_t> members(nc), fillm(cstart.begin(), cstart.end() - 1);
+  for (int64_t u = 0; u < nc; u++) { pos[u] = fillm[comp[u]] - cstart[comp[u]]; members[fillm[comp[u]]++] = u; }
+  std::vector<int64_t> estart(ncomp + 1, 0), edges(eu.size());
+  for (size_t e = 0; e < eu.size(); e++) estart[comp[eu[e]] + 1]++;
+  for (int64_t c = 0; c < ncomp; c++) estart[c + 1] += estart[c];
+  std::vector<int64_t> fille(estart.begin(), estart.end() - 1);
+  for (size_t e = 0; e < eu.size(); e++) edges[fille[comp[eu[e]]]++] = (int64_t)e;
+  std::vector<int64_t> order(ncomp);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return cstart[x + 1] - cstart[x] > cstart[y + 1] - cstart[y];
+  });
+  auto solve = [&](int64_t c) -> i128 {
+    const int64_t k = cstart[c + 1] - cstart[c];
+    const int64_t *mem = members.data() + cstart[c];
+    if (estart[c + 1] == estart[c]) {                 // a lone node: no path through it
+      for (int64_t i = 0; i < k; i++) side[mem[i]] = rt[mem[i]] > 0 ? 0 : 1;
+      return 0;
+    }
+    std::vector<int64_t> fa, fb;
+    std::vector<i128> fc;
+    for (int64_t q = estart[c]; q < estart[c + 1]; q++) {
+      const int64_t e = edges[q];
+      fa.push_back(pos[eu[e]]); fb.push_back(pos[ev[e]]); fc.push_back(ecap[e]);
+    }
+    for (int64_t i = 0; i < k; i++) {
+      const int64_t u = mem[i];
+      if (rs[u] > 0) { fa.push_back(k); fb.push_back(i); fc.push_back(rs[u]); }
+      if (rt[u] > 0) { fa.push_back(i); fb.push_back(k + 1); fc.push_back(rt[u]); }
+    }
+    FlowGraph F = flow_graph(k + 2, fa, fb, fc);
+    std::vector<uint8_t> ls;
+    const i128 f = max_flow(F, k, k + 1, ls);
+    for (int64_t i = 0; i < k; i++) side[mem[i]] = ls[i];
+    return f;
+  };
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nth = (int)std::min<int64_t>({(int64_t)std::min(hw, 16u), ncomp, nc / 4096 + 1});
+  std::vector<i128> part(nth, 0);
+  std::atomic<int64_t> next{0};
+  auto worker = [&](int tid) {
+    for (int64_t q; (q = next.fetch_add(1)) < ncomp;) part[tid] += solve(order[q]);
+  };
+  std::vector<std::thread> pool;
+  for (int tid = 1; tid < nth; tid++) pool.emplace_back(worker, tid);
+  worker(0);
+  for (auto &th : pool) th.join();
+  for (const i128 f : part) flow += f;
+  return flow;
 }
 
 irls_status check_options(const irls_options &o, std::string &err) {
