@@ -202,6 +202,19 @@ irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, 
 irls_status irls_mincut_update_capacities(irls_mincut_t h, int64_t m, const int64_t *edge_u,
                                           const int64_t *edge_v, const double *cap);
 
+/* Cheeger-type bracket of the minimum cut value (Section 2.3, the
+ * Cheeger-type inequality phi^2/2 <= lambda_2 <= 2 phi of the pencil (L, D)
+ * with D = C at s and t).  With C = 2 * (sum of all capacities) and E01 the
+ * energy x^T L x of round 0 (W = C, x_s = 1, x_t = 0), lambda_2 = 2 E01 / C
+ * and phi = mu* / C, so
+ *   E01 <= mu* <= 2 sqrt(C E01):  *lower = E01, *upper = 2 sqrt(C E01).
+ * E01 comes from the round-0 CG solve (to cg_rtol) of the last
+ * irls_mincut_solve (or solve_range with start 0) with init == 0; it depends
+ * on the graph only, so it stays valid until irls_mincut_update_capacities.
+ * Errors: IRLS_ERR_NOT_SOLVED without such a solve; IRLS_ERR_OPTIONS for a
+ * batch handle. */
+irls_status irls_mincut_cheeger_bracket(irls_mincut_t h, double *lower, double *upper);
+
 /* Copy the current potentials (host; x_s = 1, x_t = 0): n doubles, or for a
  * batch handle sum(n_g) doubles laid out like node_off. */
 irls_status irls_mincut_potentials(irls_mincut_t h, double *x);

@@ -73,6 +73,7 @@ def lib():
         L.irls_mincut_cut.argtypes = [H, PU8, PF64, P64]
         L.irls_mincut_cut_two_level.argtypes = [H, PU8, PF64, C.POINTER(TwoLevelInfo)]
         L.irls_mincut_update_capacities.argtypes = [H, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.irls_mincut_cheeger_bracket.argtypes = [H, PF64, PF64]
         L.irls_mincut_potentials.argtypes = [H, PF64]
         L.irls_mincut_set_potentials.argtypes = [H, C.c_void_p]
         L.irls_mincut_info.argtypes = [H, P64, P64, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -87,7 +88,8 @@ def lib():
                                                P64, P64, C.POINTER(Options), C.c_void_p]
         L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
         L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
-        for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "update_capacities", "potentials",
+        for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "update_capacities",
+                  "cheeger_bracket", "potentials",
                   "set_potentials",
                   "info", "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
@@ -219,6 +221,14 @@ class MinCut:
         rc = lib().irls_mincut_update_capacities(self.h, m, pu, pv, pc)
         if rc != OK:
             raise self._err(rc)
+
+    def cheeger_bracket(self):
+        """irls_mincut_cheeger_bracket: (lower, upper) bounds on the minimum cut."""
+        lo, hi = C.c_double(0), C.c_double(0)
+        rc = lib().irls_mincut_cheeger_bracket(self.h, C.byref(lo), C.byref(hi))
+        if rc != OK:
+            raise self._err(rc)
+        return lo.value, hi.value
 
     def cut_two_level(self):
         """Two-level rounding (irls_mincut_cut_two_level). Returns (in_S bool [n],

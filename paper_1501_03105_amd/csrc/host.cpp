@@ -447,6 +447,16 @@ i128 coarse_min_cut(int64_t nc, const std::vector<int32_t> &eu, const std::vecto
   return flow;
 }
 
+// C = 2 * (sum of all merged capacities): interior edges are stored in both
+// rows of the CSR, terminal edges once per node, and the s-t edge once.
+double total_capacity2(const HostGraph &g) {
+  double c = 0.0;
+  for (double x : g.ccap) c += x;
+  for (double x : g.cs) c += 2.0 * x;
+  for (double x : g.ct) c += 2.0 * x;
+  return c + 2.0 * g.cst;
+}
+
 irls_status check_options(const irls_options &o, std::string &err) {
   if (o.struct_size != (int32_t)sizeof(irls_options)) { err = "irls_options.struct_size mismatch"; return IRLS_ERR_OPTIONS; }
   if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
@@ -559,6 +569,10 @@ struct irls_mincut_s {
   hipStream_t stream = nullptr;
   std::string err;
   bool solved = false;
+  // Cheeger-type bracket: C = 2 * (total capacity), and the round-0 energy
+  // E01 of the last solve whose round 0 used W = C
+  double ctot = 0.0, e01 = 0.0;
+  bool e01_valid = false;
   bool batch = false;
   GraphDev g;
   i128 D0 = 0;
@@ -1086,6 +1100,7 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
     g.cmax = hg.cmax;
     g.no_source_edges = hg.no_source_edges;
     h->D0 = hg.D0;
+    h->ctot = total_capacity2(hg);
     h->solver = o.solver ? o.solver
                          : ((o.precision == 0 && o.precond == 0 && hg.nt <= kResidentMaxRows) ? 2 : 1);
     if (h->solver == 2 && o.format == 2) {
@@ -1195,13 +1210,33 @@ irls_status solve_impl(irls_mincut_t h, int start, const double *x0, double eps_
 
 extern "C" {
 
+// After a solve from round 0 with init 0: round 0's energy E01 = x^T L x at
+// W = C, for the Cheeger-type bracket.  It depends on the graph alone, so it
+// stays valid until the capacities change.
+irls_status keep_round0_energy(irls_mincut_t h, int32_t start) {
+  if (start != 0 || h->opt.init != 0) return IRLS_OK;
+  if (h->g.nt == 0) {
+    h->e01 = h->g.cst;                                 // only the s-t edge carries flow
+  } else {
+    irls_round_stats r0;
+    HIPCHK(h, hipMemcpy(&r0, h->dstats, sizeof(r0), hipMemcpyDeviceToHost), "readback");
+    h->e01 = r0.flow;
+  }
+  h->e01_valid = true;
+  return IRLS_OK;
+}
+
 irls_status irls_mincut_solve(irls_mincut_t h, const double *x0, irls_round_stats *stats) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (h->batch) { h->err = "use irls_mincut_solve_batch for a batch handle"; return IRLS_ERR_OPTIONS; }
   try {
     h->solved = false;
     irls_status rc = solve_impl(h, 0, x0, -1.0, h->opt.rounds, stats);
-    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) h->solved = true;
+    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) {
+      h->solved = true;
+      irls_status r2 = keep_round0_energy(h, 0);
+      if (r2 != IRLS_OK) return r2;
+    }
     return rc;
   } catch (...) {
     h->err = "unexpected host exception";
@@ -1221,7 +1256,11 @@ irls_status irls_mincut_solve_range(irls_mincut_t h, int32_t start, const double
   try {
     h->solved = false;
     irls_status rc = solve_impl(h, start, x0, eps_first, rounds, stats);
-    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) h->solved = true;
+    if (rc == IRLS_OK || rc == IRLS_WARN_CG_MAXIT) {
+      h->solved = true;
+      irls_status r2 = keep_round0_energy(h, start);
+      if (r2 != IRLS_OK) return r2;
+    }
     return rc;
   } catch (...) {
     h->err = "unexpected host exception";
@@ -1475,6 +1514,8 @@ irls_status irls_mincut_update_capacities(irls_mincut_t h, int64_t m, const int6
     g.fx_k = hg.fx_k;
     g.no_source_edges = hg.no_source_edges;
     h->D0 = hg.D0;
+    h->ctot = total_capacity2(hg);
+    h->e01_valid = false;
     if (h->solver == 2) {
       rc = upload_res_record(h);
       if (rc != IRLS_OK) return rc;
@@ -1487,6 +1528,19 @@ irls_status irls_mincut_update_capacities(irls_mincut_t h, int64_t m, const int6
     h->err = "unexpected host exception";
     return IRLS_ERR_DEVICE;
   }
+}
+
+irls_status irls_mincut_cheeger_bracket(irls_mincut_t h, double *lower, double *upper) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!lower || !upper) { h->err = "lower and upper must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch) { h->err = "not available for a batch handle"; return IRLS_ERR_OPTIONS; }
+  if (!h->e01_valid) {
+    h->err = "needs a solve from round 0 with init 0 (round 0 at W = C) since the capacities were set";
+    return IRLS_ERR_NOT_SOLVED;
+  }
+  *lower = h->e01;
+  *upper = 2.0 * std::sqrt(h->ctot * h->e01);
+  return IRLS_OK;
 }
 
 irls_status irls_mincut_potentials(irls_mincut_t h, double *x) {

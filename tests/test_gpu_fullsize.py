@@ -38,6 +38,7 @@ def test_fullsize_sweep_and_invariants(P, oracle_mod, seg128):
         x = mc.potentials()
         inS, val, k = mc.cut()
         S2, val2, info2 = mc.cut_two_level()
+        lo, hi = mc.cheeger_bracket()
     assert rc == P.OK
     So, vo, ko, _ = oracle_mod.sweep(g, x)
     say(f"128^3: cut {val!r} k {k}; oracle sweep of the same x {vo!r} k {ko}")
@@ -69,6 +70,9 @@ def test_fullsize_sweep_and_invariants(P, oracle_mod, seg128):
     assert val2 == oracle_mod.cut_value(g, S2)
     assert val2 >= mu * (1 - 1e-12) and val2 <= val
     assert info2["n_sc"] < g.n // 10
+    # the Cheeger-type bracket from round 0
+    say(f"128^3: Cheeger-type bracket [{lo!r}, {hi!r}] around mu* {mu!r}")
+    assert lo <= mu and mu <= hi
 
 
 @pytest.mark.parametrize("l", [1, 25])
