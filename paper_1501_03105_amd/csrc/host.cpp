@@ -6,15 +6,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <limits>
 #include <new>
 #include <numeric>
 #include <string>
-#include <vector>
-#include <atomic>
+#include <system_error>
 #include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -436,13 +438,27 @@ i128 coarse_min_cut(int64_t nc, const std::vector<int32_t> &eu, const std::vecto
   const int nth = (int)std::min<int64_t>({(int64_t)std::min(hw, 16u), ncomp, nc / 4096 + 1});
   std::vector<i128> part(nth, 0);
   std::atomic<int64_t> next{0};
+  // an exception in a worker (an allocation failure) stops the others from
+  // taking more components and is rethrown here, after every thread joined
+  std::vector<std::exception_ptr> errs(nth);
   auto worker = [&](int tid) {
-    for (int64_t q; (q = next.fetch_add(1)) < ncomp;) part[tid] += solve(order[q]);
+    try {
+      for (int64_t q; (q = next.fetch_add(1)) < ncomp;) part[tid] += solve(order[q]);
+    } catch (...) {
+      errs[tid] = std::current_exception();
+      next.store(ncomp);
+    }
   };
   std::vector<std::thread> pool;
-  for (int tid = 1; tid < nth; tid++) pool.emplace_back(worker, tid);
+  try {
+    for (int tid = 1; tid < nth; tid++) pool.emplace_back(worker, tid);
+  } catch (const std::system_error &) {
+    // fewer threads than asked for: the running ones take the remaining work
+  }
   worker(0);
   for (auto &th : pool) th.join();
+  for (const std::exception_ptr &e : errs)
+    if (e) std::rethrow_exception(e);
   for (const i128 f : part) flow += f;
   return flow;
 }
