@@ -149,6 +149,12 @@ def bench_batch(args, spec, opts, desc):
     mb = P.MinCutBatch(gs, stream=torch.cuda.current_stream(), **opts)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
+    # rows per wavefront: measured per row-length bin on short solves (setup,
+    # not part of a step)
+    t0 = time.perf_counter()
+    lanes = mb.autotune(rounds=2, reps=2)
+    t_tune = time.perf_counter() - t0
+    print(f"[bench] autotuned lanes per row by bin {lanes} in {t_tune:.1f}s", file=sys.stderr, flush=True)
 
     def step():
         rc, st = mb.solve()
@@ -167,6 +173,16 @@ def bench_batch(args, spec, opts, desc):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     iters = [sum(r["cg_iters"] for r in s) for s in st]
+    # the same steps with the default table, for the autotuner's gain
+    default_lanes = [min(2 << b, 64) for b in range(len(lanes))]
+    mb.set_row_lanes(default_lanes)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, vals_def = step()
+    torch.cuda.synchronize()
+    dt_def = time.perf_counter() - t0
     mb.close()
     # The plain FP64 GPU path (one multi-workgroup solve per graph, one graph
     # after another) on every 16th graph in size order, each after one untimed
@@ -201,6 +217,11 @@ def bench_batch(args, spec, opts, desc):
                    "interior_edges": int(sum(g.meta["interior"] for g in gs)),
                    "cg_iters_total": int(sum(iters)), "cg_iters_max_graph": int(max(iters)),
                    "setup_s": round(t_setup, 3),
+                   "autotune": {"lanes_per_row_by_bin": lanes, "seconds": round(t_tune, 3),
+                                "default_lanes": default_lanes,
+                                "default_cuts_per_s": round(len(gs) * args.steps / dt_def, 3),
+                                "max_rel_cut_difference_from_default": float(
+                                    np.max(np.abs(vals - vals_def) / np.maximum(np.abs(vals_def), 1e-300)))},
                    "plain_fp64_one_by_one": {
                        "cuts_per_s": round(plain_rate, 3),
                        "speedup_of_batch": round(rate / plain_rate, 2),

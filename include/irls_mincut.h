@@ -285,6 +285,36 @@ irls_status irls_mincut_solve_batch(irls_mincut_t h, irls_round_stats *stats);
  * node_off; cut_values NULL or G doubles. */
 irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, double *cut_values);
 
+/* Rows per wavefront of the resident solver (a batch handle, or a single
+ * graph with solver 2).  Not in the paper, which has no GPU kernels: a tuning
+ * knob of how the solver's per-row sums and SpMV map rows to lanes.  Rows of
+ * at most 128 entries are binned by length: bin b (0..5) holds rows of at
+ * most 2^(b+1) entries (bin 5: 33 to 128).  lanes[b] lanes walk each row of
+ * bin b, each lane taking every lanes[b]-th entry; 64 / lanes[b] rows share
+ * a wavefront.  The default is lanes[b] = min(2^(b+1), 64), one entry per
+ * lane (bin 5: two).  Longer rows are always cut into 64-entry chunks.
+ * The lanes change the order of each row's summation, not the arithmetic:
+ * results agree to rounding, and are bit-identical across runs for one table.
+ *
+ * irls_mincut_set_row_lanes sets the table:
+ *   lanes   6 int32 (host): each a power of two from 1 to min(2^(b+1), 64).
+ * irls_mincut_autotune measures it: one sweep of coordinate descent over the
+ * bins that hold rows, each trying its default and a half, a quarter and an
+ * eighth of it (not below 1), timing `reps` resident solves of rounds
+ * 0..`rounds` per candidate (the minimum counts) with HIP events; a bin
+ * changes only for a gain of at least 2 % over its current choice.  The
+ * timing solves start as irls_mincut_solve would; the potentials in place
+ * before the call are restored after it, so the handle's state is unchanged
+ * but for the table.  The next solve runs (and a batch re-captures its HIP
+ * graph) with the chosen table.
+ *   rounds  0 .. the handle's rounds; reps >= 1
+ *   lanes   NULL or 6 int32 (host): the table chosen
+ * Errors (both): IRLS_ERR_OPTIONS for a handle that does not use the
+ * resident solver or for values out of range; autotune with init 2 before
+ * the potentials are set: IRLS_ERR_NOT_SOLVED. */
+irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes);
+irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes);
+
 #ifdef __cplusplus
 }
 #endif

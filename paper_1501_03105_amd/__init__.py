@@ -88,10 +88,14 @@ def lib():
                                                P64, P64, C.POINTER(Options), C.c_void_p]
         L.irls_mincut_solve_batch.argtypes = [H, C.POINTER(RoundStats)]
         L.irls_mincut_cut_batch.argtypes = [H, PU8, PF64]
+        P32 = C.POINTER(C.c_int32)
+        L.irls_mincut_set_row_lanes.argtypes = [H, P32]
+        L.irls_mincut_autotune.argtypes = [H, C.c_int32, C.c_int32, P32]
         for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "update_capacities",
                   "cheeger_bracket", "potentials",
                   "set_potentials",
-                  "info", "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch"):
+                  "info", "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch",
+                  "set_row_lanes", "autotune"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
         PF32 = C.POINTER(C.c_float)
         L.irls_gnn_create.argtypes = [C.POINTER(H), C.c_int32, C.c_int32, C.c_uint64, C.c_void_p]
@@ -156,7 +160,29 @@ def _stats_list(arr):
     return [{f: getattr(r, f) for f in STAT_FIELDS} for r in arr]
 
 
-class MinCut:
+ROW_LANE_BINS = 6
+
+
+class _RowLanes:
+    """Rows per wavefront of the resident solver (irls_mincut_set_row_lanes,
+    irls_mincut_autotune); lanes[b] = lanes per row of length bin b."""
+
+    def set_row_lanes(self, lanes):
+        arr = (C.c_int32 * ROW_LANE_BINS)(*[int(x) for x in lanes])
+        rc = lib().irls_mincut_set_row_lanes(self.h, arr)
+        if rc != OK:
+            raise self._err(rc)
+
+    def autotune(self, rounds=1, reps=2):
+        """Times candidate tables and keeps the fastest; returns it."""
+        arr = (C.c_int32 * ROW_LANE_BINS)()
+        rc = lib().irls_mincut_autotune(self.h, rounds, reps, arr)
+        if rc != OK:
+            raise self._err(rc)
+        return list(arr)
+
+
+class MinCut(_RowLanes):
     """One graph on the GPU: irls_mincut_create / _solve / _cut / ... / _destroy."""
 
     def __init__(self, n, eu, ev, cap, s, t, stream=None, **opts):
@@ -306,7 +332,7 @@ class MinCut:
         self.close()
 
 
-class MinCutBatch:
+class MinCutBatch(_RowLanes):
     """Many independent graphs solved together: irls_mincut_create_batch /
     _solve_batch / _cut_batch.  `graphs` are objects with n, eu, ev, cap, s, t
     (local node ids)."""

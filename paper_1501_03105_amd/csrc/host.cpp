@@ -616,6 +616,7 @@ struct irls_mincut_s {
   int32_t *hv_brow = nullptr, *hv_bbeg = nullptr, *hv_bend = nullptr;
   double *hv_part = nullptr;
   BatchGraph res_graph;             // single-graph handles with solver 2
+  uint32_t lane_code = kDefaultLaneCode;   // resident solver: lanes per light row by bin
   Scalars *pinned = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
   // resident solver (one graph, or every graph of a batch)
@@ -859,7 +860,7 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
   return result;
 }
 
-irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
+ResidentArgs resident_args(irls_mincut_t h) {
   const irls_options &o = h->opt;
   ResidentArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -899,6 +900,13 @@ irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
   a.warm = o.warm_start;
   a.rtol = o.cg_rtol;
   a.maxit = o.cg_maxit;
+  a.lane_code = h->lane_code;
+  return a;
+}
+
+irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
+  const irls_options &o = h->opt;
+  const ResidentArgs a = resident_args(h);
   const int64_t nrec = (int64_t)h->G * (o.rounds + 1);
   if (h->batch) {
     // the whole batched solve (queue reset + one persistent launch running
@@ -941,6 +949,42 @@ irls_status solve_resident(irls_mincut_t h, irls_round_stats *stats) {
 
 // The graph record of a single-graph resident handle (heavy-row counts and
 // lanes from create; the capacity-dependent fields from the graph).
+// Light rows of the resident solver's graphs in each length bin.
+void resident_bin_rows(irls_mincut_t h, int64_t (&rows)[kBins]) {
+  for (int b = 0; b < kBins; b++) rows[b] = 0;
+  auto add = [&](const BatchGraph &B) {
+    for (int b = 0; b < kBins; b++) rows[b] += B.bin[b + 1] - B.bin[b];
+  };
+  if (h->batch) for (const BatchGraph &B : h->hgraphs) add(B);
+  else add(h->res_graph);
+}
+
+uint32_t lane_code_with(uint32_t code, int b, int lg) {
+  return (code & ~(7u << (3 * b))) | ((uint32_t)lg << (3 * b));
+}
+
+// One resident solve of `rounds` rounds, launched directly (not from the
+// captured graph) under the given lane code and timed with the two events on
+// the handle's stream.  It starts as a solve does: from x = 0.5 with init 1,
+// else from the saved potentials (which round 0 ignores with init 0).
+irls_status time_resident(irls_mincut_t h, int32_t rounds, uint32_t code, hipEvent_t e0, hipEvent_t e1,
+                          float *ms) {
+  ResidentArgs a = resident_args(h);
+  a.rounds = rounds;
+  a.lane_code = code;
+  const int64_t nrec = (int64_t)h->G * (rounds + 1);
+  if (h->opt.init == 1) HIPCHK(h, launch_fill(h->v, h->g.nt, 0.5, h->stream), "fill");
+  else HIPCHK(h, hipMemcpyAsync(h->v, h->vsave, h->g.nt * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+              "restore");
+  HIPCHK(h, hipEventRecord(e0, h->stream), "event");
+  HIPCHK(h, launch_resident_reset(h->rnext, h->dstats, nrec, h->stream), "reset");
+  HIPCHK(h, launch_resident(a, h->grid_res, 1024, h->stream), "resident solve");
+  HIPCHK(h, hipEventRecord(e1, h->stream), "event");
+  HIPCHK(h, hipEventSynchronize(e1), "sync");
+  HIPCHK(h, hipEventElapsedTime(ms, e0, e1), "event time");
+  return IRLS_OK;
+}
+
 irls_status upload_res_record(irls_mincut_t h) {
   BatchGraph rg = h->res_graph;
   rg.node0 = 0;
@@ -1677,6 +1721,108 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
     HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
     *avg_ms = (double)ms / reps;
     return IRLS_OK;
+  } catch (...) {
+    h->err = "unexpected host exception";
+    return IRLS_ERR_DEVICE;
+  }
+}
+
+irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!lanes) { h->err = "lanes must not be NULL"; return IRLS_ERR_NULL; }
+  if (!h->batch && h->solver != 2) { h->err = "row lanes apply to the resident solver (solver 2 or a batch)"; return IRLS_ERR_OPTIONS; }
+  uint32_t code = 0;
+  for (int b = 0; b < kBins; b++) {
+    int lg = 0;
+    while (lg < 7 && (1 << lg) < lanes[b]) lg++;
+    if (lanes[b] < 1 || (1 << lg) != lanes[b] || lg > bin_default_lg(b)) {
+      h->err = "lanes[" + std::to_string(b) + "] must be a power of two from 1 to " +
+               std::to_string(1 << bin_default_lg(b));
+      return IRLS_ERR_OPTIONS;
+    }
+    code = lane_code_with(code, b, lg);
+  }
+  if (code != h->lane_code) {
+    h->lane_code = code;
+    if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }   // captured with the old code
+  }
+  return IRLS_OK;
+}
+
+irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (!h->batch && h->solver != 2) { h->err = "autotuning applies to the resident solver (solver 2 or a batch)"; return IRLS_ERR_OPTIONS; }
+  if (rounds < 0 || rounds > h->opt.rounds || reps < 1) {
+    h->err = "rounds must lie in [0, the handle's rounds] and reps >= 1";
+    return IRLS_ERR_OPTIONS;
+  }
+  if (h->opt.init == 2 && !h->solved) {
+    h->err = "init = 2 starts from the potentials: set them (or solve) first";
+    return IRLS_ERR_NOT_SOLVED;
+  }
+  const bool was_solved = h->solved;
+  h->solved = false;                   // until the potentials are back in place
+  try {
+    if (h->g.nt > 0) {
+      if (!h->vsave) HIPCHK(h, h->dalloc(&h->vsave, h->g.nt), "alloc");
+      HIPCHK(h, hipMemcpyAsync(h->vsave, h->v, h->g.nt * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+             "save");
+      struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+          for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+        }
+      } ev;
+      for (hipEvent_t &e : ev.e) HIPCHK(h, hipEventCreate(&e), "event");
+      int64_t rows[kBins];
+      resident_bin_rows(h, rows);
+      uint32_t code = h->lane_code;
+      auto best_of = [&](uint32_t c, float &t) -> irls_status {
+        t = std::numeric_limits<float>::infinity();
+        for (int r = 0; r < reps; r++) {
+          float ms = 0.0f;
+          irls_status rc = time_resident(h, rounds, c, ev.e[0], ev.e[1], &ms);
+          if (rc != IRLS_OK) return rc;
+          t = std::min(t, ms);
+        }
+        return IRLS_OK;
+      };
+      // one sweep of coordinate descent over the bins that hold rows: the
+      // lanes per row of bin b from its default down to an eighth of it; a
+      // change must gain 2 % over the bin's current choice
+      for (int b = 0; b < kBins; b++) {
+        if (rows[b] == 0) continue;
+        const int cur = (int)((code >> (3 * b)) & 7u);
+        float tcur;
+        irls_status rc = best_of(code, tcur);
+        if (rc != IRLS_OK) return rc;
+        int best = cur;
+        float tbest = tcur;
+        for (int lg = bin_default_lg(b); lg >= 0 && lg >= bin_default_lg(b) - 3; lg--) {
+          if (lg == cur) continue;
+          float t;
+          rc = best_of(lane_code_with(code, b, lg), t);
+          if (rc != IRLS_OK) return rc;
+          if (t < 0.98f * tcur && t < tbest) { best = lg; tbest = t; }
+        }
+        code = lane_code_with(code, b, best);
+      }
+      HIPCHK(h, hipMemcpyAsync(h->v, h->vsave, h->g.nt * sizeof(double), hipMemcpyDeviceToDevice, h->stream),
+             "restore");
+      HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+      if (code != h->lane_code) {
+        h->lane_code = code;
+        if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+      }
+    }
+    h->solved = was_solved;
+    if (lanes)
+      for (int b = 0; b < kBins; b++) lanes[b] = 1 << ((h->lane_code >> (3 * b)) & 7u);
+    return IRLS_OK;
+  } catch (const std::bad_alloc &) {
+    h->err = "host allocation failed";
+    return IRLS_ERR_OOM;
   } catch (...) {
     h->err = "unexpected host exception";
     return IRLS_ERR_DEVICE;

@@ -189,9 +189,14 @@ constexpr int32_t kHeavyRow = 128;
 constexpr int32_t kChunk = 64;
 constexpr int kChunkQ = 4;        // partial sums kept per chunk (the most any pass needs)
 // Light rows are binned by length: bin b holds rows of at most 2^(b+1)
-// entries (bin 5: at most 128), walked by groups of min(2^(b+1), 64) lanes,
-// so the lanes of a wavefront finish their rows together.
+// entries (bin 5: at most 128).  By default a group of min(2^(b+1), 64)
+// lanes walks each row of bin b, so the lanes of a wavefront finish their
+// rows together; the lane code (3 bits per bin: log2 of the lanes) may set
+// fewer lanes per row, each then taking several entries.
 constexpr int kBins = 6;
+constexpr int bin_default_lg(int b) { return b + 1 < 6 ? b + 1 : 6; }
+constexpr uint32_t kDefaultLaneCode = (1u << 0) | (2u << 3) | (3u << 6) | (4u << 9) | (5u << 12) | (6u << 15);
+static_assert(kBins == 6, "the default lane code lists six bins");
 
 struct BatchGraph {
   int64_t node0;                  // first row in the concatenated non-terminal arrays
@@ -235,6 +240,7 @@ struct ResidentArgs {
   int32_t form, init, warm;
   double rtol;
   int64_t maxit;
+  uint32_t lane_code;             // lanes per light row by bin (see kBins)
 };
 hipError_t launch_resident(const ResidentArgs &a, int grid, int block, hipStream_t st);
 hipError_t launch_resident_reset(unsigned *next_graph, irls_round_stats *st, int64_t nrec, hipStream_t s);

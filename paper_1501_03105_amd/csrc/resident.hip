@@ -25,12 +25,15 @@ struct ResRows {
   const int32_t *bin;                 // [kBins + 1] bin boundaries (the graph's record)
   const int32_t *crow, *cbeg, *cend, *hrow, *hc0, *hc1;
   int32_t nchunks, nheavy;
+  uint32_t lane_code;                 // log2 of the lanes per light row of bin b at bits 3b..3b+2
   double *cpart;
 };
 
-// Lanes per row in bin b and the entries one lane takes at most.
-__device__ __forceinline__ constexpr int bin_lanes(int b) { return (2 << b) < 64 ? (2 << b) : 64; }
-__device__ __forceinline__ constexpr int bin_steps(int b) { return b == kBins - 1 ? kHeavyRow / 64 : 1; }
+// Lanes per row of bin b are 2^lg (lg from the lane code, uniform across the
+// workgroup); a row of the bin has at most bin_max(b) entries, so a lane
+// takes at most bin_max(b) / 2^lg of them.
+__device__ __forceinline__ int bin_lg(const ResRows &R, int b) { return (int)((R.lane_code >> (3 * b)) & 7u); }
+__device__ __forceinline__ constexpr int bin_max(int b) { return b == kBins - 1 ? kHeavyRow : (2 << b); }
 
 // Heavy rows of a pass: their 64-entry chunks spread over the wavefronts,
 // each reduced across the wavefront, then after a barrier one wavefront per
@@ -73,7 +76,7 @@ __device__ __forceinline__ void heavy_pass(const ResRows &R, F f, Fin fin) {
 
 // One pass of per-row sums over the CSR entries: f(i, e, s) adds entry e of
 // row i into s[0..NQ); fin(i, s) receives each row's totals once, on one
-// lane.  Light rows go by length bin, a group of bin_lanes(b) lanes per row;
+// lane.  Light rows go by length bin, a group of 2^bin_lg(b) lanes per row;
 // heavy rows by chunks.  Deterministic: no atomics.  Every thread of the
 // workgroup must call it; the caller puts a barrier between two passes.
 template <int NQ, typename F, typename Fin>
@@ -81,7 +84,7 @@ __device__ __forceinline__ void rows_pass(const ResRows &R, F f, Fin fin) {
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
 #pragma unroll 1
   for (int b = 0; b < kBins; b++) {
-    const int L = bin_lanes(b), rpw = 64 / L, sub = lane / L, lid = lane % L;
+    const int lg = bin_lg(R, b), L = 1 << lg, rpw = 64 >> lg, sub = lane >> lg, lid = lane & (L - 1);
     const int32_t hi = R.bin[b + 1];
 #pragma unroll 1
     for (int32_t j0 = R.bin[b] + wid * rpw; j0 < hi; j0 += kResWaves * rpw) {
@@ -120,7 +123,8 @@ __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, con
   constexpr int U = kSpmvRows;
 #pragma unroll 1
   for (int b = 0; b < kBins; b++) {
-    const int L = bin_lanes(b), rpw = 64 / L, sub = lane / L, lid = lane % L;
+    const int lg = bin_lg(R, b), L = 1 << lg, rpw = 64 >> lg, sub = lane >> lg, lid = lane & (L - 1);
+    const int steps = R.nnz > 0 ? bin_max(b) >> lg : 0;           // entry 0 must exist
     const int32_t hi = R.bin[b + 1];
     const int32_t step = kResWaves * rpw;
     // The next row groups' (row, entry range) triples are loaded one pass
@@ -148,7 +152,7 @@ __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, con
 #pragma unroll
       for (int u = 0; u < U; u++) acc[u] = 0.0;
 #pragma unroll 1
-      for (int t = 0; t < (R.nnz > 0 ? bin_steps(b) : 0); t++) {   // entry 0 must exist
+      for (int t = 0; t < steps; t++) {
         int32_t c[U];
         double wv[U], pv[U];
         bool ok[U];
@@ -268,6 +272,7 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
     R.hc1 = a.heavy_c1 + gr.heavy0;
     R.nchunks = gr.nchunks;
     R.nheavy = gr.nheavy;
+    R.lane_code = a.lane_code;
     R.cpart = a.chunk_part + gr.chunk0 * kChunkQ;
     double eps = a.eps0;
     for (int l = 0; l <= a.rounds; l++) {

@@ -75,6 +75,8 @@ def test_null_handle_calls(P):
     assert L.irls_mincut_cut_two_level(None, None, None, None) == P.ERR_NULL
     assert L.irls_mincut_update_capacities(None, 0, None, None, None) == P.ERR_NULL
     assert L.irls_mincut_cheeger_bracket(None, None, None) == P.ERR_NULL
+    assert L.irls_mincut_set_row_lanes(None, None) == P.ERR_NULL
+    assert L.irls_mincut_autotune(None, 1, 1, None) == P.ERR_NULL
     assert L.irls_mincut_potentials(None, None) == P.ERR_NULL
     L.irls_mincut_destroy(None)
     assert L.irls_mincut_last_error(None)

@@ -109,3 +109,95 @@ def test_batch_rmat512_fullsize(P, oracle_mod, rmat512):
     say(f"rmat512: potential error on the 6 smallest graphs {max(errs):.2e}; "
         f"total CG iterations {sum(r['cg_iters'] for s in st for r in s)}")
     assert max(errs) <= 1e-6
+
+
+def lane_bounds():
+    return [min(2 << b, 64) for b in range(6)]
+
+
+def check_against_oracle(P, oracle_mod, gs, mb):
+    rc, st = mb.solve()
+    xs = mb.potentials()
+    masks, vals = mb.cut()
+    assert rc == P.OK
+    for g, x, S, v, sg in zip(gs, xs, masks, vals, st):
+        xo, so, _ = oracle_mod.irls(g, **OPTS)
+        So, vo, _, _ = oracle_mod.sweep(g, xo)
+        assert max_pot_err(x, xo) <= 1e-7
+        assert v == vo and np.array_equal(S, So)
+        assert all(abs(a["cg_iters"] - b["cg_iters"]) <= max(3, 0.02 * b["cg_iters"])
+                   for a, b in zip(sg, so))
+    return np.concatenate(xs), vals
+
+
+@pytest.mark.parametrize("table", ["one lane per row", "half the default"])
+def test_batch_row_lanes_match_oracle(P, oracle_mod, table):
+    """Fewer lanes per row (each lane then takes several entries of a row)
+    only reorders each row's sums: the oracle bars hold, reruns are
+    bit-identical, and the captured graph is re-captured with the new table."""
+    gs = mixed_batch()
+    lanes = [1] * 6 if table == "one lane per row" else [max(1, L // 2) for L in lane_bounds()]
+    say(f"row lanes {lanes}")
+    with P.MinCutBatch(gs, **OPTS) as mb:
+        mb.solve()                                       # captured with the default table
+        x_def = np.concatenate(mb.potentials())
+        mb.set_row_lanes(lanes)
+        x1, v1 = check_against_oracle(P, oracle_mod, gs, mb)
+        x2, v2 = check_against_oracle(P, oracle_mod, gs, mb)
+        assert np.array_equal(x1, x2) and np.array_equal(v1, v2)
+        assert np.max(np.abs(x1 - x_def)) <= 1e-7
+        mb.set_row_lanes(lane_bounds())                  # back to the default: the same bits as before
+        mb.solve()
+        assert np.array_equal(np.concatenate(mb.potentials()), x_def)
+
+
+def test_batch_autotune(P, oracle_mod):
+    """The autotuner returns a valid table, leaves the potentials and the
+    solved state in place, and the next solve with its table meets the
+    oracle bars."""
+    gs = mixed_batch()
+    with P.MinCutBatch(gs, **OPTS) as mb:
+        mb.solve()
+        x0 = np.concatenate(mb.potentials())
+        _, v0 = mb.cut()
+        lanes = mb.autotune(rounds=2, reps=1)
+        say(f"autotuned row lanes {lanes}")
+        for L, hi in zip(lanes, lane_bounds()):
+            assert 1 <= L <= hi and L & (L - 1) == 0
+        assert np.array_equal(np.concatenate(mb.potentials()), x0)
+        _, v1 = mb.cut()
+        assert np.array_equal(v0, v1)
+        check_against_oracle(P, oracle_mod, gs, mb)
+
+
+def test_single_graph_resident_autotune(P, oracle_mod):
+    g = gen.rmat_flowimprove(2003, log2_lo=10.0, log2_hi=10.5)
+    with P.MinCut.from_graph(g, solver=2, **OPTS) as mc:
+        lanes = mc.autotune(rounds=1, reps=1)
+        for L, hi in zip(lanes, lane_bounds()):
+            assert 1 <= L <= hi and L & (L - 1) == 0
+        mc.set_row_lanes([1] * 6)
+        mc.solve()
+        x = mc.potentials()
+        _, v, _ = mc.cut()
+    xo, _, _ = oracle_mod.irls(g, **OPTS)
+    _, vo, _, _ = oracle_mod.sweep(g, xo)
+    assert max_pot_err(x, xo) <= 1e-7 and v == vo
+
+
+def test_row_lanes_errors(P):
+    g = gen.gnp(16, 0.3, seed=2)
+    with P.MinCutBatch([g]) as mb:
+        for bad in ([3, 4, 8, 16, 32, 64], [0, 4, 8, 16, 32, 64], [4, 4, 8, 16, 32, 64],
+                    [2, 4, 8, 16, 32, 128]):
+            with pytest.raises(P.IrlsError) as e:
+                mb.set_row_lanes(bad)
+            assert e.value.code == P.ERR_OPTIONS
+        for rounds, reps in ((-1, 1), (31, 1), (1, 0)):
+            with pytest.raises(P.IrlsError) as e:
+                mb.autotune(rounds, reps)
+            assert e.value.code == P.ERR_OPTIONS
+    with P.MinCut.from_graph(gen.grid2d(16, 16, seed=1), solver=1) as mc:
+        with pytest.raises(P.IrlsError) as e:
+            mc.autotune()
+        assert e.value.code == P.ERR_OPTIONS
