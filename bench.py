@@ -437,7 +437,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "n_nonterminal": info["n_nonterminal"],
                    "interior_edges": info["nnz_offdiag"] // 2, "format": info["format"],
-                   "solver": info["solver"], "cg_iters_per_cut": iters, "cut_value": val,
+                   "solver": info["solver"], "cg_iters_per_cut": iters,
+                   "cg_iters_per_round": [int(r["cg_iters"]) for r in st], "cut_value": val,
                    "setup_s": round(t_setup, 3), "two_level": two},
         "roofline": roof,
         "cpu_baseline": cpu,
