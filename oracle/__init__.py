@@ -29,7 +29,8 @@ class Round(C.Structure):
     _fields_ = [("eps", C.c_double), ("cg_iters", C.c_int64), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("s_eps", C.c_double), ("l1", C.c_double),
                 ("flow", C.c_double), ("flow_s", C.c_double), ("flow_t", C.c_double),
-                ("vmin", C.c_double), ("vmax", C.c_double), ("status", C.c_int32)]
+                ("vmin", C.c_double), ("vmax", C.c_double), ("status", C.c_int32),
+                ("lower_bound", C.c_double)]
 
 
 ROUND_FIELDS = [f for f, _ in Round._fields_]

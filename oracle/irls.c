@@ -226,6 +226,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
                         int form, double *q, orc_round *R) {
   int64_t nt = g->nt;
   double se = 0.0, l1 = 0.0, fl = 0.0, fs = 0.0, ft = 0.0;
+  double rho = 0.0;                                     /* max over edges of |w d| / c */
   double vmin = nt ? v[0] : 0.0, vmax = nt ? v[0] : 0.0;
   for (int64_t i = 0; i < nt; i++) {
     for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) {
@@ -234,6 +235,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
       se += form == 0 ? c * sqrt(d * d + eps_next) : sqrt((c * d) * (c * d) + eps_next);
       l1 += c * fabs(d);
       fl += S->w[a] * d * d;
+      if (S->w[a] * fabs(d) / c > rho) rho = S->w[a] * fabs(d) / c;
     }
     if (g->cs[i] > 0.0) {
       double c = g->cs[i], d = 1.0 - v[i];
@@ -241,6 +243,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
       l1 += c * fabs(d);
       fl += S->ws[i] * d * d;
       fs += S->ws[i] * d;
+      if (S->ws[i] * fabs(d) / c > rho) rho = S->ws[i] * fabs(d) / c;
     }
     if (g->ct[i] > 0.0) {
       double c = g->ct[i], d = v[i];
@@ -248,6 +251,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
       l1 += c * fabs(d);
       fl += S->wt[i] * d * d;
       ft += S->wt[i] * d;
+      if (S->wt[i] * fabs(d) / c > rho) rho = S->wt[i] * fabs(d) / c;
     }
     if (v[i] < vmin) vmin = v[i];
     if (v[i] > vmax) vmax = v[i];
@@ -259,8 +263,13 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
     fl += S->wst;
     fs += S->wst;
     ft += S->wst;
+    if (S->wst / c > rho) rho = S->wst / c;
   }
   R->s_eps = se; R->l1 = l1; R->flow = fl; R->flow_s = fs; R->flow_t = ft;
+  /* the electrical flow f_e = w_e d_e is conserved where the system is solved;
+     divided by max(1, rho) it respects every capacity, so its value bounds the
+     minimum cut from below (max-flow / min-cut duality) */
+  R->lower_bound = (fs < ft ? fs : ft) / (rho > 1.0 ? rho : 1.0);
   R->vmin = vmin; R->vmax = vmax;
   /* true residual of this round's system */
   if (nt > 0) {

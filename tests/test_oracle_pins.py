@@ -116,6 +116,51 @@ def test_path_every_round_matches_series_circuit(oracle_mod):
     assert val == min(caps)
 
 
+def test_path_lower_bound_by_hand(oracle_mod):
+    """The per-round lower bound on a path, by hand: a series circuit carries
+    one flow F = 1 / sum(1/g_j) on every edge, so rho = F / min(c) and the
+    bound F / max(1, rho) is min(F, min c) (the path's minimum cut is min c).
+    Round 0 (g = c) gives F < min c: the bound is the flow itself."""
+    caps = [0.9, 0.35, 0.8, 0.6, 0.25, 1.1, 0.7]
+    g = path_graph(caps)
+    k = len(caps) - 1
+    x, R, _ = oracle_mod.irls(g, rounds=0, cg_rtol=1e-14)
+    F0 = 1.0 / sum(1.0 / c for c in caps)
+    assert F0 < min(caps)
+    assert R[0]["lower_bound"] == pytest.approx(F0, rel=1e-12)
+    prev = x
+    eps = 0.1
+    for T in range(1, 12):
+        xT, R, _ = oracle_mod.irls(g, rounds=T, cg_rtol=1e-14)
+        pot = [1.0] + list(prev[:k]) + [0.0]
+        cond = [c / np.sqrt((pot[j] - pot[j + 1]) ** 2 + eps) for j, c in enumerate(caps)]
+        F = 1.0 / sum(1.0 / w for w in cond)
+        assert R[T]["lower_bound"] == pytest.approx(min(F, min(caps)), rel=1e-9), T
+        prev = xT
+        eps *= 0.5
+
+
+def test_lower_bound_below_min_cut(oracle_mod):
+    """Every round's lower bound lies below the exhaustive minimum cut (its
+    flow, scaled to respect every capacity, is feasible), round 0's equals
+    its flow value E0 (there |x_u - x_v| <= 1, so rho <= 1), ||CBx||_1 lies
+    above the minimum cut, and the bound closes in on it."""
+    for seed in range(1, 51):
+        g = gen.gnp(16, 0.3, seed=seed)
+        _, R, _ = oracle_mod.irls(g, rounds=20, cg_rtol=1e-12)
+        _, mu, _ = oracle_mod.bruteforce(g)
+        assert R[0]["lower_bound"] == pytest.approx(R[0]["flow"], rel=1e-12)
+        for r in R:
+            assert r["lower_bound"] <= mu * (1 + 1e-9)
+            assert mu <= r["l1"] * (1 + 1e-12)
+        assert R[-1]["lower_bound"] >= 0.99 * mu
+    for g in (gen.grid2d(40, 30, seed=5), gen.grid3d_seg(12, seed=2)):
+        _, R, _ = oracle_mod.irls(g, rounds=30, cg_rtol=1e-10)
+        _, mu = oracle_mod.maxflow(g)
+        assert all(r["lower_bound"] <= mu * (1 + 1e-9) for r in R)
+        assert R[-1]["lower_bound"] >= 0.95 * mu
+
+
 def test_uniform_grid_reduces_to_path(oracle_mod):
     """Uniform interior capacity 1 on an nx-by-ny grid with equal terminal
     capacity q on the left and right columns: by symmetry the round-0
