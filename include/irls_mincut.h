@@ -72,8 +72,8 @@ typedef struct {
   int32_t solver;             /* 0 auto; 1 multi-workgroup kernels; 2 one resident workgroup */
   int32_t chunk;              /* CG iterations launched between host checks, 0 = auto */
   int32_t inputs_on_device;   /* 1: edge arrays and x0 are device pointers */
-  int32_t rows_per_wave;      /* CSR SpMV rows per 64-lane wavefront: 0 autotune, else
-                                 1,2,4,...,64 */
+  int32_t rows_per_wave;      /* CSR SpMV rows per 64-lane wavefront: 0 auto (from the
+                                 average row length), else 1,2,4,...,64 */
   int32_t precond;            /* 0: Jacobi, M = diag(L~) (default);
                                  1: block-Jacobi (Section 3.1), M = the principal submatrices
                                     of L~ over blocks of block_size consecutive rows, each
@@ -88,6 +88,12 @@ typedef struct {
                                  D^-1/2 L~ D^-1/2 -- in exact arithmetic the same iterates as
                                  Jacobi PCG (Section 3.1), but the SpMV reads no diagonal;
                                  1: always the z = D^-1 r form */
+  double  stop_gap;           /* 0 (default): run every round.  > 0: stop after the first
+                                 round whose certified gap l1 - lower_bound (see
+                                 irls_round_stats) is at most stop_gap * l1; then
+                                 mu* <= sweep cut <= l1 <= lower_bound / (1 - stop_gap).
+                                 Rounds after the stop are not run: their records hold
+                                 eps = 0 and cg_iters = 0 */
 } irls_options;
 
 /* Per-round record (round 0 first). */
@@ -103,6 +109,15 @@ typedef struct {
   double  flow_s, flow_t;     /* flow leaving s / entering t */
   double  vmin, vmax;         /* range of the non-terminal potentials (Proposition 2) */
   int32_t status;             /* irls_status of this round's CG */
+  double  lower_bound;        /* min(flow_s, flow_t) / max(1, rho), rho = the largest
+                                 g_e |x_u - x_v| / c_e over all edges: this round's
+                                 electrical flow (Proposition 3) scaled to respect every
+                                 capacity.  Where the round's system is solved (up to its
+                                 residual) the flow is conserved, so by max-flow / min-cut
+                                 duality lower_bound <= mu*; with l1 >= mu* the pair
+                                 brackets the minimum cut.  In round 0 (g = c,
+                                 |x_u - x_v| <= 1) it is the flow value E0 of the
+                                 Cheeger-type bracket. */
 } irls_round_stats;
 
 void irls_options_default(irls_options *o);

@@ -26,14 +26,15 @@ class Options(C.Structure):
                 ("fp64_weights_below_eps", C.c_double), ("format", C.c_int32),
                 ("solver", C.c_int32), ("chunk", C.c_int32), ("inputs_on_device", C.c_int32),
                 ("rows_per_wave", C.c_int32), ("precond", C.c_int32), ("block_size", C.c_int32),
-                ("unscaled_cg", C.c_int32)]
+                ("unscaled_cg", C.c_int32), ("stop_gap", C.c_double)]
 
 
 class RoundStats(C.Structure):
     _fields_ = [("eps", C.c_double), ("cg_iters", C.c_int64), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("s_eps", C.c_double), ("l1", C.c_double),
                 ("flow", C.c_double), ("flow_s", C.c_double), ("flow_t", C.c_double),
-                ("vmin", C.c_double), ("vmax", C.c_double), ("status", C.c_int32)]
+                ("vmin", C.c_double), ("vmax", C.c_double), ("status", C.c_int32),
+                ("lower_bound", C.c_double)]
 
 
 STAT_FIELDS = [f for f, _ in RoundStats._fields_]

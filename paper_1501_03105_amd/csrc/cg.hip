@@ -1137,21 +1137,27 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
 // ----------------------------------------------------------------------------
 // per-round diagnostics (Section 2.1-2.2): smoothed objective, ||CBx||_1,
 // flow value x^T L x and the flows at s and t (Proposition 3), the range of v
-// (Proposition 2) and the true residual; k_stats_final adds the partials.
+// (Proposition 2), the true residual, and rho = max g|d|/c for the lower
+// bound on the minimum cut; k_stats_final adds the partials.
 // ----------------------------------------------------------------------------
 // Diagnostics of one row: its interior edges' terms are added by the caller
 // (each edge once, from its lower endpoint); this adds the terminal edges'
 // terms, the squared true residual b_u - (L~ v)_u and the range of v.
-// slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v)
+// slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v), max g|d|/c
+constexpr int kStatQ = 9;
+constexpr unsigned kStatMax = 0x1C0u;                 // slots 6..8 are maxima
 template <typename T>
-__device__ __forceinline__ void stats_edge(const CGArgs<T> &a, double c, double g, double d, double (&x)[8]) {
+__device__ __forceinline__ void stats_edge(const CGArgs<T> &a, double c, double g, double d,
+                                           double (&x)[kStatQ]) {
   x[0] += a.form == 0 ? c * sqrt(d * d + a.eps_next) : sqrt((c * d) * (c * d) + a.eps_next);
   x[1] += c * fabs(d);
   x[2] += g * d * d;
+  if (c > 0.0) x[8] = fmax(x[8], g * fabs(d) / c);
 }
 
 template <typename T>
-__device__ __forceinline__ void stats_row_tail(const CGArgs<T> &a, int64_t u, double vu, double lv, double (&x)[8]) {
+__device__ __forceinline__ void stats_row_tail(const CGArgs<T> &a, int64_t u, double vu, double lv,
+                                               double (&x)[kStatQ]) {
   const double cs = a.cs[u], ct = a.ct[u];
   if (cs > 0.0) {
     stats_edge(a, cs, a.b[u], 1.0 - vu, x);
@@ -1169,9 +1175,9 @@ __device__ __forceinline__ void stats_row_tail(const CGArgs<T> &a, int64_t u, do
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_stats(CGArgs<T> a) {
-  __shared__ double lds[8 * (kBlock / 64)];
+  __shared__ double lds[kStatQ * (kBlock / 64)];
   const double *w = a.w64 ? a.w64 : (const double *)a.w;
-  double x[8] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY};
+  double x[kStatQ] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0};
   FOR_ROWS(u, a.nt) {
     const double vu = a.v[u];
     for_each_nb<true>(a, u, [&](int64_t j, double c, int64_t wi) {
@@ -1179,15 +1185,15 @@ __global__ __launch_bounds__(kBlock) void k_stats(CGArgs<T> a) {
     });
     stats_row_tail(a, u, vu, row_apply64<true>(a, u, a.v), x);
   }
-  write_partials<8, 0xC0u>(x, a.partials, kPStats, lds);
+  write_partials<kStatQ, kStatMax>(x, a.partials, kPStats, lds);
 }
 
 template <typename T, int L>
 __global__ __launch_bounds__(kBlock) void k_stats_csr(CGArgs<T> a) {
-  __shared__ double lds[8 * (kBlock / 64)];
+  __shared__ double lds[kStatQ * (kBlock / 64)];
   const double *w = a.w64 ? a.w64 : (const double *)a.w;
   const double *D = a.D64 ? a.D64 : (const double *)a.D;
-  double x[8] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY};
+  double x[kStatQ] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0};
   for_row_groups<L>(a.nt, [&](int64_t u, int lid) {
     double off = 0.0, vu = 0.0;                // off: sum of w_uj v_j over row u's entries
     if (u >= 0) {
@@ -1203,15 +1209,15 @@ __global__ __launch_bounds__(kBlock) void k_stats_csr(CGArgs<T> a) {
     off = group_sum<L>(off);
     if (u >= 0 && lid == 0) stats_row_tail(a, u, vu, D[u] * vu - off, x);
   });
-  write_partials<8, 0xC0u>(x, a.partials, kPStats, lds);
+  write_partials<kStatQ, kStatMax>(x, a.partials, kPStats, lds);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_stats_final(CGArgs<T> a, int nblocks) {
-  __shared__ double lds[8 * (kBlock / 64)];
-  __shared__ double bc[8];
-  double tot[8];
-  read_totals<8, 0xC0u>(a.partials, kPStats, nblocks, tot, lds, bc);
+  __shared__ double lds[kStatQ * (kBlock / 64)];
+  __shared__ double bc[kStatQ];
+  double tot[kStatQ];
+  read_totals<kStatQ, kStatMax>(a.partials, kPStats, nblocks, tot, lds, bc);
   if (threadIdx.x != 0) return;
   irls_round_stats *R = a.stat;
   const Scalars *sc = a.sc;
@@ -1233,6 +1239,10 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(CGArgs<T> a, int nblocks
   R->vmin = a.nt > 0 ? -tot[6] : 0.0;
   R->vmax = a.nt > 0 ? tot[7] : 0.0;
   R->status = sc->status;
+  // the electrical flow scaled to respect every capacity (the s-t edge
+  // carries g_st at d = 1): a lower bound on the minimum cut
+  const double rho = a.cst > 0.0 ? fmax(tot[8], gst / a.cst) : tot[8];
+  R->lower_bound = fmin(R->flow_s, R->flow_t) / fmax(1.0, rho);
 }
 
 __global__ void k_fill(double *x, int64_t n, double value) {

@@ -483,7 +483,7 @@ irls_status check_options(const irls_options &o, std::string &err) {
       (o.inputs_on_device != 0 && o.inputs_on_device != 1) || o.rows_per_wave < 0 ||
       o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0 || o.precond < 0 ||
       o.precond > 1 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0 ||
-      (o.unscaled_cg != 0 && o.unscaled_cg != 1)) {
+      (o.unscaled_cg != 0 && o.unscaled_cg != 1) || !(o.stop_gap >= 0.0) || !(o.stop_gap < 1.0)) {
     err = "an option is out of range";
     return IRLS_ERR_OPTIONS;
   }
@@ -851,6 +851,19 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
     }
     if (nt > 0) HIPCHK(h, launch_stats(a, h->grid, h->stream), "stats");
     if (result == IRLS_ERR_CG_BREAKDOWN) break;
+    if (o.stop_gap > 0.0 && nt > 0) {
+      // the certified gap of this round: ||CBx||_1 - lower bound (both bound
+      // the minimum cut); the records of rounds not run are cleared
+      irls_round_stats r;
+      HIPCHK(h, hipMemcpyAsync(&r, h->dstats + l, sizeof(r), hipMemcpyDeviceToHost, h->stream), "stats read");
+      HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+      if (r.l1 - r.lower_bound <= o.stop_gap * r.l1) {
+        if (l < o.rounds)
+          HIPCHK(h, hipMemsetAsync(h->dstats + l + 1, 0, (size_t)(o.rounds - l) * sizeof(irls_round_stats),
+                                   h->stream), "clear");
+        break;
+      }
+    }
     if (l >= 1) eps *= o.eps_factor;
   }
   if (stats)
@@ -901,6 +914,7 @@ ResidentArgs resident_args(irls_mincut_t h) {
   a.rtol = o.cg_rtol;
   a.maxit = o.cg_maxit;
   a.lane_code = h->lane_code;
+  a.stop_gap = o.stop_gap;
   return a;
 }
 
@@ -1112,6 +1126,7 @@ void irls_options_default(irls_options *o) {
   o->precond = 0;
   o->block_size = 0;
   o->unscaled_cg = 0;
+  o->stop_gap = 0.0;
 }
 
 irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const int64_t *edge_u,

@@ -13,7 +13,7 @@ namespace irls {
 constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
 constexpr int kMaxGrid = 1024;       // workgroups of the streaming kernels (grid-stride)
 constexpr int kMaxDiag = 8;          // most index offsets the diagonal format stores
-constexpr int kNumPartial = 8;       // reduction slots per workgroup
+constexpr int kNumPartial = 9;       // reduction slots per workgroup
 
 // CG state shared between consecutive kernels of one solve, in device memory.
 // Only workgroup 0 of a kernel writes it, and never a field that the same
@@ -241,6 +241,8 @@ struct ResidentArgs {
   double rtol;
   int64_t maxit;
   uint32_t lane_code;             // lanes per light row by bin (see kBins)
+  double stop_gap;                // > 0: a graph stops after the first round with
+                                  // l1 - lower_bound <= stop_gap * l1
 };
 hipError_t launch_resident(const ResidentArgs &a, int grid, int block, hipStream_t st);
 hipError_t launch_resident_reset(unsigned *next_graph, irls_round_stats *st, int64_t nrec, hipStream_t s);

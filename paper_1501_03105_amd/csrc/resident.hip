@@ -234,9 +234,9 @@ __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, con
 }
 
 __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
-  __shared__ double lds[8 * (kResBlock / 64)];
-  __shared__ double bc[8];
-  __shared__ int gsh;
+  __shared__ double lds[9 * (kResBlock / 64)];
+  __shared__ double bc[9];
+  __shared__ int gsh, stop_sh;
   const int tid = threadIdx.x, bd = blockDim.x;
   for (;;) {
     if (tid == 0) gsh = (int)atomicAdd(a.next_graph, 1u);
@@ -364,8 +364,9 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
       }
       __syncthreads();
       // diagnostics of this round: x^T L x's off-diagonal part and, once per
-      // edge (j > i), the smoothed objective, ||C B x||_1 and sum w d^2
-      double x[8] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY};
+      // edge (j > i), the smoothed objective, ||C B x||_1, sum w d^2 and the
+      // largest w |d| / c (for the lower bound; kept per thread, max-reduced)
+      double x[9] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0};
       rows_pass<4>(
           R,
           [&](int64_t i, int32_t e, auto &s) {
@@ -377,6 +378,7 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
             s[1] += a.form == 0 ? c * sqrt(d * d + eps_next) : sqrt((c * d) * (c * d) + eps_next);
             s[2] += c * fabs(d);
             s[3] += w[e] * d * d;
+            x[8] = fmax(x[8], w[e] * fabs(d) / c);
           },
           [&](int64_t i, const auto &s) {
             const double vi = v[i];
@@ -390,6 +392,7 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
               x[1] += c * fabs(d);
               x[2] += b[i] * d * d;
               x[3] += b[i] * d;
+              x[8] = fmax(x[8], b[i] * fabs(d) / c);
             }
             if (ct[i] > 0.0) {
               double c = ct[i], d = vi;
@@ -397,13 +400,14 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
               x[1] += c * fabs(d);
               x[2] += gtv[i] * d * d;
               x[4] += gtv[i] * d;
+              x[8] = fmax(x[8], gtv[i] * fabs(d) / c);
             }
             double res = b[i] - acc;
             x[5] += res * res;
             x[6] = fmax(x[6], -vi);
             x[7] = fmax(x[7], vi);
           });
-      block_reduce<8, 0xC0u>(x, lds);
+      block_reduce<9, 0x1C0u>(x, lds);
       if (tid == 0) {
         double gst = 0.0, sst = 0.0;
         if (gr.cst > 0.0) {
@@ -423,10 +427,14 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
         RS.vmin = nt > 0 ? -x[6] : 0.0;
         RS.vmax = nt > 0 ? x[7] : 0.0;
         RS.status = status;
+        // the flow scaled to respect every capacity: a lower bound on the cut
+        const double rho = gr.cst > 0.0 ? fmax(x[8], gst / gr.cst) : x[8];
+        RS.lower_bound = fmin(RS.flow_s, RS.flow_t) / fmax(1.0, rho);
         st[l] = RS;
+        stop_sh = a.stop_gap > 0.0 && RS.l1 - RS.lower_bound <= a.stop_gap * RS.l1;
       }
       __syncthreads();
-      if (status == IRLS_ERR_CG_BREAKDOWN) break;
+      if (status == IRLS_ERR_CG_BREAKDOWN || stop_sh) break;
       if (!round0) eps *= a.eps_factor;
     }
   }
@@ -440,7 +448,7 @@ __global__ void k_resident_reset(unsigned *next_graph, irls_round_stats *st, int
   if (i < nrec) {
     irls_round_stats z;
     z.eps = z.rel_res = z.true_rel_res = z.s_eps = z.l1 = z.flow = z.flow_s = z.flow_t = 0.0;
-    z.vmin = z.vmax = 0.0;
+    z.vmin = z.vmax = z.lower_bound = 0.0;
     z.cg_iters = 0;
     z.status = 0;
     st[i] = z;
