@@ -439,7 +439,14 @@ def main():
                    "interior_edges": info["nnz_offdiag"] // 2, "format": info["format"],
                    "solver": info["solver"], "cg_iters_per_cut": iters,
                    "cg_iters_per_round": [int(r["cg_iters"]) for r in st], "cut_value": val,
-                   "setup_s": round(t_setup, 3), "two_level": two},
+                   "setup_s": round(t_setup, 3), "two_level": two,
+                   # the last round's lower bound (its flow scaled to respect every
+                   # capacity) and ||CBx||_1 bracket the minimum cut: delta of a cut
+                   # is at most (cut - bound) / bound
+                   "certified": {"lower_bound": st[-1]["lower_bound"], "l1": st[-1]["l1"],
+                                 "sweep_delta_at_most": (val - st[-1]["lower_bound"]) / st[-1]["lower_bound"],
+                                 "two_level_delta_at_most":
+                                     (val2 - st[-1]["lower_bound"]) / st[-1]["lower_bound"]}},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
