@@ -227,6 +227,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
   int64_t nt = g->nt;
   double se = 0.0, l1 = 0.0, fl = 0.0, fs = 0.0, ft = 0.0;
   double rho = 0.0;                                     /* max over edges of |w d| / c */
+  double over = 0.0;                                    /* sum over edges of max(0, |w d| - c) */
   double vmin = nt ? v[0] : 0.0, vmax = nt ? v[0] : 0.0;
   for (int64_t i = 0; i < nt; i++) {
     for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) {
@@ -236,6 +237,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
       l1 += c * fabs(d);
       fl += S->w[a] * d * d;
       if (S->w[a] * fabs(d) / c > rho) rho = S->w[a] * fabs(d) / c;
+      if (S->w[a] * fabs(d) > c) over += S->w[a] * fabs(d) - c;
     }
     if (g->cs[i] > 0.0) {
       double c = g->cs[i], d = 1.0 - v[i];
@@ -244,6 +246,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
       fl += S->ws[i] * d * d;
       fs += S->ws[i] * d;
       if (S->ws[i] * fabs(d) / c > rho) rho = S->ws[i] * fabs(d) / c;
+      if (S->ws[i] * fabs(d) > c) over += S->ws[i] * fabs(d) - c;
     }
     if (g->ct[i] > 0.0) {
       double c = g->ct[i], d = v[i];
@@ -252,6 +255,7 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
       fl += S->wt[i] * d * d;
       ft += S->wt[i] * d;
       if (S->wt[i] * fabs(d) / c > rho) rho = S->wt[i] * fabs(d) / c;
+      if (S->wt[i] * fabs(d) > c) over += S->wt[i] * fabs(d) - c;
     }
     if (v[i] < vmin) vmin = v[i];
     if (v[i] > vmax) vmax = v[i];
@@ -264,22 +268,31 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
     fs += S->wst;
     ft += S->wst;
     if (S->wst / c > rho) rho = S->wst / c;
+    if (S->wst > c) over += S->wst - c;
   }
   R->s_eps = se; R->l1 = l1; R->flow = fl; R->flow_s = fs; R->flow_t = ft;
-  /* the electrical flow f_e = w_e d_e is conserved where the system is solved;
-     divided by max(1, rho) it respects every capacity, so its value bounds the
-     minimum cut from below (max-flow / min-cut duality) */
-  R->lower_bound = (fs < ft ? fs : ft) / (rho > 1.0 ? rho : 1.0);
   R->vmin = vmin; R->vmax = vmax;
   /* true residual of this round's system */
+  double r1 = 0.0;                                      /* ||b - A v||_1 */
   if (nt > 0) {
     spmv(g, S, v, q);
     for (int64_t i = 0; i < nt; i++) q[i] = S->b[i] - q[i];
     double bn = sqrt(dot(S->b, S->b, nt));
     R->true_rel_res = bn > 0.0 ? sqrt(dot(q, q, nt)) / bn : 0.0;
+    for (int64_t i = 0; i < nt; i++) r1 += fabs(q[i]);
   } else {
     R->true_rel_res = 0.0;
   }
+  /* The electrical flow f_e = w_e d_e leaves node u's balance off by the
+     residual r_u, so its net flow across any s-t cut is at least
+     F = max(flow_s, flow_t) - ||r||_1.  Two lower bounds on the minimum cut
+     follow: divided by max(1, rho) it respects every capacity, so F / max(1,
+     rho) is at most the cut's capacity; and across any cut it carries at most
+     the cut's capacity plus the overload sum(max(0, |f_e| - c_e)) of the
+     cut's edges, hence of all edges (max-flow / min-cut duality). */
+  double F = (fs > ft ? fs : ft) - r1;
+  double lb1 = F / (rho > 1.0 ? rho : 1.0), lb2 = F - over;
+  R->lower_bound = lb1 > lb2 ? lb1 : lb2;
 }
 
 int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,

@@ -57,10 +57,10 @@ typedef struct {
   double  flow_t;        /* flow entering t */
   double  vmin, vmax;    /* range of the non-terminal potentials */
   int32_t status;
-  double  lower_bound;   /* min(flow_s, flow_t) / max(1, rho), rho = max over edges of
-                            w_e |x_u - x_v| / c_e: the round's electrical flow scaled to
-                            respect every capacity, so a lower bound on the minimum cut
-                            when the round's system is solved (up to its residual) */
+  double  lower_bound;   /* with f_e = w_e (x_u - x_v), F = max(flow_s, flow_t) -
+                            ||b - A v||_1 and rho = max_e |f_e| / c_e:
+                            max(F / max(1, rho), F - sum_e max(0, |f_e| - c_e)),
+                            a lower bound on the minimum cut */
 } orc_round;
 
 void orc_options_default(orc_options *o);

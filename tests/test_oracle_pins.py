@@ -116,18 +116,25 @@ def test_path_every_round_matches_series_circuit(oracle_mod):
     assert val == min(caps)
 
 
+def by_hand_bound(F, caps):
+    """A series circuit carries one flow F on every edge: rho = F / min(c),
+    the overload is sum(max(0, F - c_j))."""
+    return max(min(F, min(caps)), F - sum(max(0.0, F - c) for c in caps))
+
+
 def test_path_lower_bound_by_hand(oracle_mod):
     """The per-round lower bound on a path, by hand: a series circuit carries
-    one flow F = 1 / sum(1/g_j) on every edge, so rho = F / min(c) and the
-    bound F / max(1, rho) is min(F, min c) (the path's minimum cut is min c).
-    Round 0 (g = c) gives F < min c: the bound is the flow itself."""
+    one flow F = 1 / sum(1/g_j) on every edge, so the scaled bound
+    F / max(1, rho) is min(F, min c) and the overload bound is
+    F - sum(max(0, F - c_j)); the record holds the larger (the path's minimum
+    cut is min c).  Round 0 (g = c) gives F < min c: the bound is the flow."""
     caps = [0.9, 0.35, 0.8, 0.6, 0.25, 1.1, 0.7]
     g = path_graph(caps)
     k = len(caps) - 1
     x, R, _ = oracle_mod.irls(g, rounds=0, cg_rtol=1e-14)
     F0 = 1.0 / sum(1.0 / c for c in caps)
     assert F0 < min(caps)
-    assert R[0]["lower_bound"] == pytest.approx(F0, rel=1e-12)
+    assert R[0]["lower_bound"] == pytest.approx(F0, rel=1e-12)         # the residual is ~1e-16
     prev = x
     eps = 0.1
     for T in range(1, 12):
@@ -135,30 +142,33 @@ def test_path_lower_bound_by_hand(oracle_mod):
         pot = [1.0] + list(prev[:k]) + [0.0]
         cond = [c / np.sqrt((pot[j] - pot[j + 1]) ** 2 + eps) for j, c in enumerate(caps)]
         F = 1.0 / sum(1.0 / w for w in cond)
-        assert R[T]["lower_bound"] == pytest.approx(min(F, min(caps)), rel=1e-9), T
+        assert R[T]["lower_bound"] == pytest.approx(by_hand_bound(F, caps), rel=1e-9), T
+        assert R[T]["lower_bound"] <= min(caps) * (1 + 1e-12)
         prev = xT
         eps *= 0.5
 
 
 def test_lower_bound_below_min_cut(oracle_mod):
-    """Every round's lower bound lies below the exhaustive minimum cut (its
-    flow, scaled to respect every capacity, is feasible), round 0's equals
-    its flow value E0 (there |x_u - x_v| <= 1, so rho <= 1), ||CBx||_1 lies
-    above the minimum cut, and the bound closes in on it."""
+    """Every round's lower bound lies below the exact minimum cut, round 0's
+    is its flow value E0 less the residual (there |x_u - x_v| <= 1, so
+    rho <= 1), ||CBx||_1 lies above the minimum cut, and the bound closes in
+    on it."""
     for seed in range(1, 51):
         g = gen.gnp(16, 0.3, seed=seed)
         _, R, _ = oracle_mod.irls(g, rounds=20, cg_rtol=1e-12)
         _, mu, _ = oracle_mod.bruteforce(g)
-        assert R[0]["lower_bound"] == pytest.approx(R[0]["flow"], rel=1e-12)
+        assert R[0]["lower_bound"] == pytest.approx(R[0]["flow"], rel=1e-9)
         for r in R:
-            assert r["lower_bound"] <= mu * (1 + 1e-9)
+            assert r["lower_bound"] <= mu * (1 + 1e-12)
             assert mu <= r["l1"] * (1 + 1e-12)
         assert R[-1]["lower_bound"] >= 0.99 * mu
-    for g in (gen.grid2d(40, 30, seed=5), gen.grid3d_seg(12, seed=2)):
+    # where the potentials polarise (the segmentation grid) few edges carry
+    # more than their capacity and the overload bound is tight
+    for g, tight in ((gen.grid2d(40, 30, seed=5), 0.95), (gen.grid3d_seg(12, seed=2), 0.999)):
         _, R, _ = oracle_mod.irls(g, rounds=30, cg_rtol=1e-10)
         _, mu = oracle_mod.maxflow(g)
-        assert all(r["lower_bound"] <= mu * (1 + 1e-9) for r in R)
-        assert R[-1]["lower_bound"] >= 0.95 * mu
+        assert all(r["lower_bound"] <= mu * (1 + 1e-12) for r in R)
+        assert R[-1]["lower_bound"] >= tight * mu
 
 
 def test_uniform_grid_reduces_to_path(oracle_mod):
