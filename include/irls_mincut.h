@@ -109,15 +109,19 @@ typedef struct {
   double  flow_s, flow_t;     /* flow leaving s / entering t */
   double  vmin, vmax;         /* range of the non-terminal potentials (Proposition 2) */
   int32_t status;             /* irls_status of this round's CG */
-  double  lower_bound;        /* min(flow_s, flow_t) / max(1, rho), rho = the largest
-                                 g_e |x_u - x_v| / c_e over all edges: this round's
-                                 electrical flow (Proposition 3) scaled to respect every
-                                 capacity.  Where the round's system is solved (up to its
-                                 residual) the flow is conserved, so by max-flow / min-cut
-                                 duality lower_bound <= mu*; with l1 >= mu* the pair
-                                 brackets the minimum cut.  In round 0 (g = c,
-                                 |x_u - x_v| <= 1) it is the flow value E0 of the
-                                 Cheeger-type bracket. */
+  double  lower_bound;        /* a lower bound on the minimum cut mu* from this round's
+                                 electrical flow f_e = g_e (x_u - x_v) (Proposition 3).
+                                 Node u's imbalance is the residual r_u, so f's net flow
+                                 across any s-t cut is at least
+                                 F = max(flow_s, flow_t) - ||b - L~ x||_1.  By max-flow /
+                                 min-cut duality both F / max(1, rho), with rho = the
+                                 largest |f_e| / c_e (f scaled to respect every capacity),
+                                 and F - sum_e max(0, |f_e| - c_e) (a cut carries at most
+                                 its capacity plus its edges' overload) are at most mu*;
+                                 this is the larger.  With l1 >= mu* the pair brackets
+                                 the minimum cut.  In round 0 (g = c, |x_u - x_v| <= 1)
+                                 it is the flow value E0 of the Cheeger-type bracket,
+                                 less the residual. */
 } irls_round_stats;
 
 void irls_options_default(irls_options *o);

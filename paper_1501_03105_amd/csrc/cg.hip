@@ -1137,14 +1137,16 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
 // ----------------------------------------------------------------------------
 // per-round diagnostics (Section 2.1-2.2): smoothed objective, ||CBx||_1,
 // flow value x^T L x and the flows at s and t (Proposition 3), the range of v
-// (Proposition 2), the true residual, and rho = max g|d|/c for the lower
-// bound on the minimum cut; k_stats_final adds the partials.
+// (Proposition 2), the true residual, and for the lower bound on the minimum
+// cut rho = max g|d|/c, the overload sum max(0, g|d| - c) and ||r||_1;
+// k_stats_final adds the partials.
 // ----------------------------------------------------------------------------
 // Diagnostics of one row: its interior edges' terms are added by the caller
 // (each edge once, from its lower endpoint); this adds the terminal edges'
 // terms, the squared true residual b_u - (L~ v)_u and the range of v.
-// slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v), max g|d|/c
-constexpr int kStatQ = 9;
+// slots: s_eps, l1, flow, flow_s, flow_t, res^2, max(-v), max(v), max g|d|/c,
+// overload, |res|
+constexpr int kStatQ = 11;
 constexpr unsigned kStatMax = 0x1C0u;                 // slots 6..8 are maxima
 template <typename T>
 __device__ __forceinline__ void stats_edge(const CGArgs<T> &a, double c, double g, double d,
@@ -1152,7 +1154,10 @@ __device__ __forceinline__ void stats_edge(const CGArgs<T> &a, double c, double 
   x[0] += a.form == 0 ? c * sqrt(d * d + a.eps_next) : sqrt((c * d) * (c * d) + a.eps_next);
   x[1] += c * fabs(d);
   x[2] += g * d * d;
-  if (c > 0.0) x[8] = fmax(x[8], g * fabs(d) / c);
+  if (c > 0.0) {
+    x[8] = fmax(x[8], g * fabs(d) / c);
+    x[9] += fmax(0.0, g * fabs(d) - c);
+  }
 }
 
 template <typename T>
@@ -1169,6 +1174,7 @@ __device__ __forceinline__ void stats_row_tail(const CGArgs<T> &a, int64_t u, do
   }
   const double res = a.b[u] - lv;
   x[5] += res * res;
+  x[10] += fabs(res);
   x[6] = fmax(x[6], -vu);
   x[7] = fmax(x[7], vu);
 }
@@ -1177,7 +1183,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_stats(CGArgs<T> a) {
   __shared__ double lds[kStatQ * (kBlock / 64)];
   const double *w = a.w64 ? a.w64 : (const double *)a.w;
-  double x[kStatQ] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0};
+  double x[kStatQ] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0, 0, 0};
   FOR_ROWS(u, a.nt) {
     const double vu = a.v[u];
     for_each_nb<true>(a, u, [&](int64_t j, double c, int64_t wi) {
@@ -1193,7 +1199,7 @@ __global__ __launch_bounds__(kBlock) void k_stats_csr(CGArgs<T> a) {
   __shared__ double lds[kStatQ * (kBlock / 64)];
   const double *w = a.w64 ? a.w64 : (const double *)a.w;
   const double *D = a.D64 ? a.D64 : (const double *)a.D;
-  double x[kStatQ] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0};
+  double x[kStatQ] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0, 0, 0};
   for_row_groups<L>(a.nt, [&](int64_t u, int lid) {
     double off = 0.0, vu = 0.0;                // off: sum of w_uj v_j over row u's entries
     if (u >= 0) {
@@ -1239,10 +1245,15 @@ __global__ __launch_bounds__(kBlock) void k_stats_final(CGArgs<T> a, int nblocks
   R->vmin = a.nt > 0 ? -tot[6] : 0.0;
   R->vmax = a.nt > 0 ? tot[7] : 0.0;
   R->status = sc->status;
-  // the electrical flow scaled to respect every capacity (the s-t edge
-  // carries g_st at d = 1): a lower bound on the minimum cut
+  // Lower bound on the minimum cut from the electrical flow f = g d: its net
+  // flow across any cut is at least F (the residual is each node's
+  // imbalance); scaled by 1 / max(1, rho) it respects every capacity, and
+  // across any cut it exceeds the capacity by at most the total overload.
+  // The s-t edge carries g_st at d = 1.
   const double rho = a.cst > 0.0 ? fmax(tot[8], gst / a.cst) : tot[8];
-  R->lower_bound = fmin(R->flow_s, R->flow_t) / fmax(1.0, rho);
+  const double over = tot[9] + (a.cst > 0.0 ? fmax(0.0, gst - a.cst) : 0.0);
+  const double F = fmax(R->flow_s, R->flow_t) - tot[10];
+  R->lower_bound = fmax(F / fmax(1.0, rho), F - over);
 }
 
 __global__ void k_fill(double *x, int64_t n, double value) {

@@ -13,7 +13,7 @@ namespace irls {
 constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
 constexpr int kMaxGrid = 1024;       // workgroups of the streaming kernels (grid-stride)
 constexpr int kMaxDiag = 8;          // most index offsets the diagonal format stores
-constexpr int kNumPartial = 9;       // reduction slots per workgroup
+constexpr int kNumPartial = 11;      // reduction slots per workgroup
 
 // CG state shared between consecutive kernels of one solve, in device memory.
 // Only workgroup 0 of a kernel writes it, and never a field that the same

@@ -234,8 +234,8 @@ __device__ __forceinline__ void spmv_pass(const ResRows &R, const double *w, con
 }
 
 __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
-  __shared__ double lds[9 * (kResBlock / 64)];
-  __shared__ double bc[9];
+  __shared__ double lds[11 * (kResBlock / 64)];
+  __shared__ double bc[11];
   __shared__ int gsh, stop_sh;
   const int tid = threadIdx.x, bd = blockDim.x;
   for (;;) {
@@ -364,9 +364,10 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
       }
       __syncthreads();
       // diagnostics of this round: x^T L x's off-diagonal part and, once per
-      // edge (j > i), the smoothed objective, ||C B x||_1, sum w d^2 and the
-      // largest w |d| / c (for the lower bound; kept per thread, max-reduced)
-      double x[9] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0};
+      // edge (j > i), the smoothed objective, ||C B x||_1 and sum w d^2; for
+      // the lower bound the largest w |d| / c, the overload max(0, w|d| - c)
+      // and ||r||_1 (kept per thread, then reduced over the workgroup)
+      double x[11] = {0, 0, 0, 0, 0, 0, -INFINITY, -INFINITY, 0, 0, 0};
       rows_pass<4>(
           R,
           [&](int64_t i, int32_t e, auto &s) {
@@ -379,6 +380,7 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
             s[2] += c * fabs(d);
             s[3] += w[e] * d * d;
             x[8] = fmax(x[8], w[e] * fabs(d) / c);
+            x[9] += fmax(0.0, w[e] * fabs(d) - c);
           },
           [&](int64_t i, const auto &s) {
             const double vi = v[i];
@@ -393,6 +395,7 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
               x[2] += b[i] * d * d;
               x[3] += b[i] * d;
               x[8] = fmax(x[8], b[i] * fabs(d) / c);
+              x[9] += fmax(0.0, b[i] * fabs(d) - c);
             }
             if (ct[i] > 0.0) {
               double c = ct[i], d = vi;
@@ -401,13 +404,15 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
               x[2] += gtv[i] * d * d;
               x[4] += gtv[i] * d;
               x[8] = fmax(x[8], gtv[i] * fabs(d) / c);
+              x[9] += fmax(0.0, gtv[i] * fabs(d) - c);
             }
             double res = b[i] - acc;
             x[5] += res * res;
+            x[10] += fabs(res);
             x[6] = fmax(x[6], -vi);
             x[7] = fmax(x[7], vi);
           });
-      block_reduce<9, 0x1C0u>(x, lds);
+      block_reduce<11, 0x1C0u>(x, lds);
       if (tid == 0) {
         double gst = 0.0, sst = 0.0;
         if (gr.cst > 0.0) {
@@ -427,9 +432,11 @@ __global__ __launch_bounds__(kResBlock) void k_resident(ResidentArgs a) {
         RS.vmin = nt > 0 ? -x[6] : 0.0;
         RS.vmax = nt > 0 ? x[7] : 0.0;
         RS.status = status;
-        // the flow scaled to respect every capacity: a lower bound on the cut
+        // lower bound on the minimum cut (as in the multi-workgroup stats)
         const double rho = gr.cst > 0.0 ? fmax(x[8], gst / gr.cst) : x[8];
-        RS.lower_bound = fmin(RS.flow_s, RS.flow_t) / fmax(1.0, rho);
+        const double over = x[9] + (gr.cst > 0.0 ? fmax(0.0, gst - gr.cst) : 0.0);
+        const double F = fmax(RS.flow_s, RS.flow_t) - x[10];
+        RS.lower_bound = fmax(F / fmax(1.0, rho), F - over);
         st[l] = RS;
         stop_sh = a.stop_gap > 0.0 && RS.l1 - RS.lower_bound <= a.stop_gap * RS.l1;
       }

@@ -48,8 +48,8 @@ def test_lower_bound_matches_oracle(P, oracle_mod, case):
         err = abs(a["lower_bound"] - b["lower_bound"]) / b["lower_bound"]
         worst = max(worst, err)
         assert err <= 1e-5, (l, a["lower_bound"], b["lower_bound"])
-        assert a["lower_bound"] <= mu * (1 + 1e-6), l
-    assert st[0]["lower_bound"] == pytest.approx(st[0]["flow"], rel=1e-9)
+        assert a["lower_bound"] <= mu * (1 + 1e-9), l
+    assert st[0]["lower_bound"] == pytest.approx(st[0]["flow"], rel=1e-6)
     say(f"{name}: lower bound within {worst:.1e} of the oracle's; last round "
         f"{st[-1]['lower_bound'] / mu:.5f} mu*, l1 {st[-1]['l1'] / mu:.5f} mu*")
 
@@ -63,7 +63,7 @@ def test_lower_bound_batch(P, oracle_mod):
         mu = exact_min_cut(oracle_mod, g)
         for a, b in zip(st, so):
             assert a["lower_bound"] == pytest.approx(b["lower_bound"], rel=1e-5)
-            assert a["lower_bound"] <= mu * (1 + 1e-6)
+            assert a["lower_bound"] <= mu * (1 + 1e-9)
 
 
 def first_round_within(st, gap):
