@@ -331,6 +331,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--gnn-epochs", type=int, default=30)
+    ap.add_argument("--early-stop-gap", type=float, default=0.01,
+                    help="also time the certified-gap stopping rule (stop_gap) on the same instance; 0: skip")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run 5 plain device copies of MIB MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -412,6 +414,35 @@ def main():
               file=sys.stderr, flush=True)
     mc.close()
 
+    # A mode of the library beside the configured run: the same instance with
+    # the certified-gap stopping rule (rounds stop once ||CBx||_1 and the
+    # round's lower bound on the minimum cut are within stop_gap), its
+    # time-to-cut, and the two-level rounding of the stopped potentials.
+    early = None
+    if args.early_stop_gap > 0 and info["solver"] == 1:
+        with P.MinCut.from_graph(g, stream=stream, stop_gap=args.early_stop_gap, **opts) as me:
+            me.solve()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ste = me.solve()
+            _, vale, _ = me.cut()
+            torch.cuda.synchronize()
+            dte = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            _, vale2, _ = me.cut_two_level()
+            torch.cuda.synchronize()
+            dte2 = time.perf_counter() - t0
+        L = max(l for l, r in enumerate(ste) if l == 0 or r["eps"] > 0)
+        lb = ste[L]["lower_bound"]
+        early = {"stop_gap": args.early_stop_gap, "last_round": L, "rounds_configured": opts["rounds"],
+                 "cg_iters": int(sum(r["cg_iters"] for r in ste)), "seconds_to_cut": round(dte, 4),
+                 "cuts_per_s": round(1.0 / dte, 3), "sweep_cut": vale, "lower_bound": lb,
+                 "certified_sweep_delta_at_most": (vale - lb) / lb,
+                 "two_level_cut": vale2, "two_level_seconds": round(dte2, 4),
+                 "two_level_cut_equals_configured_run": vale2 == val2}
+        print(f"[bench] stop_gap {args.early_stop_gap}: rounds 0..{L}, {early['cg_iters']} CG iterations, "
+              f"{dte*1e3:.1f} ms to the sweep cut {vale:.10g}; two-level {vale2:.10g}", file=sys.stderr, flush=True)
+
     if args.calibrate_copy > 0:
         nel = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -443,6 +474,7 @@ def main():
                    # the last round's lower bound (its flow scaled to respect every
                    # capacity) and ||CBx||_1 bracket the minimum cut: delta of a cut
                    # is at most (cut - bound) / bound
+                   "early_stop": early,
                    "certified": {"lower_bound": st[-1]["lower_bound"], "l1": st[-1]["l1"],
                                  "sweep_delta_at_most": (val - st[-1]["lower_bound"]) / st[-1]["lower_bound"],
                                  "two_level_delta_at_most":
