@@ -324,7 +324,7 @@ def bench_gnn(args, spec, opts, desc):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="seg128", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -377,8 +377,11 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for i in range(args.steps):
-        st, val = step()
+        ts = time.perf_counter()
+        st, val = step()                     # the cut's readback synchronises the stream
+        step_ms.append(1000.0 * (time.perf_counter() - ts))
         print(f"[bench] step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -469,6 +472,8 @@ def main():
         "config": {"workload": desc, "name": args.workload, "n_nonterminal": info["n_nonterminal"],
                    "interior_edges": info["nnz_offdiag"] // 2, "format": info["format"],
                    "solver": info["solver"], "cg_iters_per_cut": iters,
+                   "step_ms": [round(t, 3) for t in step_ms],
+                   "median_step_ms": round(sorted(step_ms)[len(step_ms) // 2], 3),
                    "cg_iters_per_round": [int(r["cg_iters"]) for r in st], "cut_value": val,
                    "setup_s": round(t_setup, 3), "two_level": two,
                    # the last round's lower bound (its flow scaled to respect every
