@@ -254,12 +254,19 @@ irls_status build_host_graph(HostGraph &g, int64_t n, int64_t m, const int64_t *
 }
 
 // ----------------------------------------------------------------------------
-// Exact maximum flow / minimum cut of a small undirected graph with 128-bit
-// integer capacities (the coarse graph of the two-level rounding): Dinic's
-// blocking flows on the level graph of residual arcs.  The returned source
-// side is the set of nodes that cannot reach t in the final residual graph,
-// which is the same for every maximum flow (the largest minimum-cut source
-// side).
+// Exact maximum flow / minimum cut of an undirected graph with 128-bit
+// integer capacities (the coarse graph of the two-level rounding): the first
+// phase of push-relabel, which ends in a maximum preflow.  Active nodes are
+// discharged highest label first; labels are reset to exact residual
+// distances to t by a reverse breadth-first search at the start and after
+// work proportional to the graph, and the gap heuristic lifts every node
+// above an emptied label to n (such nodes cannot reach t).
+// The returned source side is the set of nodes that cannot reach t in the
+// residual graph of the preflow.  Nodes that reach t hold no excess at the
+// end, so the preflow saturates every arc into that set and carries nothing
+// out of it.  Returning the excess to s (the second phase) would only change
+// arcs outside it, so it is also the set a maximum flow gives: the largest
+// minimum-cut source side.
 // ----------------------------------------------------------------------------
 struct FlowGraph {
   int64_t n = 0;
@@ -290,53 +297,104 @@ FlowGraph flow_graph(int64_t n, const std::vector<int64_t> &a, const std::vector
 
 i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_side) {
   const int64_t n = F.n;
-  std::vector<int64_t> level(n), it(n), queue(n), path;
-  i128 flow = 0;
-  for (;;) {
-    std::fill(level.begin(), level.end(), -1);
+  std::vector<int64_t> d(n, n), cur(n), queue(n);
+  std::vector<i128> ex(n, 0);
+  std::vector<int64_t> anext(n, -1), ahead(n + 1, -1);               // active nodes by label
+  std::vector<int64_t> lnext(n, -1), lprev(n, -1), lhead(n + 1, -1);  // all nodes by label (< n)
+  int64_t amax = -1, lmax = -1;
+  auto list_insert = [&](int64_t v) {
+    const int64_t h = lhead[d[v]];
+    lnext[v] = h;
+    lprev[v] = -1;
+    if (h >= 0) lprev[h] = v;
+    lhead[d[v]] = v;
+    lmax = std::max(lmax, d[v]);
+  };
+  auto list_remove = [&](int64_t v) {
+    if (lprev[v] >= 0) lnext[lprev[v]] = lnext[v];
+    else lhead[d[v]] = lnext[v];
+    if (lnext[v] >= 0) lprev[lnext[v]] = lprev[v];
+  };
+  auto activate = [&](int64_t v) {
+    anext[v] = ahead[d[v]];
+    ahead[d[v]] = v;
+    amax = std::max(amax, d[v]);
+  };
+  auto global_relabel = [&]() {
+    std::fill(d.begin(), d.end(), n);
+    std::fill(ahead.begin(), ahead.end(), -1);
+    std::fill(lhead.begin(), lhead.end(), -1);
+    amax = lmax = -1;
     int64_t qh = 0, qt = 0;
-    level[s] = 0;
-    queue[qt++] = s;
+    d[t] = 0;
+    queue[qt++] = t;
     while (qh < qt) {
-      const int64_t v = queue[qh++];
-      for (int64_t a = F.first[v]; a < F.first[v + 1]; a++)
-        if (F.res[a] > 0 && level[F.to[a]] < 0) { level[F.to[a]] = level[v] + 1; queue[qt++] = F.to[a]; }
+      const int64_t y = queue[qh++];
+      for (int64_t a = F.first[y]; a < F.first[y + 1]; a++) {
+        const int64_t x = F.to[a];
+        if (x != s && d[x] == n && F.res[F.mate[a]] > 0) { d[x] = d[y] + 1; queue[qt++] = x; }
+      }
     }
-    if (level[t] < 0) break;
-    for (int64_t v = 0; v < n; v++) it[v] = F.first[v];
-    path.clear();
-    int64_t v = s;
-    for (;;) {                                          // augmenting paths in the level graph
-      while (v != t) {
-        int64_t a = it[v];
-        for (; a < F.first[v + 1]; a++)
-          if (F.res[a] > 0 && level[F.to[a]] == level[v] + 1) break;
-        it[v] = a;
-        if (a < F.first[v + 1]) {
-          path.push_back(a);
-          v = F.to[a];
-        } else {                                        // dead end: leave it out of this phase
-          level[v] = -1;
-          if (path.empty()) break;
-          v = F.to[F.mate[path.back()]];
-          path.pop_back();
-          it[v]++;
+    for (int64_t v = 0; v < n; v++) {
+      if (v == s || v == t || d[v] >= n) continue;
+      cur[v] = F.first[v];
+      list_insert(v);
+      if (ex[v] > 0) activate(v);
+    }
+  };
+  for (int64_t a = F.first[s]; a < F.first[s + 1]; a++) {      // saturate every arc out of s
+    const i128 c = F.res[a];
+    if (c <= 0) continue;
+    F.res[a] = 0;
+    F.res[F.mate[a]] += c;
+    ex[F.to[a]] += c;
+  }
+  global_relabel();
+  int64_t work = 0;
+  const int64_t work_limit = 6 * n + (int64_t)F.to.size();
+  while (amax >= 0) {
+    const int64_t v = ahead[amax];
+    if (v < 0) { amax--; continue; }
+    ahead[amax] = anext[v];
+    if (d[v] != amax || ex[v] <= 0) continue;         // lifted by a gap after it was queued
+    while (ex[v] > 0) {
+      if (cur[v] == F.first[v + 1]) {                  // no admissible arc left: relabel
+        const int64_t old = d[v];
+        list_remove(v);
+        if (lhead[old] < 0) {                          // gap at `old`
+          for (int64_t L = old + 1; L <= lmax; L++) {
+            for (int64_t x = lhead[L]; x >= 0; x = lnext[x]) d[x] = n;
+            lhead[L] = -1;
+          }
+          lmax = old - 1;
+          d[v] = n;
+          break;
         }
+        int64_t m = n;
+        for (int64_t a = F.first[v]; a < F.first[v + 1]; a++)
+          if (F.res[a] > 0) m = std::min(m, d[F.to[a]] + 1);
+        work += 12 + (F.first[v + 1] - F.first[v]);
+        d[v] = m;
+        if (m >= n) break;
+        cur[v] = F.first[v];
+        list_insert(v);
+        continue;
       }
-      if (v != t) break;
-      i128 d = F.res[path[0]];
-      for (int64_t a : path) d = std::min(d, F.res[a]);
-      size_t keep = path.size();
-      for (size_t i = 0; i < path.size(); i++) {
-        const int64_t a = path[i];
-        F.res[a] -= d;
-        F.res[F.mate[a]] += d;
-        if (F.res[a] == 0 && i < keep) keep = i;        // the first arc the path saturated
+      const int64_t a = cur[v], w = F.to[a];
+      if (F.res[a] > 0 && d[w] == d[v] - 1) {          // push along an admissible arc
+        const i128 delta = std::min(ex[v], F.res[a]);
+        F.res[a] -= delta;
+        F.res[F.mate[a]] += delta;
+        ex[v] -= delta;
+        if (w != t && ex[w] == 0) activate(w);
+        ex[w] += delta;
+      } else {
+        cur[v]++;
       }
-      flow += d;
-      // continue from the tail of the first saturated arc
-      v = F.to[F.mate[path[keep]]];
-      path.resize(keep);
+    }
+    if (work > work_limit) {
+      global_relabel();
+      work = 0;
     }
   }
   // nodes that reach t through residual arcs form the sink side
@@ -353,7 +411,7 @@ i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_s
   }
   source_side.assign(n, 0);
   for (int64_t v = 0; v < n; v++) source_side[v] = reach[v] ? 0 : 1;
-  return flow;
+  return ex[t];
 }
 
 // Minimum s_c-t_c cut of the coarse graph: nodes 0..nc-1 with capacity ws[u]
