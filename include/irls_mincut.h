@@ -330,7 +330,8 @@ irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, doub
  *   lanes   NULL or 6 int32 (host): the table chosen
  * Errors (both): IRLS_ERR_OPTIONS for a handle that does not use the
  * resident solver or for values out of range; autotune with init 2 before
- * the potentials are set: IRLS_ERR_NOT_SOLVED. */
+ * the potentials are set: IRLS_ERR_NOT_SOLVED.  A device error during the
+ * timing solves leaves the potentials undefined and the handle unsolved. */
 irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes);
 irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes);
 
