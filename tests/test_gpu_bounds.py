@@ -139,3 +139,32 @@ def test_stop_gap_options(P):
         with pytest.raises(P.IrlsError) as e:
             P.MinCut.from_graph(g, stop_gap=bad)
         assert e.value.code == P.ERR_OPTIONS
+
+
+def test_stop_gap_precision_form_and_continuation(P):
+    """The rule on the FP32 form, and on a continuation (solve_range from the
+    kept potentials): in both the stopped run equals the run without the rule
+    up to its first round within the gap, and later records are empty."""
+    g = gen.grid3d_seg(24, seed=2)
+    gap = 0.06
+    for kw in (dict(precision=1), dict()):
+        with P.MinCut.from_graph(g, **OPTS, **kw) as full:
+            _, sf = full.solve()
+        L = first_round_within(sf, gap)
+        assert L is not None and 0 < L < OPTS["rounds"]
+        with P.MinCut.from_graph(g, stop_gap=gap, **OPTS, **kw) as mc:
+            _, st = mc.solve()
+        assert st[:L + 1] == sf[:L + 1]
+        assert all(r["eps"] == 0.0 and r["cg_iters"] == 0 for r in st[L + 1:])
+    # continuation: rounds 1..12 from the potentials of a 6-round solve
+    with P.MinCut.from_graph(g, **OPTS) as a, P.MinCut.from_graph(g, stop_gap=gap, **OPTS) as b:
+        a.solve_range(0, 6)
+        x6 = a.potentials()
+        _, cf = a.solve_range(1, 12, eps_first=1e-2)
+        b.set_potentials(x6)
+        _, cs = b.solve_range(1, 12, eps_first=1e-2)
+    L = first_round_within(cf, gap)
+    assert L is not None and L < 12
+    assert cs[:L + 1] == cf[:L + 1]
+    assert all(r["eps"] == 0.0 and r["cg_iters"] == 0 for r in cs[L + 1:])
+    say(f"stop_gap {gap}: precision form and continuation stop where the unstopped runs first reach it")
