@@ -328,10 +328,19 @@ irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, doub
  * graph) with the chosen table.
  *   rounds  0 .. the handle's rounds; reps >= 1
  *   lanes   NULL or 6 int32 (host): the table chosen
+ * For a single-graph handle on the multi-workgroup solver in the CSR format,
+ * irls_mincut_autotune instead tunes that path's rows per wavefront (its
+ * SpMV and per-round CSR kernels): it times 20 * reps SpMV launches
+ * (irls_mincut_time_kernel, which 0) on the last solve's system at each of
+ * 1, 2, 4, ..., 64 rows per wavefront, keeps the fastest (again by at least
+ * 2 %), and writes lanes[0] = 64 / rows per wavefront, lanes[1..5] = 0;
+ * rounds is ignored.  It needs a solved handle (else IRLS_ERR_NOT_SOLVED)
+ * and has nothing to tune in the diagonal format (IRLS_ERR_OPTIONS).
  * Errors (both): IRLS_ERR_OPTIONS for a handle that does not use the
- * resident solver or for values out of range; autotune with init 2 before
- * the potentials are set: IRLS_ERR_NOT_SOLVED.  A device error during the
- * timing solves leaves the potentials undefined and the handle unsolved. */
+ * resident solver or the CSR format, or for values out of range; autotune
+ * with init 2 before the potentials are set: IRLS_ERR_NOT_SOLVED.  A device
+ * error during the timing solves leaves the potentials undefined and the
+ * handle unsolved. */
 irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes);
 irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes);
 

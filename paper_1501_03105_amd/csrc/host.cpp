@@ -1822,8 +1822,46 @@ irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes) {
   return IRLS_OK;
 }
 
+// The multi-workgroup CSR path: rows per wavefront of its SpMV (and per-round
+// CSR kernels), measured by timing the SpMV on the last solve's system.
+static irls_status autotune_csr(irls_mincut_t h, int32_t reps, int32_t *lanes) {
+  const int32_t K = h->opt.precision == 1 ? make_args<float>(h).K : make_args<double>(h).K;
+  if (K > 0) { h->err = "the diagonal format has no rows per wavefront to tune"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "the CSR SpMV is timed on a solved system: call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
+  const int launches = 20 * reps;
+  double tcur = 0.0;
+  irls_status rc = irls_mincut_time_kernel(h, 0, launches, &tcur);
+  if (rc != IRLS_OK) return rc;
+  const int cur = h->rpw;
+  int best = cur;
+  double tbest = tcur;
+  for (int rpw = 1; rpw <= 64; rpw *= 2) {
+    if (rpw == cur) continue;
+    h->rpw = rpw;
+    double t = 0.0;
+    rc = irls_mincut_time_kernel(h, 0, launches, &t);
+    if (rc != IRLS_OK) { h->rpw = cur; return rc; }
+    if (t < 0.98 * tcur && t < tbest) { best = rpw; tbest = t; }
+  }
+  h->rpw = best;
+  if (lanes) {
+    lanes[0] = 64 / best;
+    for (int b = 1; b < kBins; b++) lanes[b] = 0;
+  }
+  return IRLS_OK;
+}
+
 irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (reps < 1) { h->err = "reps must be >= 1"; return IRLS_ERR_OPTIONS; }
+  if (!h->batch && h->solver == 1) {
+    try {
+      return autotune_csr(h, reps, lanes);
+    } catch (...) {
+      h->err = "unexpected host exception";
+      return IRLS_ERR_DEVICE;
+    }
+  }
   if (!h->batch && h->solver != 2) { h->err = "autotuning applies to the resident solver (solver 2 or a batch)"; return IRLS_ERR_OPTIONS; }
   if (rounds < 0 || rounds > h->opt.rounds || reps < 1) {
     h->err = "rounds must lie in [0, the handle's rounds] and reps >= 1";

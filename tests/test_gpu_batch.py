@@ -197,7 +197,28 @@ def test_row_lanes_errors(P):
             with pytest.raises(P.IrlsError) as e:
                 mb.autotune(rounds, reps)
             assert e.value.code == P.ERR_OPTIONS
-    with P.MinCut.from_graph(gen.grid2d(16, 16, seed=1), solver=1) as mc:
+    with P.MinCut.from_graph(gen.grid2d(16, 16, seed=1), solver=1) as mc:   # diagonal format
+        mc.solve()
         with pytest.raises(P.IrlsError) as e:
-            mc.autotune()
+            mc.autotune()                                 # nothing to tune
         assert e.value.code == P.ERR_OPTIONS
+
+
+def test_csr_rows_per_wave_autotune(P, oracle_mod):
+    """The multi-workgroup CSR path: autotuning times its SpMV at each rows
+    per wavefront and keeps one; solves with it still meet the oracle bars."""
+    for g in (gen.grid2d(64, 64, seed=0), gen.rmat_flowimprove(2003, log2_lo=10.0, log2_hi=10.5)):
+        with P.MinCut.from_graph(g, solver=1, format=1, **OPTS) as mc:
+            with pytest.raises(P.IrlsError) as e:
+                mc.autotune()                             # needs a solved system to time
+            assert e.value.code == P.ERR_NOT_SOLVED
+            mc.solve()
+            lanes = mc.autotune(reps=1)
+            assert lanes[0] in (1, 2, 4, 8, 16, 32, 64) and lanes[1:] == [0] * 5
+            say(f"CSR n={g.n}: autotuned lanes per row {lanes[0]}")
+            mc.solve()
+            x = mc.potentials()
+            _, v, _ = mc.cut()
+        xo, _, _ = oracle_mod.irls(g, **OPTS)
+        _, vo, _, _ = oracle_mod.sweep(g, xo)
+        assert max_pot_err(x, xo) <= 1e-7 and v == vo
