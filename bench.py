@@ -40,6 +40,9 @@ WORKLOADS = {
                      dict(rounds=40, cg_rtol=1e-8, precision=1, refine_every=20),
                      "3-D 256^3 segmentation grid, FP32 conductances/SpMV/CG vectors, FP64 "
                      "potentials, dots and residual replacement every 20 CG steps"),
+    "seg256-slab": (dict(kind="slab", N=256, planes=32, seed=2), dict(rounds=40, cg_rtol=1e-8),
+                    "one GPU's share of the 256^3 segmentation grid split into 8 z-slabs: its first "
+                    "32 planes (256x256x32) as a graph of their own, FP64, 40 rounds, CG to 1e-8"),
     "seg128-bj": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8, precond=1),
                   "3-D 128^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi "
                   "preconditioner (x-lines of 128 rows, tridiagonal blocks)"),
@@ -59,6 +62,8 @@ def make_graph(spec):
         return gen.rmat_batch(spec["count"], first_seed=spec["seed"])
     if kind == "seg":
         return gen.grid3d_seg(spec["N"], seed=spec["seed"])
+    if kind == "slab":
+        return gen.grid3d_seg_slab(spec["N"], spec["planes"], seed=spec["seed"])
     return gen.grid2d(spec["nx"], spec["ny"], seed=spec["seed"])
 
 

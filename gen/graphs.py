@@ -205,6 +205,23 @@ def grid3d_seg(N=128, seed=1, corr_len=8.0, beta=0.05, mu_fg=0.3, mu_bg=0.7, sd=
     return Graph(nn + 2, s, t, eu, ev, cap, meta=meta)
 
 
+def grid3d_seg_slab(N=256, planes=32, seed=2):
+    """The first `planes` z-planes of grid3d_seg(N, seed): the share of one
+    GPU when the N^3 instance is split into z-slabs (N^2 * planes nodes,
+    numbered as in the full grid; edges to the next slab dropped)."""
+    g = grid3d_seg(N, seed=seed)
+    keep_n = N * N * planes
+    s, t = keep_n, keep_n + 1
+    term_u, term_v = (g.eu == g.s) | (g.eu == g.t), (g.ev == g.s) | (g.ev == g.t)
+    inside = (term_u | (g.eu < keep_n)) & (term_v | (g.ev < keep_n))
+    eu = np.where(g.eu == g.s, s, np.where(g.eu == g.t, t, g.eu))[inside]
+    ev = np.where(g.ev == g.s, s, np.where(g.ev == g.t, t, g.ev))[inside]
+    cap = g.cap[inside]
+    interior = int(np.sum((eu < keep_n) & (ev < keep_n)))
+    meta = dict(kind="grid3d_seg_slab", N=N, planes=planes, seed=seed, interior=interior)
+    return Graph(keep_n + 2, s, t, eu, ev, cap, meta=meta)
+
+
 # ----------------------------------------------------------------------------
 # R-MAT FlowImprove-style instances
 # ----------------------------------------------------------------------------

@@ -68,3 +68,24 @@ def test_rmat_instance():
     assert np.array_equal(np.sort(term), np.arange(nt))
     nball = int(np.sum(g.eu == g.s))
     assert nball == int(np.ceil(0.05 * nt))
+
+
+def test_seg_slab_is_the_first_planes():
+    """The slab is the full grid restricted to its first planes: the same
+    interior edges and capacities among them, and both terminal edges of
+    every kept node with the full grid's capacities."""
+    import numpy as np
+    full = gen.grid3d_seg(24, seed=2)
+    g = gen.grid3d_seg_slab(24, 5, seed=2)
+    keep = 24 * 24 * 5
+    assert (g.n, g.s, g.t) == (keep + 2, keep, keep + 1)
+    m = (full.eu < keep) & (full.ev < keep)
+    k = int(m.sum())
+    assert g.meta["interior"] == k
+    assert np.array_equal(g.eu[:k], full.eu[m]) and np.array_equal(g.ev[:k], full.ev[m])
+    assert np.array_equal(g.cap[:k], full.cap[m])
+    src = g.eu == g.s
+    snk = g.ev == g.t
+    assert np.array_equal(np.sort(g.ev[src]), np.arange(keep)) and np.array_equal(np.sort(g.eu[snk]), np.arange(keep))
+    fsrc = (full.eu == full.s) & (full.ev < keep)
+    assert np.array_equal(g.cap[src], full.cap[fsrc])
