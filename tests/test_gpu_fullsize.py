@@ -101,3 +101,33 @@ def test_fullsize_round_solves_oracle_system(P, oracle_mod, seg128, l):
     R = st[l]
     assert R["flow_s"] - R["flow"] == pytest.approx(v @ r, rel=1e-3, abs=1e-9 * R["flow"])
     assert R["flow_s"] - R["flow_t"] == pytest.approx(r.sum(), rel=1e-3, abs=1e-9 * R["flow"])
+
+
+def test_fullsize_256_precision_form(P, oracle_mod):
+    """The 256^3 precision form at full size, in the benchmark's launch
+    configuration (FP32 conductances, SpMV and CG vectors; FP64 potentials,
+    dots and residual replacement every 20 steps; 40 rounds, CG to 1e-8), and
+    the plain FP64 path on the same instance.  Checked at this size: both
+    sweeps are the oracle's exact sweep of their potentials, the potentials
+    stay in [0, 1], every round's lower bound stays below both cuts, and the
+    precision form's cut is within the stated 1e-4 of the FP64 path's."""
+    g = gen.grid3d_seg(256, seed=2)
+    vals, xs = [], []
+    for kw in (dict(precision=1, refine_every=20), dict()):
+        with P.MinCut.from_graph(g, rounds=40, cg_rtol=1e-8, solver=1, **kw) as mc:
+            assert mc.spmv_variant()[0] == 4                   # the scaled marching SpMV
+            rc, st = mc.solve()
+            x = mc.potentials()
+            inS, val, k = mc.cut()
+        assert rc == P.OK
+        So, vo, ko, _ = oracle_mod.sweep(g, x)
+        assert val == vo and k == ko and np.array_equal(inS, So)
+        for l, r in enumerate(st):
+            assert r["vmin"] >= -1e-6 and r["vmax"] <= 1 + 1e-6, l
+            assert r["lower_bound"] <= val * (1 + 1e-12), l
+        vals.append(val)
+        xs.append(x)
+    rel = abs(vals[0] - vals[1]) / vals[1]
+    say(f"256^3: precision form cut {vals[0]!r}, FP64 cut {vals[1]!r} (relative {rel:.1e}); "
+        f"largest potential difference {np.max(np.abs(xs[0] - xs[1])):.1e}")
+    assert rel <= 1e-4
