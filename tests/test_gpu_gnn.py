@@ -190,3 +190,63 @@ def test_trained_network_saves_cg_work(P):
     say(f"  total CG iterations: plain {tot_p}, warm {tot_w}")
     assert tot_w < tot_p
     net.close()
+
+
+def induced_subgraph(g, keep):
+    """The subgraph of g on the nodes where keep is True (s and t kept): nodes
+    renumbered in ascending id, s and t last; returns it and the old ids."""
+    from gen.graphs import Graph
+    keep = keep.copy()
+    keep[g.s] = keep[g.t] = True
+    old = np.flatnonzero(keep)
+    old = old[(old != g.s) & (old != g.t)]
+    new = -np.ones(g.n, np.int64)
+    new[old] = np.arange(old.shape[0])
+    n = old.shape[0]
+    new[g.s], new[g.t] = n, n + 1
+    m = keep[g.eu] & keep[g.ev]
+    return Graph(n + 2, n, n + 1, new[g.eu[m]], new[g.ev[m]], g.cap[m]), old
+
+
+def test_fullsize_192_forward_matches_oracle(P, G):
+    """The network at the full size of the warm-start workload (a held-out
+    192^3 segmentation grid, 7.1M nodes) in the launch configuration the
+    benchmark uses (multi-workgroup handle), against the oracle's forward
+    pass of the same weights at 200 sampled nodes.  A node's prediction
+    depends only on nodes within 3 hops (three message-passing layers), and
+    their features and normalised rows only on nodes within 4, so the oracle
+    runs once on the union of the sampled nodes' 4-hop balls.  (The log eps
+    head averages over every node; it is compared at smaller sizes.)"""
+    N = 192
+    g, I = seg(N, 20000)
+    net = P.Gnn(seed=29)
+    flat = net.get_params().astype(np.float64)
+    xs = start_potentials(g, 5)
+    with P.MinCut.from_graph(g, solver=1, rounds=40, cg_rtol=1e-8) as mc:
+        x, _ = net.predict(mc, I, x_start=xs)
+    net.close()
+    assert x[g.s] == 1.0 and x[g.t] == 0.0
+    assert np.all((x >= 0.0) & (x <= 1.0))
+    rng = np.random.default_rng(3)
+    samples = rng.choice(N ** 3, 200, replace=False)
+    keep = np.zeros(g.n, bool)
+    sx, sy, sz = samples % N, (samples // N) % N, samples // (N * N)
+    r = np.arange(-4, 5)
+    for dx in r:
+        for dy in r:
+            for dz in r:
+                if abs(dx) + abs(dy) + abs(dz) > 4:
+                    continue
+                X, Y, Z = sx + dx, sy + dy, sz + dz
+                ok = (X >= 0) & (X < N) & (Y >= 0) & (Y < N) & (Z >= 0) & (Z < N)
+                keep[(X + N * Y + N * N * Z)[ok]] = True
+    sub, old = induced_subgraph(g, keep)
+    I_sub = np.concatenate([I[old], [0.0, 0.0]])
+    xs_sub = np.concatenate([xs[old], [1.0, 0.0]])
+    feats, A, ids = G.graph_inputs(sub, I_sub, xs_sub)
+    xo, _ = G.predict(flat, feats, A)
+    pos = np.searchsorted(old, samples)
+    err = np.abs(x[samples] - xo[pos])
+    say(f"gnn forward 192^3: {sub.n - 2} nodes in the sampled balls; xhat at 200 nodes "
+        f"max {err.max():.2e} mean {err.mean():.2e}")
+    assert err.max() <= XHAT_TOL
