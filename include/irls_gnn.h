@@ -77,7 +77,12 @@ irls_status irls_gnn_loss_grad(irls_gnn_t g, irls_mincut_t h, const double *inte
 /* One Adam step with the last gradient (FP32 moments, bias-corrected). */
 irls_status irls_gnn_adam_step(irls_gnn_t g, double lr, double beta1, double beta2, double eps);
 
+/* Free the network and its device memory (NULL is a no-op). */
 void irls_gnn_destroy(irls_gnn_t g);
+
+/* Text of the last error of g, or of the calling thread's last failed
+ * irls_gnn_create when g == NULL.  Valid until the next call on the same
+ * network / thread. */
 const char *irls_gnn_last_error(irls_gnn_t g);
 
 #ifdef __cplusplus

@@ -124,6 +124,8 @@ typedef struct {
                                  less the residual. */
 } irls_round_stats;
 
+/* Fills *o with the defaults given beside each field, struct_size included
+ * (NULL is a no-op). */
 void irls_options_default(irls_options *o);
 
 /* Build a handle for graph G.
