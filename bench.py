@@ -355,6 +355,8 @@ def main():
     ap.add_argument("--gnn-epochs", type=int, default=30)
     ap.add_argument("--early-stop-gap", type=float, default=0.01,
                     help="also time the certified-gap stopping rule (stop_gap) on the same instance; 0: skip")
+    ap.add_argument("--precision-form", type=int, default=1,
+                    help="1: also time the precision form on the same instance; 0: skip")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run 5 plain device copies of MIB MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -468,6 +470,26 @@ def main():
         print(f"[bench] stop_gap {args.early_stop_gap}: rounds 0..{L}, {early['cg_iters']} CG iterations, "
               f"{dte*1e3:.1f} ms to the sweep cut {vale:.10g}; two-level {vale2:.10g}", file=sys.stderr, flush=True)
 
+    # The precision form (FP32 conductances, SpMV and CG vectors; FP64
+    # potentials, dots and residual replacement) on the same instance, beside
+    # the configured FP64 run: its time-to-cut and its cut against the FP64 cut.
+    precision = None
+    if args.precision_form and info["solver"] == 1 and opts.get("precision", 0) == 0:
+        with P.MinCut.from_graph(g, stream=stream, precision=1, refine_every=20, **opts) as mp:
+            mp.solve()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, stp = mp.solve()
+            _, valp, _ = mp.cut()
+            torch.cuda.synchronize()
+            dtp = time.perf_counter() - t0
+        precision = {"seconds_to_cut": round(dtp, 4), "cuts_per_s": round(1.0 / dtp, 3),
+                     "speedup_vs_fp64": round(ms_step / 1000.0 / dtp, 3),
+                     "cg_iters": int(sum(r["cg_iters"] for r in stp)), "cut_value": valp,
+                     "relative_cut_difference_vs_fp64": abs(valp - val) / val}
+        print(f"[bench] precision form: {dtp*1e3:.1f} ms to the cut {valp:.10g} "
+              f"({precision['relative_cut_difference_vs_fp64']:.1e} from the FP64 cut)", file=sys.stderr, flush=True)
+
     if args.calibrate_copy > 0:
         nel = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(nel, dtype=torch.float64, device="cuda")
@@ -502,6 +524,7 @@ def main():
                    # capacity) and ||CBx||_1 bracket the minimum cut: delta of a cut
                    # is at most (cut - bound) / bound
                    "early_stop": early,
+                   "precision_form": precision,
                    "certified": {"lower_bound": st[-1]["lower_bound"], "l1": st[-1]["l1"],
                                  "sweep_delta_at_most": (val - st[-1]["lower_bound"]) / st[-1]["lower_bound"],
                                  "two_level_delta_at_most":
