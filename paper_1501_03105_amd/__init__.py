@@ -149,6 +149,22 @@ def _ptr(a, dtype):
     return arr.ctypes.data, arr, False
 
 
+def _ptr_as(a, dtype, on_device):
+    """_ptr with the array moved where the handle reads its inputs: a CUDA
+    tensor for a handle created with inputs_on_device, host memory otherwise."""
+    if a is None:
+        return None, None, False
+    if on_device:
+        import torch
+        tdt = {np.int64: torch.int64, np.float64: torch.float64}[dtype]
+        t = (a if _is_torch(a) else torch.as_tensor(np.asarray(a))).to(device="cuda", dtype=tdt).contiguous()
+        return t.data_ptr(), t, True
+    if _is_torch(a):
+        a = a.detach().cpu().numpy()
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, arr, False
+
+
 def _stream_ptr(stream):
     if stream is None:
         return None
@@ -213,7 +229,7 @@ class MinCut(_RowLanes):
     def solve(self, x0=None, allow_maxit=True):
         """Run all rounds. Returns (status, per-round stats list)."""
         st = (RoundStats * (self.opt.rounds + 1))()
-        px, keep, _ = _ptr(x0, np.float64)
+        px, keep, _ = _ptr_as(x0, np.float64, self.opt.inputs_on_device)
         rc = lib().irls_mincut_solve(self.h, px, st)
         if rc not in (OK, WARN_CG_MAXIT) or (rc == WARN_CG_MAXIT and not allow_maxit):
             raise self._err(rc)
@@ -222,7 +238,7 @@ class MinCut(_RowLanes):
     def solve_range(self, start, rounds, eps_first=-1.0, x0=None):
         """irls_mincut_solve_range: start 0 (options), 1 (continue), 2 (from x0)."""
         st = (RoundStats * (rounds + 1))()
-        px, keep, _ = _ptr(x0, np.float64)
+        px, keep, _ = _ptr_as(x0, np.float64, self.opt.inputs_on_device)
         rc = lib().irls_mincut_solve_range(self.h, start, px, float(eps_first), rounds, st)
         if rc not in (OK, WARN_CG_MAXIT):
             raise self._err(rc)
@@ -241,9 +257,10 @@ class MinCut(_RowLanes):
 
     def update_capacities(self, eu, ev, cap):
         """irls_mincut_update_capacities: same structure, new capacities."""
-        pu, ku, _ = _ptr(eu, np.int64)
-        pv, kv, _ = _ptr(ev, np.int64)
-        pc, kc, _ = _ptr(cap, np.float64)
+        dev = self.opt.inputs_on_device
+        pu, ku, _ = _ptr_as(eu, np.int64, dev)
+        pv, kv, _ = _ptr_as(ev, np.int64, dev)
+        pc, kc, _ = _ptr_as(cap, np.float64, dev)
         m = 0 if ku is None else int(ku.shape[0] if hasattr(ku, "shape") else len(ku))
         rc = lib().irls_mincut_update_capacities(self.h, m, pu, pv, pc)
         if rc != OK:
@@ -277,7 +294,7 @@ class MinCut(_RowLanes):
         return x
 
     def set_potentials(self, x):
-        px, keep, _ = _ptr(x, np.float64)
+        px, keep, _ = _ptr_as(x, np.float64, self.opt.inputs_on_device)
         rc = lib().irls_mincut_set_potentials(self.h, px)
         if rc != OK:
             raise self._err(rc)

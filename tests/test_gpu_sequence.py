@@ -109,3 +109,35 @@ def test_sequence_warm_continuation(P, oracle_mod):
         f"{(vf - mu) / mu:.2e} / {(vf2 - mu) / mu:.2e}")
     for v in (vw, vw2, vf, vf2):
         assert v >= mu * (1 - 1e-12)
+
+
+def test_update_and_potentials_from_either_memory(P):
+    """The binding moves arrays to where the handle reads its inputs: torch
+    CUDA tensors on a handle created from host arrays, and host arrays on a
+    handle created from device tensors, give the host-only results."""
+    import torch
+    g1 = gen.grid2d(32, 32, seed=3)
+    g2 = perturbed(g1, seed=5)
+    opts = dict(rounds=12, cg_rtol=1e-10, solver=1)
+    cuda = lambda a: torch.as_tensor(np.asarray(a)).cuda()
+    with P.MinCut.from_graph(g1, **opts) as ref:
+        ref.update_capacities(g2.eu, g2.ev, g2.cap)
+        ref.solve()
+        x_ref = ref.potentials()
+        ref.set_potentials(x_ref)
+        _, c_ref = ref.solve_range(1, 4, eps_first=1e-3)
+        y_ref = ref.potentials()
+    with P.MinCut.from_graph(g1, **opts) as a:                    # host handle, device arrays
+        a.update_capacities(cuda(g2.eu), cuda(g2.ev), cuda(g2.cap))
+        a.solve()
+        assert np.array_equal(a.potentials(), x_ref)
+        a.set_potentials(cuda(x_ref))
+        _, ca = a.solve_range(1, 4, eps_first=1e-3)
+        assert ca == c_ref and np.array_equal(a.potentials(), y_ref)
+    with P.MinCut(g1.n, cuda(g1.eu), cuda(g1.ev), cuda(g1.cap), g1.s, g1.t, **opts) as b:   # device handle
+        b.update_capacities(g2.eu, g2.ev, g2.cap)
+        b.solve()
+        assert np.array_equal(b.potentials(), x_ref)
+        b.set_potentials(x_ref)
+        _, cb = b.solve_range(1, 4, eps_first=1e-3)
+        assert cb == c_ref and np.array_equal(b.potentials(), y_ref)
