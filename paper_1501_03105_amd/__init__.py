@@ -465,6 +465,8 @@ class Gnn:
     def _dptr(a):
         if a is None:
             return None, None
+        if _is_torch(a):                      # the network's inputs are host arrays
+            a = a.detach().cpu().numpy()
         a = np.ascontiguousarray(a, np.float64)
         return a.ctypes.data_as(C.POINTER(C.c_double)), a
 
@@ -491,7 +493,7 @@ class Gnn:
         return le.value
 
     def loss_grad(self, mc, y, log_eps_target, lam=0.1, intensity=None, x_start=None, want_grad=False):
-        y = np.ascontiguousarray(y, np.float64)
+        _, y = self._dptr(y)
         pi, ki = self._dptr(intensity)
         px, kx = self._dptr(x_start)
         loss = C.c_double()
