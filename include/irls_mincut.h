@@ -328,7 +328,7 @@ irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, doub
  * before the call are restored after it, so the handle's state is unchanged
  * but for the table.  The next solve runs (and a batch re-captures its HIP
  * graph) with the chosen table.
- *   rounds  0 .. the handle's rounds; reps >= 1
+ *   rounds  0 .. the handle's rounds; reps 1 .. 100
  *   lanes   NULL or 6 int32 (host): the table chosen
  * For a single-graph handle on the multi-workgroup solver in the CSR format,
  * irls_mincut_autotune instead tunes that path's rows per wavefront (its

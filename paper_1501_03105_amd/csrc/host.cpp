@@ -1853,7 +1853,7 @@ static irls_status autotune_csr(irls_mincut_t h, int32_t reps, int32_t *lanes) {
 
 irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
-  if (reps < 1) { h->err = "reps must be >= 1"; return IRLS_ERR_OPTIONS; }
+  if (reps < 1 || reps > 100) { h->err = "reps must lie in 1..100"; return IRLS_ERR_OPTIONS; }
   if (!h->batch && h->solver == 1) {
     try {
       return autotune_csr(h, reps, lanes);
@@ -1863,8 +1863,8 @@ irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, 
     }
   }
   if (!h->batch && h->solver != 2) { h->err = "autotuning applies to the resident solver (solver 2 or a batch)"; return IRLS_ERR_OPTIONS; }
-  if (rounds < 0 || rounds > h->opt.rounds || reps < 1) {
-    h->err = "rounds must lie in [0, the handle's rounds] and reps >= 1";
+  if (rounds < 0 || rounds > h->opt.rounds) {
+    h->err = "rounds must lie in [0, the handle's rounds]";
     return IRLS_ERR_OPTIONS;
   }
   if (h->opt.init == 2 && !h->solved) {

@@ -193,7 +193,7 @@ def test_row_lanes_errors(P):
             with pytest.raises(P.IrlsError) as e:
                 mb.set_row_lanes(bad)
             assert e.value.code == P.ERR_OPTIONS
-        for rounds, reps in ((-1, 1), (31, 1), (1, 0)):
+        for rounds, reps in ((-1, 1), (31, 1), (1, 0), (1, 101)):
             with pytest.raises(P.IrlsError) as e:
                 mb.autotune(rounds, reps)
             assert e.value.code == P.ERR_OPTIONS
