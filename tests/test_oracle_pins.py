@@ -148,6 +148,52 @@ def test_path_lower_bound_by_hand(oracle_mod):
         eps *= 0.5
 
 
+def test_record_l1_and_s_eps_by_hand(oracle_mod):
+    """||CBx||_1 and the smoothed objective S_eps of every round record, by
+    hand (eq. l1-min and the smoothed objective of Section 2.1): on a path
+    the potentials of every round follow from the series circuit alone, so
+    both sums are written out from closed-form potentials, never from the
+    oracle's.  S_eps of round l is taken at the next round's eps (eps0 for
+    round 0).  Both conductance forms, and a triangle with an s-t edge (it
+    is cut by every s-t cut, so it adds c to ||CBx||_1 and c*sqrt(1+eps) to
+    S_eps)."""
+    caps = [0.9, 0.35, 0.8, 0.6, 0.25, 1.1, 0.7]
+    g = path_graph(caps)
+    k = len(caps) - 1
+    for form in (0, 1):
+        def cond(c, d, eps):
+            return c / np.sqrt(d * d + eps) if form == 0 else c * c / np.sqrt((c * d) ** 2 + eps)
+
+        def smooth(c, d, eps):
+            return c * np.sqrt(d * d + eps) if form == 0 else np.sqrt((c * d) ** 2 + eps)
+
+        pot = [1.0] + list(series_potentials(caps)) + [0.0]        # round 0: W = C
+        eps = 0.1
+        for T in range(0, 10):
+            _, R, _ = oracle_mod.irls(g, rounds=T, cg_rtol=1e-14, weight_form=form)
+            d = [pot[j] - pot[j + 1] for j in range(k + 1)]
+            eps_next = 0.1 if T == 0 else eps * 0.5
+            l1 = sum(c * abs(dj) for c, dj in zip(caps, d))
+            se = sum(smooth(c, dj, eps_next) for c, dj in zip(caps, d))
+            assert R[T]["l1"] == pytest.approx(l1, rel=1e-10), (form, T)
+            assert R[T]["s_eps"] == pytest.approx(se, rel=1e-10), (form, T)
+            eps = eps_next if T > 0 else 0.1
+            pot = [1.0] + list(series_potentials([cond(c, dj, eps) for c, dj in zip(caps, d)])) + [0.0]
+    # one non-terminal u between s and t, plus the s-t edge itself
+    a, b, c = 0.7, 0.3, 0.45
+    g = mk(3, 1, 2, [(1, 0, a), (0, 2, b), (1, 2, c)])
+    v, eps = a / (a + b), 0.1
+    for T in range(0, 8):
+        _, R, _ = oracle_mod.irls(g, rounds=T, cg_rtol=1e-14)
+        eps_next = 0.1 if T == 0 else eps * 0.5
+        assert R[T]["l1"] == pytest.approx(a * (1 - v) + b * v + c, rel=1e-12), T
+        assert R[T]["s_eps"] == pytest.approx(a * np.sqrt((1 - v) ** 2 + eps_next) + b * np.sqrt(v * v + eps_next)
+                                              + c * np.sqrt(1 + eps_next), rel=1e-12), T
+        eps = eps_next if T > 0 else 0.1
+        gs, gt = a / np.sqrt((1 - v) ** 2 + eps), b / np.sqrt(v * v + eps)
+        v = gs / (gs + gt)
+
+
 def test_lower_bound_below_min_cut(oracle_mod):
     """Every round's lower bound lies below the exact minimum cut, round 0's
     is its flow value E0 less the residual (there |x_u - x_v| <= 1, so
