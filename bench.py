@@ -4,13 +4,15 @@
 A step is one whole pass of the hot path on one synthetic instance already
 resident in HBM: every IRLS round (reweight + Jacobi-PCG) followed by the
 sweep cut, i.e. irls_mincut_solve + irls_mincut_cut.  The default workload is
-the 128^3 6-connected segmentation grid (2,097,152 non-terminal nodes,
-6,242,304 interior edges), FP64, 40 rounds with eps halved from 0.1, CG to a
-relative residual of 1e-8.
+the 256^3 6-connected segmentation grid (16,777,216 non-terminal nodes,
+50,135,040 interior edges), plain FP64, 40 rounds with eps halved from 0.1, CG
+to a relative residual of 1e-8; beside it the same instance in the precision
+form (FP32 SpMV, FP64 dots and residual replacement).
 
 Prints one JSON line with the throughput (cuts/s), the roofline of the SpMV
-kernel (algorithmic bytes / measured launch time vs 8 TB/s) and the CPU
-oracle timed on a bounded sample of the same workload.
+kernel (algorithmic bytes / its mean in-solve launch time, from HIP events
+around each launch during the timed steps, vs 8 TB/s) and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -111,6 +113,27 @@ def profiled_traffic(kernel, workload):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def golden_run(workload):
+    """The oracle's full run of this workload, if one is stored (written on the
+    CPU by tests/golden/make_golden_fullsize.py, which calls only the oracle)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, opts, gpu_iters_total, budget_s):
     """Oracle time per CG iteration on the first rounds of the same instance,
     scaled to the GPU run's total CG iterations, plus the oracle sweep."""
@@ -133,6 +156,7 @@ def cpu_baseline(g, opts, gpu_iters_total, budget_s):
     est = per_it * gpu_iters_total + t_sweep
     return {
         "value": 1.0 / est, "unit": "cuts/s", "cores": oracle.max_threads(), "kind": "oracle",
+        "cpu_model": cpu_model(), "nproc": os.cpu_count(),
         "sample": (f"oracle IRLS rounds 0..{rounds} of the same instance ({it_total} CG iterations "
                    f"in {t_total:.1f} s) + one oracle sweep ({t_sweep:.1f} s); time-to-cut "
                    f"estimated as per-iteration cost x the GPU run's {gpu_iters_total} CG iterations "
@@ -348,7 +372,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="seg128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="seg256", choices=sorted(WORKLOADS))
+    ap.add_argument("--kernel-events", type=int, default=16, metavar="EVERY",
+                    help="N >= 1: HIP events around the SpMV launches of CG iterations 0, N, 2N, ... of "
+                         "every round of the timed steps (the roofline's launch time); 0: none (the "
+                         "roofline then falls back to back-to-back launches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--kernel-reps", type=int, default=100)
@@ -395,10 +423,18 @@ def main():
         _, val, k = mc.cut()
         return st, val
 
+    warm_ms = []
     for i in range(args.warmup):
+        ts = time.perf_counter()
         st, val = step()
-        print(f"[bench] warmup {i}: cut {val:.10g}, CG iterations {sum(r['cg_iters'] for r in st)}",
-              file=sys.stderr, flush=True)
+        warm_ms.append(1000.0 * (time.perf_counter() - ts))
+        print(f"[bench] warmup {i}: cut {val:.10g}, CG iterations {sum(r['cg_iters'] for r in st)}, "
+              f"{warm_ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+    # the SpMV's in-solve launch times: an event pair around each of its
+    # launches in the timed steps (the warm-up steps run without them)
+    events = args.kernel_events > 0 and info["solver"] == 1
+    if events:
+        mc.set_kernel_timing(0, args.kernel_events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     step_ms = []
@@ -406,9 +442,12 @@ def main():
         ts = time.perf_counter()
         st, val = step()                     # the cut's readback synchronises the stream
         step_ms.append(1000.0 * (time.perf_counter() - ts))
-        print(f"[bench] step {i} done", file=sys.stderr, flush=True)
+        print(f"[bench] step {i} done ({step_ms[-1]:.1f} ms)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ktime = mc.kernel_timing() if events else None
+    if events:
+        mc.set_kernel_timing(-1)
     iters = sum(r["cg_iters"] for r in st)
     ms_step = 1000.0 * dt / args.steps
     # the two-level rounding of the same potentials, timed on its own (it is
@@ -424,22 +463,35 @@ def main():
 
     roof = None
     if info["solver"] == 1:
-        spmv_ms = mc.time_kernel(0, args.kernel_reps)
+        # back-to-back launches on the last round's system, for comparison
+        b2b_ms = mc.time_kernel(0, args.kernel_reps)
         # the update alternates between odd and even iterations (they differ
         # on the scaled system): the mean of the two
         upd_ms = 0.5 * (mc.time_kernel(1, args.kernel_reps) + mc.time_kernel(2, args.kernel_reps))
         variant, spmv_grid = mc.spmv_variant()
         kname = mc.SPMV_KERNELS[variant]
         nbytes = spmv_bytes(info, opts.get("precision", 0), variant)
+        if ktime and ktime["n_working"] > 0:
+            spmv_ms = ktime["ms_working"] / ktime["n_working"]
+            how = (f"mean of {ktime['n_working']} SpMV launches that did work in the {args.steps} "
+                   f"timed steps: those of CG iterations 0, {args.kernel_events}, "
+                   f"{2 * args.kernel_events}, ... of every round, each between two HIP events on the "
+                   f"solve's stream ({ktime['n_all'] - ktime['n_working']} sampled launches queued past "
+                   f"convergence, which return at once, are left out)")
+        else:
+            spmv_ms = b2b_ms
+            how = f"mean of {args.kernel_reps} back-to-back launches on the last round's system"
         achieved = nbytes / (spmv_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(kname, args.workload), "kernel": kname,
-                "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5), "workgroups": spmv_grid,
+                "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5), "launch_time": how,
+                "back_to_back_launch_ms": round(b2b_ms, 5), "workgroups": spmv_grid,
                 "update_kernel_ms": round(upd_ms, 5)}
-        print(f"[bench] spmv {spmv_ms*1e3:.1f} us ({achieved:.0f} GB/s), update {upd_ms*1e3:.1f} us",
-              file=sys.stderr, flush=True)
+        print(f"[bench] spmv {spmv_ms*1e3:.1f} us in the solve ({achieved:.0f} GB/s; back to back "
+              f"{b2b_ms*1e3:.1f} us), update {upd_ms*1e3:.1f} us", file=sys.stderr, flush=True)
     mc.close()
+    gold = golden_run(args.workload)
 
     # A mode of the library beside the configured run: the same instance with
     # the certified-gap stopping rule (rounds stop once ||CBx||_1 and the
@@ -487,6 +539,9 @@ def main():
                      "speedup_vs_fp64": round(ms_step / 1000.0 / dtp, 3),
                      "cg_iters": int(sum(r["cg_iters"] for r in stp)), "cut_value": valp,
                      "relative_cut_difference_vs_fp64": abs(valp - val) / val}
+        if gold:
+            ov = gold["sweep"]["value"]
+            precision["relative_cut_error_vs_fp64_oracle"] = abs(valp - ov) / ov
         print(f"[bench] precision form: {dtp*1e3:.1f} ms to the cut {valp:.10g} "
               f"({precision['relative_cut_difference_vs_fp64']:.1e} from the FP64 cut)", file=sys.stderr, flush=True)
 
@@ -505,6 +560,17 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(g, opts, iters, args.cpu_budget)
+        if gold:
+            cpu["full_run"] = {"seconds": round(gold["timing"]["seconds"], 1),
+                               "threads": gold["timing"]["threads"], "cpu_model": gold["timing"]["cpu_model"],
+                               "cg_iters": gold["cg_iters_total"], "cut_value": gold["sweep"]["value"],
+                               "where": "the oracle's whole run of this instance (all rounds + sweep), "
+                                        "timed when its golden file was written on the build host"}
+    oracle_ref = None
+    if gold:
+        ov = gold["sweep"]["value"]
+        oracle_ref = {"cut_value": ov, "k_star": gold["sweep"]["k_star"], "cg_iters": gold["cg_iters_total"],
+                      "gpu_cut_equals_oracle": val == ov, "relative_cut_error": abs(val - ov) / ov}
 
     out = {
         "metric": "IRLS s-t min-cut time-to-cut, as cuts per second (solve + sweep, graph resident)",
@@ -518,6 +584,8 @@ def main():
                    "solver": info["solver"], "cg_iters_per_cut": iters,
                    "step_ms": [round(t, 3) for t in step_ms],
                    "median_step_ms": round(sorted(step_ms)[len(step_ms) // 2], 3),
+                   "warmup_step_ms_without_events": [round(t, 3) for t in warm_ms],
+                   "oracle": oracle_ref,
                    "cg_iters_per_round": [int(r["cg_iters"]) for r in st], "cut_value": val,
                    "setup_s": round(t_setup, 3), "two_level": two,
                    # the last round's lower bound (its flow scaled to respect every

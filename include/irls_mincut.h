@@ -262,6 +262,23 @@ irls_status irls_mincut_info(irls_mincut_t h, int64_t *n_nonterminal, int64_t *n
  * the resident solver or a batch. */
 irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *grid);
 
+/* Tile shape of the marching SpMV (variant 3 or 4 above; Section 3.1's PCG
+ * product on grids).  A workgroup of `threads` threads (256 or 512) owns a
+ * tile of one plane and walks a chunk of planes:
+ *   lines 0:   `threads` consecutive groups of rows of the plane (any grid);
+ *   lines >= 1 (3-D grids): that many consecutive grid lines (offset off[1])
+ *              by threads / lines row groups of each line.
+ * The tile's two boundary lines are re-read by the neighbouring tiles, so
+ * taller tiles move fewer bytes.  threads = lines = 0 restores the default
+ * (256, 0).  The shape changes no result beyond the rounding order of the
+ * SpMV's partial dot products.  Errors: IRLS_ERR_OPTIONS when the handle does
+ * not march (batch, resident solver, CSR) or cannot take the shape (lines
+ * must divide threads; a tile no wider or taller than a plane).
+ * irls_mincut_march_tile reports the shape in use and the planes per
+ * workgroup (all 0 without the marching SpMV); pointers may be NULL. */
+irls_status irls_mincut_set_march_tile(irls_mincut_t h, int32_t threads, int32_t lines);
+irls_status irls_mincut_march_tile(irls_mincut_t h, int32_t *threads, int32_t *lines, int32_t *planes);
+
 /* Time one hot kernel of the CG loop on the handle's stream with HIP events:
  * `which` 0 = SpMV (with its fused direction update), 1 = the CG vector
  * update of an odd iteration, 2 = of an even one (they differ only on the
@@ -271,6 +288,28 @@ irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *
  * (p, q; potentials untouched) -- call solve again before resuming. */
 irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps,
                                     double *avg_ms);
+
+/* In-solve timing of one kernel of the CG iteration (Section 3.1's PCG; the
+ * SpMV is its dominant cost).  From this call on, every solve of the handle
+ * brackets the launches of that kernel for CG iterations 0, every,
+ * 2 * every, ... of each round with a HIP event pair on the handle's stream,
+ * and the totals are reset:
+ *   which  -1 off, 0 the SpMV (with its fused direction update), 1 the vector
+ *          update, 2 the FP64 residual replacement of the precision form
+ *   every  >= 1: the sampling stride (each event pair adds a marker before and
+ *          after its launch, a few microseconds; a stride keeps that small)
+ * Needs a single-graph handle on the multi-workgroup solver (solver 1), and
+ * precision 1 for which = 2; IRLS_ERR_OPTIONS otherwise.  The solve's results
+ * are unchanged. */
+irls_status irls_mincut_set_kernel_timing(irls_mincut_t h, int32_t which, int32_t every);
+
+/* Totals of the in-solve timing since irls_mincut_set_kernel_timing: the
+ * summed duration (ms) and count of the timed launches that did work (in
+ * each round, the launches of CG iterations below its converged count) and of
+ * all timed launches (launches queued past convergence return at once).  Any
+ * pointer may be NULL (host memory). */
+irls_status irls_mincut_kernel_timing(irls_mincut_t h, double *ms_working, int64_t *n_working,
+                                      double *ms_all, int64_t *n_all);
 
 /* Free the handle and all its device memory (NULL is a no-op). */
 void irls_mincut_destroy(irls_mincut_t h);
@@ -335,14 +374,18 @@ irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, doub
  * SpMV and per-round CSR kernels): it times 20 * reps SpMV launches
  * (irls_mincut_time_kernel, which 0) on the last solve's system at each of
  * 1, 2, 4, ..., 64 rows per wavefront, keeps the fastest (again by at least
- * 2 %), and writes lanes[0] = 64 / rows per wavefront, lanes[1..5] = 0;
- * rounds is ignored.  It needs a solved handle (else IRLS_ERR_NOT_SOLVED)
- * and has nothing to tune in the diagonal format (IRLS_ERR_OPTIONS).
- * Errors (both): IRLS_ERR_OPTIONS for a handle that does not use the
- * resident solver or the CSR format, or for values out of range; autotune
- * with init 2 before the potentials are set: IRLS_ERR_NOT_SOLVED.  A device
- * error during the timing solves leaves the potentials undefined and the
- * handle unsolved. */
+ * 2 %), and writes lanes[0] = 64 / rows per wavefront, lanes[1..5] = 0.
+ * On the marching SpMV (diagonal format) it tunes the tile shape the same
+ * way over every shape irls_mincut_set_march_tile accepts here (256 or 512
+ * threads; 0, 1, 2, 4, ..., 32 lines) and writes lanes[0] = threads,
+ * lanes[1] = lines, lanes[2..5] = 0.  For both, rounds is ignored; a solved
+ * handle is needed (else IRLS_ERR_NOT_SOLVED); a diagonal format without
+ * the marching SpMV has nothing to tune (IRLS_ERR_OPTIONS).
+ * Errors (all): IRLS_ERR_OPTIONS for a handle that does not use the
+ * resident solver, the CSR format or the marching SpMV, or for values out of
+ * range; autotune with init 2 before the potentials are set:
+ * IRLS_ERR_NOT_SOLVED.  A device error during the timing solves leaves the
+ * potentials undefined and the handle unsolved. */
 irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes);
 irls_status irls_mincut_autotune(irls_mincut_t h, int32_t rounds, int32_t reps, int32_t *lanes);
 

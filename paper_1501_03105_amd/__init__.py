@@ -81,6 +81,11 @@ def lib():
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.irls_mincut_time_kernel.argtypes = [H, C.c_int32, C.c_int32, PF64]
         L.irls_mincut_spmv_kernel.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.irls_mincut_set_kernel_timing.argtypes = [H, C.c_int32, C.c_int32]
+        L.irls_mincut_set_march_tile.argtypes = [H, C.c_int32, C.c_int32]
+        L.irls_mincut_march_tile.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                             C.POINTER(C.c_int32)]
+        L.irls_mincut_kernel_timing.argtypes = [H, PF64, P64, PF64, P64]
         L.irls_mincut_destroy.argtypes = [H]
         L.irls_mincut_destroy.restype = None
         L.irls_mincut_last_error.argtypes = [H]
@@ -95,7 +100,9 @@ def lib():
         for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "update_capacities",
                   "cheeger_bracket", "potentials",
                   "set_potentials",
-                  "info", "time_kernel", "spmv_kernel", "create_batch", "solve_batch", "cut_batch",
+                  "info", "time_kernel", "spmv_kernel", "set_kernel_timing", "kernel_timing",
+                  "set_march_tile", "march_tile",
+                  "create_batch", "solve_batch", "cut_batch",
                   "set_row_lanes", "autotune"):
             getattr(L, "irls_mincut_" + f).restype = C.c_int
         PF32 = C.POINTER(C.c_float)
@@ -331,6 +338,36 @@ class MinCut(_RowLanes):
         if rc != OK:
             raise self._err(rc)
         return ms.value
+
+    def set_march_tile(self, threads, lines):
+        """irls_mincut_set_march_tile: (0, 0) restores the default shape."""
+        rc = lib().irls_mincut_set_march_tile(self.h, threads, lines)
+        if rc != OK:
+            raise self._err(rc)
+
+    def march_tile(self):
+        """Returns (threads, lines, planes per workgroup) of the marching SpMV (zeros if none)."""
+        a, b, c = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        rc = lib().irls_mincut_march_tile(self.h, C.byref(a), C.byref(b), C.byref(c))
+        if rc != OK:
+            raise self._err(rc)
+        return a.value, b.value, c.value
+
+    def set_kernel_timing(self, which, every=1):
+        """irls_mincut_set_kernel_timing: -1 off, 0 SpMV, 1 update, 2 residual
+        replacement; launches of iterations 0, every, 2 * every, ... are timed."""
+        rc = lib().irls_mincut_set_kernel_timing(self.h, which, every)
+        if rc != OK:
+            raise self._err(rc)
+
+    def kernel_timing(self):
+        """Returns dict(ms_working, n_working, ms_all, n_all) of the in-solve timing."""
+        mw, ma = C.c_double(0), C.c_double(0)
+        nw, na = C.c_int64(0), C.c_int64(0)
+        rc = lib().irls_mincut_kernel_timing(self.h, C.byref(mw), C.byref(nw), C.byref(ma), C.byref(na))
+        if rc != OK:
+            raise self._err(rc)
+        return dict(ms_working=mw.value, n_working=nw.value, ms_all=ma.value, n_all=na.value)
 
     def close(self):
         if getattr(self, "h", None):

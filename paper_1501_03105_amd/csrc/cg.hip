@@ -275,7 +275,7 @@ __device__ bool cg_iteration_finish(const CGArgs<T> &a, const IterStartLoads &l,
   Scalars *sc = a.sc;
   const int nb = a.grid_main;
   const int64_t i = l.i;
-  __shared__ double s_start[3 * (kBlock / 64)];      // used once per kernel
+  __shared__ double s_start[3 * (kMaxBlock / 64)];   // used once per kernel
   double t[3] = {l.part[0], l.part[1], l.done != 0 ? 1.0 : 0.0};
   block_allreduce_once<3, 0x4u>(t, s_start);
   if (t[2] != 0.0) return false;
@@ -590,33 +590,69 @@ __device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int
   march_load_p(a, pin, u0, s);
 }
 
+// Tiles of one plane of the marching SpMV, of BS row groups (R rows each).
+//   ty = 0: BS consecutive row groups of the plane (any grid);
+//   ty >= 1 (3-D grids, where a plane of P rows is P / N lines of N = off[1]
+//   rows): ty consecutive lines by tx = BS / ty row groups of each line.
+// Tiles are numbered line block by line block, so consecutive tiles, which
+// run on the same XCD, are neighbours.
+struct MarchTiles {
+  int64_t N, lines, gx, tx, tiles_x, tiles;
+  int32_t TY;
+};
+
+template <int R, int BS>
+__host__ __device__ inline MarchTiles march_tiles(int64_t P, int64_t N1, int32_t ty) {
+  MarchTiles m;
+  m.TY = ty;
+  if (ty == 0) {                                   // the plane as one line
+    m.N = P;
+    m.lines = 1;
+    m.gx = P / R;
+    m.tx = BS;
+  } else {
+    m.N = N1;
+    m.lines = P / N1;
+    m.gx = N1 / R;
+    m.tx = BS / ty;
+  }
+  m.tiles_x = (m.gx + m.tx - 1) / m.tx;
+  m.tiles = m.tiles_x * (ty == 0 ? 1 : (m.lines + ty - 1) / ty);
+  return m;
+}
+
 // Diagonal SpMV marching along the largest offset P = off[K-1] (the plane
-// size of a grid: rows u = c + P k).  A workgroup owns a tile of kBlock
-// R-row groups of one plane and walks a chunk of consecutive planes; each
+// size of a grid: rows u = c + P k).  A workgroup of BS threads owns a tile
+// of one plane (see MarchTiles) and walks a chunk of consecutive planes; each
 // thread keeps the direction values of planes k-1 and k and the conductance
 // of its edge to plane k-1 in registers, so the +-P neighbours, which lie a
 // whole plane away in memory, are never reloaded.  Offsets below P are read
-// as in k_spmv_dia_vec.  All loads of the first two steps are issued before
-// the start-of-iteration reduction, so they are in flight while it runs.
-// Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of chunks,
-// so the planes at chunk seams are shared in its L2.  The summation order per
-// row is that of k_spmv_dia_vec.
-template <typename T, int K, int R, bool SC>
-__global__ __launch_bounds__(kBlock) void k_spmv_dia_march(CGArgs<T> a) {
-  __shared__ double lds[4 * (kBlock / 64)];
+// as in k_spmv_dia_vec: the +-N neighbours inside a tile are loaded by their
+// own threads at the same step and hit in cache, those on the tile's two
+// boundary lines come from the neighbouring tiles, so taller tiles re-read
+// fewer of them from memory.  All loads of the first two steps are issued
+// before the start-of-iteration reduction, so they are in flight while it
+// runs.  Workgroup b runs on XCD b % 8; each XCD takes a contiguous range of
+// tiles and chunks, so tile boundaries and the planes at chunk seams are
+// mostly shared in its L2.  The summation order per row is that of
+// k_spmv_dia_vec.
+template <typename T, int K, int R, bool SC, int BS>
+__global__ __launch_bounds__(BS) void k_spmv_dia_march(CGArgs<T> a) {
+  __shared__ double lds[4 * (BS / 64)];
   __shared__ double bc[4];
   typedef vec_t<T, R> V;
   const V zero = (T)0;
   const int64_t nt = a.nt, P = a.off[K - 1];
-  const int64_t gp = P / R, tiles = (gp + kBlock - 1) / kBlock;
+  const MarchTiles mt = march_tiles<R, BS>(P, a.off[1], a.march_ty);
   const int64_t nplanes = (nt + P - 1) / P, zc = a.march_planes;
   const int64_t L = (int64_t)(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
-  const int64_t tile = L % tiles, chunk = L / tiles;
-  const int64_t cgrp = tile * kBlock + threadIdx.x;
-  const int64_t c = cgrp * R;
+  const int64_t tile = L % mt.tiles, chunk = L / mt.tiles;
+  const int64_t gxi = (tile % mt.tiles_x) * mt.tx + threadIdx.x % mt.tx;       // row group in its line
+  const int64_t line = mt.TY == 0 ? 0 : (tile / mt.tiles_x) * mt.TY + threadIdx.x / mt.tx;
+  const int64_t c = line * mt.N + gxi * R;
   const int64_t k0 = chunk * zc;
   const int64_t k1 = k0 + zc < nplanes ? k0 + zc : nplanes;
-  const bool active = cgrp < gp && k0 < nplanes && c + P * k0 < nt;
+  const bool active = gxi < mt.gx && line < mt.lines && k0 < nplanes && c + P * k0 < nt;
   // planes of this chunk that hold this thread's rows (a last plane may be partial)
   const int64_t kmax = active ? (nt - c + P - 1) / P : 0;
   const int64_t kend = k1 < kmax ? k1 : kmax;
@@ -1331,21 +1367,57 @@ bool vec_ok(const CGArgs<T> &a) {
 }
 
 // Marching needs the vector layout, at least two planes, and planes of at
-// least one full tile (kBlock groups); the chunk length keeps the grid near
-// kMarchGrid workgroups: one per CU, each keeping two steps of loads in
-// flight per thread (measured faster than two or four per CU on 256^3 grids,
-// and no slower on 128^3, where the longer chunks halve the re-read seams).
+// least one full tile; the chunk length keeps the grid near kMarchGrid
+// workgroups: one per CU, each keeping two steps of loads in flight per
+// thread (measured faster than two or four per CU on 256^3 grids, and no
+// slower on 128^3, where the longer chunks halve the re-read seams).
 constexpr int kMarchGrid = 256;
 
+// Whether a marching launch can take a tile shape: bs threads (256 or 512);
+// ty = 0 (planes of at least one tile), or on 3-D grids ty >= 1 dividing bs,
+// with planes made of whole lines of whole row groups and a tile no wider or
+// taller than a plane.
+template <typename T>
+bool march_shape_ok(const CGArgs<T> &a, int bs, int ty) {
+  constexpr int R = kVecRows<T>;
+  if (bs != 256 && bs != 512) return false;
+  const int64_t P = a.off[a.K - 1];
+  if (ty == 0) return P / R >= bs;
+  if (a.K != 3) return false;
+  const int64_t N = a.off[1];
+  if (ty < 1 || bs % ty != 0 || N <= 0 || P % N != 0 || N % R != 0) return false;
+  return ty <= P / N && bs / ty <= N / R;
+}
+
+template <typename T>
+int64_t march_tile_count(const CGArgs<T> &a, int bs, int ty) {
+  constexpr int R = kVecRows<T>;
+  const int64_t P = a.off[a.K - 1], N = a.K == 3 ? a.off[1] : P;
+  return (bs == 256 ? march_tiles<R, 256>(P, N, ty) : march_tiles<R, 512>(P, N, ty)).tiles;
+}
+
+// The tile shape is the caller's (a.march_bs, a.march_ty) when a launch can
+// take it, else 256 consecutive row groups.
 template <typename T>
 void spmv_layout(CGArgs<T> &a, int grid_main) {
   constexpr int R = kVecRows<T>;
   a.grid_spmv = grid_main;
+  int bs = a.march_bs, ty = a.march_ty;
   a.march_planes = 0;
+  a.march_bs = 0;
+  a.march_ty = 0;
   if (a.K < 2 || !vec_ok(a)) return;
+  if (!march_shape_ok(a, bs, ty)) {
+    bs = 256;
+    ty = 0;
+  }
+  if (!march_shape_ok(a, bs, ty)) return;
   const int64_t P = a.off[a.K - 1];
-  const int64_t gp = P / R, tiles = (gp + kBlock - 1) / kBlock, nplanes = (a.nt + P - 1) / P;
-  if (gp < kBlock || nplanes < 2 || tiles > kMaxGrid) return;
+  const int64_t nplanes = (a.nt + P - 1) / P;
+  const int64_t tiles = march_tile_count(a, bs, ty);
+  if (nplanes < 2 || tiles > kMaxGrid) return;
+  a.march_bs = bs;
+  a.march_ty = ty;
   int64_t zc = (tiles * nplanes + kMarchGrid - 1) / kMarchGrid;
   if (zc < 4) zc = 4;
   int64_t grid = tiles * ((nplanes + zc - 1) / zc);
@@ -1368,12 +1440,23 @@ template <typename T>
 hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hipStream_t st) {
   constexpr int R = kVecRows<T>;
   if (a.march_planes > 0) {
-    if (a.scaled) {
-      if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, true>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
-      else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, true>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+    const dim3 g(a.grid_spmv);
+    if (a.march_bs == 512) {
+      if (a.scaled) {
+        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, true, 512>), g, dim3(512), 0, st, a);
+        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, true, 512>), g, dim3(512), 0, st, a);
+      } else {
+        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, false, 512>), g, dim3(512), 0, st, a);
+        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, false, 512>), g, dim3(512), 0, st, a);
+      }
     } else {
-      if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, false>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
-      else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, false>), dim3(a.grid_spmv), dim3(kBlock), 0, st, a);
+      if (a.scaled) {
+        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, true, 256>), g, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, true, 256>), g, dim3(256), 0, st, a);
+      } else {
+        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, false, 256>), g, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, false, 256>), g, dim3(256), 0, st, a);
+      }
     }
     return hipGetLastError();
   }

@@ -107,21 +107,23 @@ __device__ __forceinline__ void write_partials(double (&x)[NQ], double *partials
 
 // This thread's share of the totals of NQ partial-sum arrays (the sums over
 // partials threadIdx.x, threadIdx.x + kBlock, ...); block_allreduce then
-// finishes them.  For workgroups of kBlock threads.  The loads are unrolled
-// so they are all in flight at once; the sum order is the loop order.  Split
-// from read_totals so a kernel can issue other loads in the same memory
-// round trip and reduce them together.
+// finishes them.  Threads kBlock and up (in larger workgroups) hold zeros, so
+// every workgroup size adds the partials in the same order and gets the same
+// bits.  The loads are unrolled so they are all in flight at once; the sum
+// order is the loop order.  Split from read_totals so a kernel can issue
+// other loads in the same memory round trip and reduce them together.
 template <int NQ>
 __device__ __forceinline__ void partial_share(const double *partials, int slot, int nblocks, double (&acc)[NQ]) {
   constexpr int kPer = kMaxGrid / kBlock;
   double v[NQ][kPer];
+  const bool mine = threadIdx.x < kBlock;
 #pragma unroll
   for (int q = 0; q < NQ; q++) {
     const double *P = partials + ((size_t)slot * kNumPartial + q) * kMaxGrid;
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
       const int b = threadIdx.x + j * kBlock;
-      v[q][j] = b < nblocks ? P[b] : 0.0;
+      v[q][j] = mine && b < nblocks ? P[b] : 0.0;
     }
   }
 #pragma unroll
@@ -136,20 +138,21 @@ __device__ __forceinline__ void partial_share(const double *partials, int slot, 
 // Totals of the partial sums a previous kernel of `nblocks` workgroups left in
 // `slot`.  Every workgroup adds them in the same fixed order, so all get the
 // same bits; no atomics and no fences are needed (kernel boundaries order the
-// memory traffic).  For workgroups of kBlock threads; MAXMASK marks the
-// components reduced by max instead of sum.
+// memory traffic).  As in partial_share, threads kBlock and up contribute the
+// neutral element; MAXMASK marks the components reduced by max instead of sum.
 template <int NQ, unsigned MAXMASK = 0u>
 __device__ __forceinline__ void read_totals(const double *partials, int slot, int nblocks,
                                             double (&tot)[NQ], double *lds, double *bc) {
   constexpr int kPer = kMaxGrid / kBlock;
   double v[NQ][kPer];
+  const bool mine = threadIdx.x < kBlock;
 #pragma unroll
   for (int q = 0; q < NQ; q++) {
     const double *P = partials + ((size_t)slot * kNumPartial + q) * kMaxGrid;
 #pragma unroll
     for (int j = 0; j < kPer; j++) {
       const int b = threadIdx.x + j * kBlock;
-      v[q][j] = b < nblocks ? P[b] : (((MAXMASK >> q) & 1u) ? -INFINITY : 0.0);
+      v[q][j] = mine && b < nblocks ? P[b] : (((MAXMASK >> q) & 1u) ? -INFINITY : 0.0);
     }
   }
 #pragma unroll

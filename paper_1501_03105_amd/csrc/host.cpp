@@ -653,6 +653,7 @@ struct irls_mincut_s {
   int solver = 1;
   int rpw = 8;
   int grid = 1;
+  int32_t march_bs = 0, march_ty = 0;   // marching SpMV tile request (0, 0: the default)
   // FP64 state (both precisions)
   double *v = nullptr, *b = nullptr, *gt = nullptr;
   double *w64 = nullptr, *D64 = nullptr;
@@ -694,6 +695,17 @@ struct irls_mincut_s {
   SweepBufs sw;
   TwoLevelBufs tl;
   std::vector<void *> allocs;
+  // in-solve timing of one CG kernel (irls_mincut_set_kernel_timing): an
+  // event pair around each of its launches; per round, the first pair and the
+  // round's converged iteration count, resolved after the solve
+  int32_t prof_which = -1;
+  int32_t prof_every = 1;           // time launches 0, every, 2*every, ... of each round
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
+  struct ProfRound { size_t pair0, pair1; int64_t iters; };   // pair p times iteration (p - pair0) * every
+  std::vector<ProfRound> prof_rounds;
+  double prof_ms_work = 0.0, prof_ms_all = 0.0;
+  int64_t prof_n_work = 0, prof_n_all = 0;
 
   template <typename T>
   hipError_t dalloc(T **p, size_t count) {
@@ -710,6 +722,8 @@ struct irls_mincut_s {
     if (pinned) (void)hipHostFree(pinned);
     pinned = nullptr;
     for (auto &e : ev) if (e) (void)hipEventDestroy(e);
+    for (auto &e : prof_ev) (void)hipEventDestroy(e);
+    prof_ev.clear();
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     gexec = nullptr;
@@ -762,6 +776,8 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.weights_fp64 = 1;
   a.grid_main = h->grid;
   a.csr_lanes = h->rpw > 0 ? 64 / h->rpw : 64;
+  a.march_bs = h->march_bs;
+  a.march_ty = h->march_ty;
   spmv_layout(a, h->grid);
   a.bj_block = h->bj_block;
   a.rbuf = h->bj_r;
@@ -776,6 +792,34 @@ CGArgs<T> make_args(irls_mincut_t h) {
 // CG iterations first .. first + count - 1 of this round (the kernels learn
 // the true iteration from the scalar block; the index only steers loads that
 // are issued before they read it)
+// The next event pair of the in-solve kernel timing (created on first use,
+// reused by later solves).
+hipError_t prof_pair(irls_mincut_t h, hipEvent_t *e0, hipEvent_t *e1) {
+  while (h->prof_ev.size() < 2 * (h->prof_used + 1)) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    h->prof_ev.push_back(e);
+  }
+  *e0 = h->prof_ev[2 * h->prof_used];
+  *e1 = h->prof_ev[2 * h->prof_used + 1];
+  h->prof_used++;
+  return hipSuccess;
+}
+
+// Launch one CG kernel (iteration `it` of the round), bracketed by an event
+// pair when it is the kernel timed and `it` is a sampled iteration.
+template <typename F>
+hipError_t timed_launch(irls_mincut_t h, int which, int64_t it, F &&launch) {
+  if (h->prof_which != which || it % h->prof_every != 0) return launch();
+  hipEvent_t e0, e1;
+  hipError_t e = prof_pair(h, &e0, &e1);
+  if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+  return e;
+}
+
 template <typename T>
 hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a0, int64_t first, int64_t count) {
   hipError_t e = hipSuccess;
@@ -783,12 +827,37 @@ hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a0, int64_t first
   for (int64_t i = 0; i < count && e == hipSuccess; i++) {
     a.it_hint = first + i;
     if (a.K == 0) e = launch_direction(a, h->grid, h->stream);
-    if (e == hipSuccess) e = launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream);
-    if (e == hipSuccess) e = launch_update(a, h->grid, h->stream);
+    if (e == hipSuccess)
+      e = timed_launch(h, 0, a.it_hint, [&] { return launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream); });
+    if (e == hipSuccess) e = timed_launch(h, 1, a.it_hint, [&] { return launch_update(a, h->grid, h->stream); });
     if (e == hipSuccess && a.bj_block > 0) e = launch_bj_apply(a, h->grid, kPUpd, h->stream);
-    if (e == hipSuccess && h->opt.precision == 1) e = launch_replace_residual(a, h->grid, h->stream);
+    if (e == hipSuccess && h->opt.precision == 1)
+      e = timed_launch(h, 2, a.it_hint, [&] { return launch_replace_residual(a, h->grid, h->stream); });
   }
   return e;
+}
+
+// After a solve has synchronised: add the timed launches of its rounds to the
+// totals.  Launch i of a round did work when i < the round's CG iterations
+// (launch `iters` finds CG stopped and returns; later ones too).  The pairs of
+// a round time its launches 0, every, 2 * every, ... in order.
+irls_status prof_resolve(irls_mincut_t h) {
+  for (const auto &r : h->prof_rounds) {
+    for (size_t p = r.pair0; p < r.pair1; p++) {
+      float ms = 0.0f;
+      HIPCHK(h, hipEventElapsedTime(&ms, h->prof_ev[2 * p], h->prof_ev[2 * p + 1]), "kernel timing");
+      const bool work = (int64_t)(p - r.pair0) * h->prof_every < r.iters;
+      h->prof_ms_all += ms;
+      h->prof_n_all++;
+      if (work) {
+        h->prof_ms_work += ms;
+        h->prof_n_work++;
+      }
+    }
+  }
+  h->prof_rounds.clear();
+  h->prof_used = 0;
+  return IRLS_OK;
 }
 
 // Run CG iterations in chunks until the device reports done.  The next chunk
@@ -808,6 +877,7 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
   int64_t next = 8;
   if (h->opt.chunk > 0) first = next = h->opt.chunk;
   first = std::min(first, maxit);
+  const size_t pair0 = h->prof_used;
   HIPCHK(h, launch_iterations(h, a, 0, first), "CG launch");
   HIPCHK(h, hipMemcpyAsync(&h->pinned[0], h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream), "readback");
   HIPCHK(h, hipEventRecord(h->ev[0], h->stream), "event");
@@ -835,6 +905,7 @@ irls_status run_cg(irls_mincut_t h, const CGArgs<T> &a, int64_t pred, int64_t *i
   }
   *iters = h->pinned[slot].iter_b;
   *status = h->pinned[slot].status;
+  if (h->prof_which >= 0) h->prof_rounds.push_back({pair0, h->prof_used, *iters});
   return IRLS_OK;
 }
 
@@ -866,6 +937,8 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
   const bool fp64 = sizeof(T) == 8;
   // chunk sizing: a continuation starts near the last round's CG count
   int64_t pred = o.init == 2 ? h->last_iters : 0;
+  h->prof_rounds.clear();                          // pairs of a failed earlier solve are dropped
+  h->prof_used = 0;
   double eps = o.eps0;
   irls_status result = IRLS_OK;
   for (int l = 0; l <= o.rounds; l++) {
@@ -928,6 +1001,10 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
     HIPCHK(h, hipMemcpyAsync(stats, h->dstats, (o.rounds + 1) * sizeof(irls_round_stats),
                              hipMemcpyDeviceToHost, h->stream), "stats copy");
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  if (h->prof_which >= 0) {
+    irls_status pr = prof_resolve(h);
+    if (pr != IRLS_OK) return pr;
+  }
   return result;
 }
 
@@ -1746,6 +1823,46 @@ irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *
   return IRLS_OK;
 }
 
+// The marching SpMV's tile shape on the handle's system: (bs, ty, planes per
+// workgroup), or all 0 when the handle does not march.
+static void march_shape(irls_mincut_t h, int32_t *bs, int32_t *ty, int32_t *planes) {
+  if (h->opt.precision == 1) {
+    const CGArgs<float> a = make_args<float>(h);
+    *bs = a.march_bs; *ty = a.march_ty; *planes = a.march_planes;
+  } else {
+    const CGArgs<double> a = make_args<double>(h);
+    *bs = a.march_bs; *ty = a.march_ty; *planes = a.march_planes;
+  }
+}
+
+irls_status irls_mincut_set_march_tile(irls_mincut_t h, int32_t threads, int32_t lines) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (h->batch || h->solver != 1) { h->err = "only the multi-workgroup solver marches"; return IRLS_ERR_OPTIONS; }
+  const int32_t rb = h->march_bs, rt = h->march_ty;
+  h->march_bs = threads;
+  h->march_ty = lines;
+  if (threads == 0 && lines == 0) return IRLS_OK;
+  int32_t bs, ty, pl;
+  march_shape(h, &bs, &ty, &pl);
+  if (pl == 0 || bs != threads || ty != lines) {
+    h->march_bs = rb;
+    h->march_ty = rt;
+    h->err = "the marching SpMV cannot take this tile shape on this graph";
+    return IRLS_ERR_OPTIONS;
+  }
+  return IRLS_OK;
+}
+
+irls_status irls_mincut_march_tile(irls_mincut_t h, int32_t *threads, int32_t *lines, int32_t *planes) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  int32_t bs = 0, ty = 0, pl = 0;
+  if (!h->batch && h->solver == 1) march_shape(h, &bs, &ty, &pl);
+  if (threads) *threads = bs;
+  if (lines) *lines = ty;
+  if (planes) *planes = pl;
+  return IRLS_OK;
+}
+
 irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps, double *avg_ms) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (!avg_ms) { h->err = "avg_ms must not be NULL"; return IRLS_ERR_NULL; }
@@ -1800,6 +1917,31 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
   }
 }
 
+irls_status irls_mincut_set_kernel_timing(irls_mincut_t h, int32_t which, int32_t every) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (which < -1 || which > 2) { h->err = "which must be -1, 0, 1 or 2"; return IRLS_ERR_OPTIONS; }
+  if (every < 1) { h->err = "every must be at least 1"; return IRLS_ERR_OPTIONS; }
+  if (h->batch || h->solver != 1) { h->err = "kernel timing needs the multi-workgroup solver"; return IRLS_ERR_OPTIONS; }
+  if (which == 2 && h->opt.precision != 1) { h->err = "which = 2 needs the precision form"; return IRLS_ERR_OPTIONS; }
+  h->prof_which = which;
+  h->prof_every = every;
+  h->prof_rounds.clear();
+  h->prof_used = 0;
+  h->prof_ms_work = h->prof_ms_all = 0.0;
+  h->prof_n_work = h->prof_n_all = 0;
+  return IRLS_OK;
+}
+
+irls_status irls_mincut_kernel_timing(irls_mincut_t h, double *ms_working, int64_t *n_working,
+                                      double *ms_all, int64_t *n_all) {
+  if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
+  if (ms_working) *ms_working = h->prof_ms_work;
+  if (n_working) *n_working = h->prof_n_work;
+  if (ms_all) *ms_all = h->prof_ms_all;
+  if (n_all) *n_all = h->prof_n_all;
+  return IRLS_OK;
+}
+
 irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (!lanes) { h->err = "lanes must not be NULL"; return IRLS_ERR_NULL; }
@@ -1822,11 +1964,49 @@ irls_status irls_mincut_set_row_lanes(irls_mincut_t h, const int32_t *lanes) {
   return IRLS_OK;
 }
 
+// The marching SpMV: its tile shape, measured by timing the SpMV on the last
+// solve's system for every shape a launch can take (256 or 512 threads; 0,
+// 1, 2, ..., 32 lines per tile).
+static irls_status autotune_march(irls_mincut_t h, int32_t reps, int32_t *lanes) {
+  int32_t bs0, ty0, pl;
+  march_shape(h, &bs0, &ty0, &pl);
+  if (pl == 0) { h->err = "the diagonal format without the marching SpMV has nothing to tune"; return IRLS_ERR_OPTIONS; }
+  if (!h->solved) { h->err = "the SpMV is timed on a solved system: call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
+  const int launches = 20 * reps;
+  const int32_t rb = h->march_bs, rt = h->march_ty;
+  double tcur = 0.0;
+  irls_status rc = irls_mincut_time_kernel(h, 0, launches, &tcur);
+  if (rc != IRLS_OK) return rc;
+  int32_t best_bs = bs0, best_ty = ty0;
+  double tbest = tcur;
+  for (int32_t bs : {256, 512}) {
+    for (int32_t ty : {0, 1, 2, 4, 8, 16, 32}) {
+      h->march_bs = bs;
+      h->march_ty = ty;
+      int32_t b2, t2, p2;
+      march_shape(h, &b2, &t2, &p2);
+      if (b2 != bs || t2 != ty || (bs == bs0 && ty == ty0)) continue;      // not possible here, or the current one
+      double t = 0.0;
+      rc = irls_mincut_time_kernel(h, 0, launches, &t);
+      if (rc != IRLS_OK) { h->march_bs = rb; h->march_ty = rt; return rc; }
+      if (t < 0.98 * tcur && t < tbest) { best_bs = bs; best_ty = ty; tbest = t; }
+    }
+  }
+  h->march_bs = best_bs;
+  h->march_ty = best_ty;
+  if (lanes) {
+    lanes[0] = best_bs;
+    lanes[1] = best_ty;
+    for (int b = 2; b < kBins; b++) lanes[b] = 0;
+  }
+  return IRLS_OK;
+}
+
 // The multi-workgroup CSR path: rows per wavefront of its SpMV (and per-round
 // CSR kernels), measured by timing the SpMV on the last solve's system.
 static irls_status autotune_csr(irls_mincut_t h, int32_t reps, int32_t *lanes) {
   const int32_t K = h->opt.precision == 1 ? make_args<float>(h).K : make_args<double>(h).K;
-  if (K > 0) { h->err = "the diagonal format has no rows per wavefront to tune"; return IRLS_ERR_OPTIONS; }
+  if (K > 0) return autotune_march(h, reps, lanes);
   if (!h->solved) { h->err = "the CSR SpMV is timed on a solved system: call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
   const int launches = 20 * reps;
   double tcur = 0.0;

@@ -11,6 +11,7 @@
 namespace irls {
 
 constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
+constexpr int kMaxBlock = 512;       // largest workgroup (the marching SpMV's wide tiles)
 constexpr int kMaxGrid = 1024;       // workgroups of the streaming kernels (grid-stride)
 constexpr int kMaxDiag = 8;          // most index offsets the diagonal format stores
 constexpr int kNumPartial = 11;      // reduction slots per workgroup
@@ -87,6 +88,9 @@ struct CGArgs {
   int32_t csr_lanes;              // CSR per-round kernels: lanes per row (the SpMV's)
   int32_t march_planes;           // diagonal SpMV marching along off[K-1]: planes per
                                   // workgroup (0: the row-slab kernels)
+  int32_t march_bs;               // marching SpMV: threads per workgroup (256 or 512)
+  int32_t march_ty;               // marching SpMV on 3-D grids: grid lines (offset off[1])
+                                  // per tile; a tile is march_bs / march_ty row groups wide
   int64_t it_hint;                // CG iteration the host expects this launch to run: picks
                                   // the p buffer for loads issued before the kernel has read
                                   // the scalar block (checked there; a mismatch reloads)

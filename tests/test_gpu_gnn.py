@@ -51,7 +51,12 @@ def cases():
 XHAT_TOL = 5e-3
 S_TOL = 5e-3
 LOSS_RTOL = 2e-3
-GRAD_RTOL = 2e-2        # per parameter block, relative 2-norm
+# Gradients element by element: |g_gpu - g_orc| <= GRAD_RTOL |g_orc| +
+# GRAD_ATOL_FRAC max|g_orc of the block| (the second term covers elements
+# near zero, whose relative error is meaningless); a wrong row or column of a
+# weight gradient is off by the order of the block's scale and fails it.
+GRAD_RTOL = 1e-3
+GRAD_ATOL_FRAC = 1e-4
 
 
 def start_potentials(g, seed):
@@ -100,15 +105,21 @@ def test_loss_and_gradient_match_oracle(P, G, case):
     say(f"  loss {L:.7f} vs {Lo:.7f}")
     assert abs(L - Lo) <= LOSS_RTOL * abs(Lo)
     o = 0
-    worst = 0.0
+    worst, worst_el = 0.0, 0.0
     for nm, shp in G.param_shapes():
         k = int(np.prod(shp))
         a, b = grad[o:o + k].astype(np.float64), go[o:o + k]
+        scale = max(float(np.max(np.abs(b))), 1e-30)
         rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        worst = max(worst, rel)
-        assert rel <= GRAD_RTOL, (nm, rel, np.linalg.norm(b))
+        bound = GRAD_RTOL * np.abs(b) + GRAD_ATOL_FRAC * scale
+        ratio = float(np.max(np.abs(a - b) / bound))
+        worst, worst_el = max(worst, rel), max(worst_el, ratio)
+        bad = np.flatnonzero(np.abs(a - b) > bound)
+        assert bad.size == 0, (nm, bad[:8].tolist(), a[bad[:8]].tolist(), b[bad[:8]].tolist())
+        assert rel <= GRAD_RTOL, (nm, rel)
         o += k
-    say(f"  worst block relative gradient error {worst:.2e}")
+    say(f"  worst block relative gradient error {worst:.2e}; element-wise error up to {worst_el:.2f} "
+        f"of the bar")
     net.close()
 
 

@@ -106,3 +106,90 @@ def test_scaled_form_at_fixed_iteration_counts(P, oracle_mod, maxit, precision):
     err = max_pot_err(x, xo)
     say(f"  potential error {err:.2e}")
     assert err <= (1e-10 if precision == 0 else 1e-5)
+
+
+def tile_shapes(R, N, lines, P):
+    """The tile shapes irls_mincut_set_march_tile accepts (its documented rule)."""
+    out = []
+    for bs in (256, 512):
+        for ty in (0, 1, 2, 4, 8, 16, 32, 64):
+            if ty == 0:
+                ok = P // R >= bs
+            else:
+                ok = bs % ty == 0 and ty <= lines and bs // ty <= N // R
+            if ok:
+                out.append((bs, ty))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_march_tile_shapes_match_oracle(P, oracle_mod, precision):
+    """Every tile shape the marching SpMV accepts (256 or 512 threads; 0 or
+    1..64 lines) on a box whose lines (96 rows) and planes (80 lines) leave
+    partial tiles in x and in y and whose last plane is partial: the
+    potentials and the cut against the oracle's, for each shape in turn on one
+    handle.  Shapes outside the rule are refused and leave the shape as it was."""
+    nx, ny = 96, 80
+    g = gen.grid3d_box(nx, ny, nx * ny * 6 + 1000, seed=6)
+    R = 2 if precision == 0 else 4
+    want = tile_shapes(R, nx, ny, nx * ny)
+    xo, so, _ = oracle_mod.irls(g, **OPTS)
+    So, vo, _, _ = oracle_mod.sweep(g, xo)
+    seen = []
+    with P.MinCut.from_graph(g, solver=1, precision=precision, **OPTS) as mc:
+        assert mc.march_tile()[:2] == (256, 0)
+        for bs in (256, 512, 128):
+            for ty in (0, 1, 2, 3, 4, 8, 16, 32, 64, 128):
+                before = mc.march_tile()
+                try:
+                    mc.set_march_tile(bs, ty)
+                except P.IrlsError as e:
+                    assert e.code == P.ERR_OPTIONS and mc.march_tile() == before
+                    continue
+                assert mc.march_tile()[:2] == (bs, ty)
+                rc, st = mc.solve()
+                x = mc.potentials()
+                S, v, _ = mc.cut()
+                err = max_pot_err(x, xo)
+                say(f"  tile {bs} threads x {ty} lines ({mc.march_tile()[2]} planes per workgroup): "
+                    f"potential error {err:.2e}, cut {v!r} vs {vo!r}")
+                assert rc == P.OK
+                if precision == 0:
+                    assert err <= 1e-8
+                    assert v == vo and np.array_equal(S, So)
+                else:
+                    assert err <= 1e-4 and abs(v - vo) <= 1e-4 * vo
+                seen.append((bs, ty))
+        mc.set_march_tile(0, 0)
+        assert mc.march_tile()[:2] == (256, 0)
+    assert seen == want
+
+
+def test_in_solve_kernel_timing(P):
+    """irls_mincut_set_kernel_timing: with every launch timed, the launches that
+    did work are one per CG iteration of every round; with a stride of 4,
+    iterations 0, 4, 8, ... of each round; results are unchanged by it."""
+    g = gen.grid3d_box(64, 64, 64 * 64 * 8, seed=7)
+    with P.MinCut.from_graph(g, solver=1, **OPTS) as mc:
+        _, st0 = mc.solve()
+        x0 = mc.potentials()
+        for which in (0, 1):
+            for every in (1, 4):
+                mc.set_kernel_timing(which, every)
+                _, st = mc.solve()
+                assert np.array_equal(mc.potentials(), x0)
+                t = mc.kernel_timing()
+                iters = [r["cg_iters"] for r in st]
+                assert iters == [r["cg_iters"] for r in st0]
+                assert t["n_working"] == sum((i + every - 1) // every for i in iters if i > 0)
+                assert t["n_all"] >= t["n_working"] and t["ms_working"] > 0
+                assert t["ms_all"] >= t["ms_working"]
+                say(f"  kernel {which}, every {every}: {t['n_working']} working launches, "
+                    f"mean {1e3 * t['ms_working'] / t['n_working']:.1f} us")
+        mc.set_kernel_timing(-1)
+        mc.solve()
+        assert mc.kernel_timing()["n_all"] == 0
+        with pytest.raises(P.IrlsError):
+            mc.set_kernel_timing(2)              # the replacement kernel: precision form only
+        with pytest.raises(P.IrlsError):
+            mc.set_kernel_timing(0, 0)

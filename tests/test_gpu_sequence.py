@@ -2,13 +2,14 @@
 new capacities on a kept handle give the same results as a new handle with
 those capacities, for a fresh solve and for a continuation from the
 previous potentials, on the multi-workgroup (scaled marching, CSR) and the
-resident solvers; structure changes are refused."""
+resident solvers; a continuation equals the oracle's continuation from the
+same potentials; structure changes are refused."""
 import numpy as np
 import pytest
 
 import gen
 from gen.graphs import Graph
-from tests.gpu_util import say
+from tests.gpu_util import cmp_stats, max_pot_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +62,45 @@ def test_update_equals_new_handle(P, case):
         assert np.array_equal(a.potentials(), b.potentials())
         assert [r["cg_iters"] for r in ca] == [r["cg_iters"] for r in cb]
         assert a.cut()[1] == b.cut()[1]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_continuation_equals_oracle(P, oracle_mod, case):
+    """A continuation after new capacities against the oracle's continuation:
+    the oracle solves the old capacities, then runs 12 rounds on the new ones
+    from its own potentials (init 2, eps from 1e-3 halved).  The handle solves
+    the old capacities, takes the new ones, and continues from the oracle's
+    old potentials (potentials within 1e-8, cut set, k* and value equal) and,
+    as a sequence really runs, from the potentials it kept."""
+    name, make, kw = CASES[case]
+    g1 = make()
+    g2 = perturbed(g1, seed=17)
+    opts = dict(rounds=20, cg_rtol=1e-10)
+    x_old, _, _ = oracle_mod.irls(g1, **opts)
+    xo, so, _ = oracle_mod.irls(g2, init=2, x0=x_old, eps0=1e-3, rounds=12, cg_rtol=1e-10)
+    So, vo, ko, _ = oracle_mod.sweep(g2, xo)
+    with P.MinCut.from_graph(g1, **opts, **kw) as mc:
+        mc.solve()
+        mc.update_capacities(g2.eu, g2.ev, g2.cap)
+        _, ck = mc.solve_range(1, 12, eps_first=1e-3)          # from the kept potentials
+        xk = mc.potentials()
+        Sk, vk, kk = mc.cut()
+        mc.set_potentials(x_old)
+        _, cs = mc.solve_range(1, 12, eps_first=1e-3)          # from the oracle's
+        x = mc.potentials()
+        S, v, k = mc.cut()
+    err, errk = max_pot_err(x, xo), max_pot_err(xk, xo)
+    it_o = [r["cg_iters"] for r in so[1:]]
+    say(f"continuation {name}: potentials within {err:.2e} (kept: {errk:.2e}); cut {v!r} / kept {vk!r} / "
+        f"oracle {vo!r}; CG per round {[r['cg_iters'] for r in cs[1:]]} vs oracle {it_o}")
+    assert err <= 1e-8
+    assert v == vo and k == ko and np.array_equal(S, So)
+    assert max(abs(a["cg_iters"] - b) for a, b in zip(cs[1:], it_o)) <= 1
+    for l in range(1, 13):
+        assert cs[l]["eps"] == so[l]["eps"], l
+        assert not cmp_stats(cs[l], so[l], rtol=1e-7), (l, cmp_stats(cs[l], so[l], rtol=1e-7))
+    assert errk <= 1e-7
+    assert vk == vo and kk == ko and np.array_equal(Sk, So)
 
 
 def test_update_refuses_structure_changes(P):
