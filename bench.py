@@ -385,6 +385,9 @@ def main():
                     help="also time the certified-gap stopping rule (stop_gap) on the same instance; 0: skip")
     ap.add_argument("--precision-form", type=int, default=1,
                     help="1: also time the precision form on the same instance; 0: skip")
+    ap.add_argument("--stream-probe", type=int, default=1,
+                    help="1: also measure the GPU's streaming ceiling for the SpMV's mix of five read and "
+                         "two write streams of n_nonterminal doubles (irls_stream_probe); 0: skip")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run 5 plain device copies of MIB MiB (reference for byte counters)")
     args = ap.parse_args()
@@ -492,6 +495,21 @@ def main():
               f"{b2b_ms*1e3:.1f} us), update {upd_ms*1e3:.1f} us", file=sys.stderr, flush=True)
     mc.close()
     gold = golden_run(args.workload)
+    if roof and args.stream_probe and info["n_nonterminal"] % 2 == 0:
+        # the bandwidth a kernel with the SpMV's mix of streams (five arrays
+        # read, two written, one row each per step) and nothing else sustains
+        # at this size, and a plain copy; the better of two grid sizes each
+        probe = {}
+        for nr, nw in ((5, 2), (1, 1)):
+            best = 0.0
+            for wg in (256, 1024):
+                ms = P.stream_probe(info["n_nonterminal"], nr, nw, wg, 20, stream)
+                best = max(best, (nr + nw) * info["n_nonterminal"] * 8 / (ms * 1e-3) / 1e9)
+            probe[f"{nr}r{nw}w"] = round(best, 1)
+        roof["stream_ceiling_GBps"] = probe
+        roof["frac_of_stream_ceiling"] = round(roof["achieved"] / probe["5r2w"], 4)
+        print(f"[bench] streaming ceiling at {info['n_nonterminal']} rows: 5 reads + 2 writes "
+              f"{probe['5r2w']:.0f} GB/s, copy {probe['1r1w']:.0f} GB/s", file=sys.stderr, flush=True)
 
     # A mode of the library beside the configured run: the same instance with
     # the certified-gap stopping rule (rounds stop once ||CBx||_1 and the

@@ -279,6 +279,22 @@ irls_status irls_mincut_spmv_kernel(irls_mincut_t h, int32_t *variant, int32_t *
 irls_status irls_mincut_set_march_tile(irls_mincut_t h, int32_t threads, int32_t lines);
 irls_status irls_mincut_march_tile(irls_mincut_t h, int32_t *threads, int32_t *lines, int32_t *planes);
 
+/* Streaming ceiling of the GPU for a mix of memory streams: the bandwidth a
+ * kernel that only reads `reads` arrays and writes `writes` arrays of `rows`
+ * doubles each (two rows per thread, 16-byte accesses, rows in XCD slabs, no
+ * other work) sustains.  The CG kernels (Section 3.1's PCG: the SpMV streams
+ * five arrays in and two out per row) are read against it.  Allocates
+ * (reads + writes) * rows doubles on the current device for the call, runs
+ * one warm-up and `reps` timed launches on hip_stream (NULL: the default
+ * stream) with `workgroups` workgroups, and writes the mean launch time
+ * (ms).  Bytes moved per launch: (reads + writes) * rows * 8.
+ * Errors: IRLS_ERR_OPTIONS unless rows is even and >= 2, reads in 1..6,
+ * writes in 1..2, workgroups a multiple of 8 in 8..1024, reps in 1..1000;
+ * IRLS_ERR_OOM / IRLS_ERR_DEVICE from HIP (text via
+ * irls_mincut_last_error(NULL)). */
+irls_status irls_stream_probe(int64_t rows, int32_t reads, int32_t writes, int32_t workgroups,
+                              int32_t reps, void *hip_stream, double *avg_ms);
+
 /* Time one hot kernel of the CG loop on the handle's stream with HIP events:
  * `which` 0 = SpMV (with its fused direction update), 1 = the CG vector
  * update of an odd iteration, 2 = of an even one (they differ only on the

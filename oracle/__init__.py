@@ -52,8 +52,11 @@ def lib():
         G = [C.c_int64, C.c_int64, _I64P, _I64P, _F64P, C.c_int64, C.c_int64]
         L.orc_options_default.argtypes = [C.POINTER(Options)]
         L.orc_irls.argtypes = G + [C.POINTER(Options), _F64P, _F64P, C.POINTER(Round)]
+        L.orc_irls_blocks.argtypes = G + [C.POINTER(Options), _I64P, _F64P, _F64P, C.POINTER(Round)]
         L.orc_reduced_system.argtypes = G + [_F64P, C.c_double, C.c_int32, _I64P, _I64P, _F64P, _F64P, _I64P]
         L.orc_sweep.argtypes = G + [_F64P, _U8P, _F64P, _I64P, C.POINTER(C.c_int32)]
+        L.orc_block_apply.argtypes = G + [_F64P, C.c_double, C.c_int32, C.c_int32, C.c_int64, _I64P,
+                                          _F64P, _F64P]
         L.orc_cut_value.argtypes = G + [_U8P, _F64P]
         L.orc_maxflow.argtypes = G + [_U8P, _F64P]
         L.orc_bruteforce.argtypes = G + [_U8P, _F64P, _F64P]
@@ -82,14 +85,17 @@ def options(**kw):
     return o
 
 
-def irls(g, x0=None, allow_maxit=False, **kw):
-    """Run the oracle IRLS. Returns (x [n], list of per-round dicts, status)."""
+def irls(g, x0=None, allow_maxit=False, block_of=None, **kw):
+    """Run the oracle IRLS. Returns (x [n], list of per-round dicts, status).
+    block_of: block id per node for the block-Jacobi preconditioner (precond
+    1 exact, 2 ILU(0)); None: blocks of block_size consecutive rows."""
     o = options(**kw)
     keep, ga = _graph_args(g)
     x = np.zeros(g.n)
     rounds = (Round * (o.rounds + 1))()
     x0a = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
-    rc = lib().orc_irls(*ga, C.byref(o), _p(x0a, _F64P), _p(x, _F64P), rounds)
+    ba = None if block_of is None else np.ascontiguousarray(block_of, dtype=np.int64)
+    rc = lib().orc_irls_blocks(*ga, C.byref(o), _p(ba, _I64P), _p(x0a, _F64P), _p(x, _F64P), rounds)
     if rc not in (0, 100) or (rc == 100 and not allow_maxit):
         raise OracleError(rc, "irls")
     recs = [{f: getattr(r, f) for f in ROUND_FIELDS} for r in rounds]
@@ -115,6 +121,21 @@ def reduced_system(g, x=None, eps=0.0, weight_form=0):
     if rc:
         raise OracleError(rc, "reduced_system")
     return rowptr, col, val, b
+
+
+def block_apply(g, r, kind, block_of=None, block_size=1, x=None, eps=0.0, weight_form=0):
+    """z = M^-1 r for the block-Jacobi preconditioner of one round's system
+    (kind 1 exact, 2 ILU(0)); r, z over the non-terminal nodes in ascending id."""
+    keep, ga = _graph_args(g)
+    ra = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros(g.n - 2)
+    xa = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+    ba = None if block_of is None else np.ascontiguousarray(block_of, dtype=np.int64)
+    rc = lib().orc_block_apply(*ga, _p(xa, _F64P), eps, weight_form, kind, block_size, _p(ba, _I64P),
+                               _p(ra, _F64P), _p(z, _F64P))
+    if rc:
+        raise OracleError(rc, "block_apply")
+    return z
 
 
 def sweep(g, x):

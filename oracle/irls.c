@@ -11,11 +11,16 @@
  *
  * Section 3.1: the system is solved by preconditioned CG (Saad's PCG),
  * warm-started from the previous round's solution when requested, with the
- * paper's block-Jacobi preconditioner: M = blockdiag of the principal
- * submatrices of L~ over blocks of consecutive rows.  Blocks of size one
- * (precond 0) are the Jacobi preconditioner; precond 1 uses blocks of
- * block_size rows, each factored by a dense Cholesky factorisation once per
- * round and applied by forward and back substitution.
+ * paper's block-Jacobi preconditioner (eq. block-jacobi-subsystem): M =
+ * blockdiag of the principal submatrices of L~ over a partition of the rows
+ * into blocks, each block's rows taken in ascending order.  Blocks of size one
+ * (precond 0) are the Jacobi preconditioner.  The blocks are consecutive rows
+ * (block_size of them), or a caller's block id per node.  Each block is
+ * factored once per round and applied by forward and back substitution, by
+ * the paper's two strategies: precond 1 solves it exactly (its dense Cholesky
+ * factorisation, the symmetric form of LU), precond 2 by ILU(0) (Saad's
+ * incomplete LU with no fill: L unit lower and U upper triangular, both on
+ * the pattern of the block, with (LU)_ij = A_ij on that pattern).
  *
  * Two conductance forms are provided:
  *   form 0: g = c / sqrt(d^2 + eps)
@@ -26,6 +31,7 @@
  * chunk order, so the result does not depend on the thread count.
  */
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -117,36 +123,129 @@ static void spmv(const ograph *g, const osys *S, const double *p, double *q) {
   }
 }
 
-/* block-Jacobi preconditioner: dense Cholesky factors L (lower, row-major
- * bs x bs) of each block's principal submatrix of L~ */
+/* block-Jacobi preconditioner.  Block k holds the rows rows[ptr[k] ..
+ * ptr[k+1]) in ascending order; F + off[k] is its dense nb x nb factor
+ * (row-major): the Cholesky factor L (lower) for precond 1, or L (strictly
+ * lower, unit diagonal implied) and U (upper) in one array for precond 2. */
 typedef struct {
-  int64_t bs, nblk;
-  double *L;          /* [nblk][bs][bs] */
+  int32_t kind;       /* 1 exact (Cholesky), 2 ILU(0) */
+  int64_t nblk;
+  int64_t *ptr;       /* [nblk + 1] */
+  int64_t *rows;      /* [nt] */
+  int64_t *off;       /* [nblk] offsets into F */
+  double *F;
+  uint8_t *pat;       /* ILU(0): the block's pattern, same layout as F */
 } oprec;
 
-static void prec_factor(const ograph *g, const osys *S, oprec *P) {
-  const int64_t nt = g->nt, bs = P->bs;
-  #pragma omp parallel for schedule(static)
-  for (int64_t k = 0; k < P->nblk; k++) {
-    const int64_t lo = k * bs, hi = lo + bs < nt ? lo + bs : nt, nb = hi - lo;
-    double *A = P->L + (size_t)k * bs * bs;
-    for (int64_t i = 0; i < bs * bs; i++) A[i] = 0.0;
-    for (int64_t i = lo; i < hi; i++) {          /* the block of L~ = D - W */
-      A[(i - lo) * bs + (i - lo)] = S->D[i];
-      for (int64_t a = g->rp[i]; a < g->rp[i + 1]; a++) {
-        const int64_t j = g->nb[a];
-        if (j >= lo && j < hi) A[(i - lo) * bs + (j - lo)] -= S->w[a];
+static void prec_free(oprec *P) {
+  free(P->ptr); free(P->rows); free(P->off); free(P->F); free(P->pat);
+}
+
+static int cmp_pair(const void *a, const void *b) {
+  const int64_t *x = (const int64_t *)a, *y = (const int64_t *)b;
+  if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+  return (x[1] > y[1]) - (x[1] < y[1]);
+}
+
+/* Blocks from block ids (NULL: consecutive runs of bs rows); returns 0 or
+ * ORC_ERR_NOMEM. */
+static int prec_setup(const ograph *g, const int64_t *block_of, int64_t bs, int32_t kind, oprec *P) {
+  const int64_t nt = g->nt;
+  memset(P, 0, sizeof(*P));
+  P->kind = kind;
+  /* (block id, row) pairs sorted: rows of a block are consecutive and
+     ascending, blocks in ascending id (their order does not matter: they are
+     independent) */
+  int64_t (*pr)[2] = malloc(sizeof(*pr) * (size_t)(nt ? nt : 1));
+  int64_t *bid = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nt ? nt : 1));
+  if (!pr || !bid) { free(pr); free(bid); return ORC_ERR_NOMEM; }
+  for (int64_t i = 0; i < nt; i++) {
+    pr[i][0] = block_of ? block_of[g->orig[i]] : i / bs;
+    pr[i][1] = i;
+  }
+  qsort(pr, (size_t)nt, sizeof(*pr), cmp_pair);
+  int64_t nb = 0;
+  for (int64_t i = 0; i < nt; i++) {
+    if (i == 0 || pr[i][0] != pr[i - 1][0]) nb++;
+    bid[pr[i][1]] = nb - 1;
+  }
+  free(pr);
+  P->nblk = nb;
+  P->ptr = (int64_t *)calloc((size_t)nb + 1, sizeof(int64_t));
+  P->rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nt ? nt : 1));
+  P->off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb ? nb : 1));
+  if (!P->ptr || !P->rows || !P->off) { free(bid); prec_free(P); return ORC_ERR_NOMEM; }
+  for (int64_t i = 0; i < nt; i++) P->ptr[bid[i] + 1]++;
+  for (int64_t k = 0; k < nb; k++) P->ptr[k + 1] += P->ptr[k];
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb ? nb : 1));
+  if (!fill) { free(bid); prec_free(P); return ORC_ERR_NOMEM; }
+  for (int64_t k = 0; k < nb; k++) fill[k] = P->ptr[k];
+  for (int64_t i = 0; i < nt; i++) P->rows[fill[bid[i]]++] = i;   /* ascending within each block */
+  size_t tot = 0;
+  for (int64_t k = 0; k < nb; k++) {
+    const int64_t m = P->ptr[k + 1] - P->ptr[k];
+    P->off[k] = (int64_t)tot;
+    tot += (size_t)(m * m);
+  }
+  P->F = (double *)malloc(sizeof(double) * (tot ? tot : 1));
+  if (kind == 2) P->pat = (uint8_t *)malloc(tot ? tot : 1);
+  free(bid); free(fill);
+  if (!P->F || (kind == 2 && !P->pat)) { prec_free(P); return ORC_ERR_NOMEM; }
+  return ORC_OK;
+}
+
+/* The block's principal submatrix of L~ = D - W (dense), and its pattern. */
+static void prec_gather(const ograph *g, const osys *S, const oprec *P, int64_t k, double *A, uint8_t *pat) {
+  const int64_t b0 = P->ptr[k], m = P->ptr[k + 1] - b0;
+  const int64_t *rows = P->rows + b0;
+  for (int64_t i = 0; i < m * m; i++) { A[i] = 0.0; if (pat) pat[i] = 0; }
+  for (int64_t i = 0; i < m; i++) {
+    const int64_t r = rows[i];
+    A[i * m + i] = S->D[r];
+    if (pat) pat[i * m + i] = 1;
+    for (int64_t a = g->rp[r]; a < g->rp[r + 1]; a++) {
+      const int64_t j = g->nb[a];
+      int64_t lo = 0, hi = m;                               /* position of row j in the block */
+      while (lo < hi) { int64_t mid = (lo + hi) / 2; if (rows[mid] < j) lo = mid + 1; else hi = mid; }
+      if (lo < m && rows[lo] == j) {
+        A[i * m + lo] -= S->w[a];
+        if (pat) pat[i * m + lo] = 1;
       }
     }
-    for (int64_t j = 0; j < nb; j++) {           /* Cholesky A = L L^T, in place */
-      double d = A[j * bs + j];
-      for (int64_t c = 0; c < j; c++) d -= A[j * bs + c] * A[j * bs + c];
-      d = sqrt(d);
-      A[j * bs + j] = d;
-      for (int64_t i = j + 1; i < nb; i++) {
-        double x = A[i * bs + j];
-        for (int64_t c = 0; c < j; c++) x -= A[i * bs + c] * A[j * bs + c];
-        A[i * bs + j] = x / d;
+  }
+}
+
+static void prec_factor(const ograph *g, const osys *S, oprec *P) {
+  #pragma omp parallel for schedule(dynamic)
+  for (int64_t k = 0; k < P->nblk; k++) {
+    const int64_t m = P->ptr[k + 1] - P->ptr[k];
+    double *A = P->F + P->off[k];
+    uint8_t *pat = P->kind == 2 ? P->pat + P->off[k] : NULL;
+    prec_gather(g, S, P, k, A, pat);
+    if (P->kind == 1) {
+      for (int64_t j = 0; j < m; j++) {           /* Cholesky A = L L^T, in place */
+        double d = A[j * m + j];
+        for (int64_t c = 0; c < j; c++) d -= A[j * m + c] * A[j * m + c];
+        d = sqrt(d);
+        A[j * m + j] = d;
+        for (int64_t i = j + 1; i < m; i++) {
+          double x = A[i * m + j];
+          for (int64_t c = 0; c < j; c++) x -= A[i * m + c] * A[j * m + c];
+          A[i * m + j] = x / d;
+        }
+      }
+    } else {
+      /* ILU(0), row by row (Saad's IKJ form): for each pattern entry (i, k)
+         left of the diagonal, a_ik /= a_kk, then a_ij -= a_ik a_kj for the
+         pattern entries (i, j) right of k; nothing outside the pattern. */
+      for (int64_t i = 1; i < m; i++) {
+        for (int64_t kk = 0; kk < i; kk++) {
+          if (!pat[i * m + kk]) continue;
+          A[i * m + kk] /= A[kk * m + kk];
+          const double l = A[i * m + kk];
+          for (int64_t j = kk + 1; j < m; j++)
+            if (pat[i * m + j]) A[i * m + j] -= l * A[kk * m + j];
+        }
       }
     }
   }
@@ -160,20 +259,36 @@ static void prec_apply(const ograph *g, const osys *S, const oprec *P, const dou
     for (int64_t i = 0; i < nt; i++) z[i] = r[i] / S->D[i];
     return;
   }
-  const int64_t bs = P->bs;
-  #pragma omp parallel for schedule(static)
+  #pragma omp parallel for schedule(dynamic)
   for (int64_t k = 0; k < P->nblk; k++) {
-    const int64_t lo = k * bs, hi = lo + bs < nt ? lo + bs : nt, nb = hi - lo;
-    const double *L = P->L + (size_t)k * bs * bs;
-    for (int64_t i = 0; i < nb; i++) {           /* L y = r */
-      double x = r[lo + i];
-      for (int64_t c = 0; c < i; c++) x -= L[i * bs + c] * z[lo + c];
-      z[lo + i] = x / L[i * bs + i];
-    }
-    for (int64_t i = nb - 1; i >= 0; i--) {      /* L^T z = y */
-      double x = z[lo + i];
-      for (int64_t c = i + 1; c < nb; c++) x -= L[c * bs + i] * z[lo + c];
-      z[lo + i] = x / L[i * bs + i];
+    const int64_t m = P->ptr[k + 1] - P->ptr[k];
+    const int64_t *rows = P->rows + P->ptr[k];
+    const double *F = P->F + P->off[k];
+    if (P->kind == 1) {
+      for (int64_t i = 0; i < m; i++) {           /* L y = r */
+        double x = r[rows[i]];
+        for (int64_t c = 0; c < i; c++) x -= F[i * m + c] * z[rows[c]];
+        z[rows[i]] = x / F[i * m + i];
+      }
+      for (int64_t i = m - 1; i >= 0; i--) {      /* L^T z = y */
+        double x = z[rows[i]];
+        for (int64_t c = i + 1; c < m; c++) x -= F[c * m + i] * z[rows[c]];
+        z[rows[i]] = x / F[i * m + i];
+      }
+    } else {
+      const uint8_t *pat = P->pat + P->off[k];
+      for (int64_t i = 0; i < m; i++) {           /* L y = r, L unit lower */
+        double x = r[rows[i]];
+        for (int64_t c = 0; c < i; c++)
+          if (pat[i * m + c]) x -= F[i * m + c] * z[rows[c]];
+        z[rows[i]] = x;
+      }
+      for (int64_t i = m - 1; i >= 0; i--) {      /* U z = y */
+        double x = z[rows[i]];
+        for (int64_t c = i + 1; c < m; c++)
+          if (pat[i * m + c]) x -= F[i * m + c] * z[rows[c]];
+        z[rows[i]] = x / F[i * m + i];
+      }
     }
   }
 }
@@ -298,13 +413,19 @@ static void round_stats(const ograph *g, const osys *S, const double *v, double 
 int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
              const double *cap, int64_t s, int64_t t, const orc_options *opt,
              const double *x0, double *x_out, orc_round *rounds_out) {
+  return orc_irls_blocks(n, m, eu, ev, cap, s, t, opt, NULL, x0, x_out, rounds_out);
+}
+
+int orc_irls_blocks(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
+                    const double *cap, int64_t s, int64_t t, const orc_options *opt,
+                    const int64_t *block_of, const double *x0, double *x_out, orc_round *rounds_out) {
   orc_options o;
   if (opt) o = *opt; else orc_options_default(&o);
   if (!x_out) return ORC_ERR_NULL;
   if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
       !(o.cg_rtol > 0.0) || o.cg_maxit < 1 || (o.rounds > 0 && !(o.eps0 > 0.0)) ||
-      !(o.eps_factor > 0.0) || o.eps_factor > 1.0 || o.precond < 0 || o.precond > 1 ||
-      (o.precond == 1 && o.block_size < 1))
+      !(o.eps_factor > 0.0) || o.eps_factor > 1.0 || o.precond < 0 || o.precond > 2 ||
+      (o.precond >= 1 && !block_of && o.block_size < 1))
     return ORC_ERR_OPTIONS;
   if (o.init == 2 && !x0) return ORC_ERR_NULL;
 #ifdef _OPENMP
@@ -326,14 +447,16 @@ int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
   double *z = (double *)malloc(sizeof(double) * nv);
   double *p = (double *)malloc(sizeof(double) * nv);
   double *q = (double *)malloc(sizeof(double) * nv);
-  oprec Pr = {0, 0, NULL}, *P = NULL;
+  oprec Pr, *P = NULL;
+  memset(&Pr, 0, sizeof(Pr));
   int status = ORC_OK;
   if (!S.w || !S.ws || !S.wt || !S.D || !S.b || !v || !r || !z || !p || !q) { status = ORC_ERR_NOMEM; goto done; }
-  if (o.precond == 1 && nt > 0) {
-    Pr.bs = o.block_size < nt ? o.block_size : nt;
-    Pr.nblk = (nt + Pr.bs - 1) / Pr.bs;
-    Pr.L = (double *)malloc(sizeof(double) * (size_t)Pr.nblk * Pr.bs * Pr.bs);
-    if (!Pr.L) { status = ORC_ERR_NOMEM; goto done; }
+  if (o.precond >= 1 && nt > 0) {
+    if (block_of)
+      for (int64_t u = 0; u < n; u++)
+        if (block_of[u] < 0) { status = ORC_ERR_RANGE; goto done; }
+    status = prec_setup(&g, block_of, o.block_size < nt ? o.block_size : nt, o.precond, &Pr);
+    if (status) goto done;
     P = &Pr;
   }
 
@@ -385,7 +508,7 @@ int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
 done:
   free(S.w); free(S.ws); free(S.wt); free(S.D); free(S.b);
   free(v); free(r); free(z); free(p); free(q);
-  free(Pr.L);
+  prec_free(&Pr);
   og_free(&g);
   return status;
 }
@@ -427,4 +550,40 @@ int orc_reduced_system(int64_t n, int64_t m, const int64_t *eu, const int64_t *e
   free(v); free(S.w); free(S.ws); free(S.wt); free(S.D); free(S.b);
   og_free(&g);
   return ORC_OK;
+}
+
+int orc_block_apply(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
+                    const double *cap, int64_t s, int64_t t, const double *x, double eps,
+                    int32_t weight_form, int32_t kind, int64_t block_size, const int64_t *block_of,
+                    const double *r, double *z) {
+  if (!r || !z) return ORC_ERR_NULL;
+  if (kind < 1 || kind > 2 || (!block_of && block_size < 1)) return ORC_ERR_OPTIONS;
+  ograph g;
+  int rc = og_build(&g, n, m, eu, ev, cap, s, t);
+  if (rc) return rc;
+  int64_t nt = g.nt;
+  size_t nv = (size_t)(nt ? nt : 1);
+  double *v = (double *)calloc(nv, sizeof(double));
+  osys S;
+  S.w = (double *)malloc(sizeof(double) * (size_t)(g.rp[nt] ? g.rp[nt] : 1));
+  S.ws = (double *)malloc(sizeof(double) * nv);
+  S.wt = (double *)malloc(sizeof(double) * nv);
+  S.D = (double *)malloc(sizeof(double) * nv);
+  S.b = (double *)malloc(sizeof(double) * nv);
+  oprec P;
+  memset(&P, 0, sizeof(P));
+  if (!v || !S.w || !S.ws || !S.wt || !S.D || !S.b) rc = ORC_ERR_NOMEM;
+  if (!rc && nt > 0) {
+    if (x) for (int64_t i = 0; i < nt; i++) v[i] = x[g.orig[i]];
+    assemble(&g, &S, v, x == NULL, eps, weight_form);
+    rc = prec_setup(&g, block_of, block_size < nt ? block_size : nt, kind, &P);
+    if (!rc) {
+      prec_factor(&g, &S, &P);
+      prec_apply(&g, &S, &P, r, z);
+    }
+  }
+  prec_free(&P);
+  free(v); free(S.w); free(S.ws); free(S.wt); free(S.D); free(S.b);
+  og_free(&g);
+  return rc;
 }

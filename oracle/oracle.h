@@ -40,9 +40,11 @@ typedef struct {
   double  cg_rtol;       /* stop when ||r||_2 <= rtol ||b||_2 */
   int64_t cg_maxit;
   int32_t threads;       /* OpenMP threads, 0 = runtime default */
-  int32_t precond;       /* 0: Jacobi (diagonal); 1: block-Jacobi, blocks of block_size
-                            consecutive non-terminal rows (the principal submatrices of L~) */
-  int32_t block_size;    /* rows per block for precond 1 (>= 1) */
+  int32_t precond;       /* 0: Jacobi (diagonal); block-Jacobi over blocks of rows (the
+                            principal submatrices of L~), each solved 1: exactly (dense
+                            Cholesky) or 2: by ILU(0) in ascending row order */
+  int32_t block_size;    /* rows per block for precond 1, 2 when no block ids are given
+                            (blocks of consecutive non-terminal rows; >= 1) */
 } orc_options;
 
 typedef struct {
@@ -72,6 +74,24 @@ void orc_options_default(orc_options *o);
 int orc_irls(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
              const double *cap, int64_t s, int64_t t, const orc_options *opt,
              const double *x0, double *x_out, orc_round *rounds_out);
+
+/* orc_irls with the block-Jacobi blocks given by block_of (n entries, >= 0,
+ * indexed by node id; entries of s and t ignored): rows with equal ids form a
+ * block.  block_of NULL: blocks of block_size consecutive rows. */
+int orc_irls_blocks(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
+                    const double *cap, int64_t s, int64_t t, const orc_options *opt,
+                    const int64_t *block_of, const double *x0, double *x_out,
+                    orc_round *rounds_out);
+
+/* One application z = M^-1 r of the block-Jacobi preconditioner of a round's
+ * system (x, eps, weight_form as for orc_reduced_system): blocks from
+ * block_of (n entries) or of block_size consecutive rows, each factored by
+ * kind 1 (exact, dense Cholesky) or 2 (ILU(0)).  r and z: n_nonterminal
+ * entries, non-terminal nodes in ascending id. */
+int orc_block_apply(int64_t n, int64_t m, const int64_t *eu, const int64_t *ev,
+                    const double *cap, int64_t s, int64_t t, const double *x, double eps,
+                    int32_t weight_form, int32_t kind, int64_t block_size, const int64_t *block_of,
+                    const double *r, double *z);
 
 /* Reduced Laplacian of one round (pattern + values) for tests.
  * x: n potentials, or NULL for round 0 (conductance = capacity).

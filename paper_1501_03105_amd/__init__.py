@@ -83,6 +83,9 @@ def lib():
         L.irls_mincut_spmv_kernel.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.irls_mincut_set_kernel_timing.argtypes = [H, C.c_int32, C.c_int32]
         L.irls_mincut_set_march_tile.argtypes = [H, C.c_int32, C.c_int32]
+        L.irls_stream_probe.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                        PF64]
+        L.irls_stream_probe.restype = C.c_int
         L.irls_mincut_march_tile.argtypes = [H, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                              C.POINTER(C.c_int32)]
         L.irls_mincut_kernel_timing.argtypes = [H, PF64, P64, PF64, P64]
@@ -566,3 +569,13 @@ def create_error(n, eu, ev, cap, s, t, **opts):
         return OK
     except IrlsError as e:
         return e.code
+
+
+def stream_probe(rows, reads, writes, workgroups=256, reps=20, stream=None):
+    """irls_stream_probe: mean launch time (ms) of a kernel streaming `reads`
+    input and `writes` output arrays of `rows` doubles."""
+    ms = C.c_double(0)
+    rc = lib().irls_stream_probe(int(rows), reads, writes, workgroups, reps, _stream_ptr(stream), C.byref(ms))
+    if rc != OK:
+        raise IrlsError(rc, lib().irls_mincut_last_error(None).decode())
+    return ms.value

@@ -219,7 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_scale_w(CGArgs<T> a) {
     for (int k = 0; k < a.K; k++) {
       const int64_t j = u + a.off[k];
       const double wv = j < a.nt ? (a.w64 ? a.w64[k * a.nt + u] : (double)a.w[k * a.nt + u]) : 0.0;
-      a.wh[k * a.nt + u] = (T)(wv != 0.0 ? wv / sqrt(du * diag64(a, j)) : 0.0);
+      const double wh = wv != 0.0 ? wv / sqrt(du * diag64(a, j)) : 0.0;
+      a.wh[k * a.nt + u] = (T)wh;
+      if (a.wh64) a.wh64[k * a.nt + u] = wh;         // the FP64 residual replacement's copy
     }
   }
 }
@@ -1170,6 +1172,133 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
   write_partials<2>(x, a.partials, kPRep, lds);
 }
 
+// precision 1 on the symmetrically scaled system (diagonal layout, 16-byte
+// row vectors): the same replacement, formed in the scaled variables with the
+// round's FP64 scaled conductances wh64 = w / sqrt(D_u D_j):
+//   r^ = D^-1/2 b - (v^ - W^ v^),   v^ = D^1/2 v (the CG variable, plus the
+//   step alpha p an even iteration left pending),
+// which equals D^-1/2 (b - L~ v) without a square root per neighbour.  Each
+// thread takes R consecutive rows with unconditional vector loads; a
+// neighbour outside the matrix is read at a valid index whose conductance is
+// zero (as in the marching SpMV).  ||r||^2 = sum D_u r^_u^2 for the stopping
+// test, r^T z = ||z||^2 with z = r^ rounded to T.
+template <typename T, int K, int R>
+__global__ __launch_bounds__(kBlock) void k_replace_scaled(CGArgs<T> a) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  __shared__ double bc[4];
+  typedef vec_t<double, R> VD;
+  typedef vec_t<T, R> VT;
+  Scalars *sc = a.sc;
+  const int32_t done = sc->done;
+  const int64_t i = sc->iter_b;
+  const int32_t refine = sc->refine_every;
+  const double bb = sc->bb;
+  double t[3];
+  {
+    double u[2];
+    partial_share<2>(a.partials, kPUpd, a.grid_main, u);
+    t[0] = u[0];
+    t[1] = u[1];
+    t[2] = done != 0 ? 1.0 : 0.0;
+  }
+  block_allreduce<3, 0x4u>(t, lds, bc);
+  if (t[2] != 0.0) return;
+  const bool conv_rec = sqrt(t[1]) <= a.rtol * sqrt(bb);
+  if (!(conv_rec || i % refine == 0)) return;
+  const bool pending = (i & 1) != 0;
+  const double ap = pending ? sc->alpha_par[0] : 0.0;
+  const int64_t nt = a.nt;
+  const double *__restrict__ wh = a.wh64;
+  auto vhat = [&](int64_t j) -> VD {                     // R consecutive true scaled potentials
+    const VD v = vload<double, R>(a.v + j);
+    const VT p = vload<T, R>(a.p1 + j);
+    VD o;
+#pragma unroll
+    for (int q = 0; q < R; q++) o[q] = v[q] + ap * (double)p[q];
+    return o;
+  };
+  auto vhat1 = [&](int64_t j) -> double { return a.v[j] + ap * (double)a.p1[j]; };
+  double x[2] = {0.0, 0.0};
+  const int64_t ng = nt / R;
+  FOR_ROWS(g, ng) {
+    const int64_t u0 = g * R;
+    const VD vc = vhat(u0);
+    const VD w0 = vload<double, R>(wh + u0);
+    const double vr = vhat1(u0 + R < nt ? u0 + R : u0);   // w0 of row nt - 1 is 0
+    const double vl = vhat1(u0 > 0 ? u0 - 1 : u0);
+    const double wl = wh[u0 > 0 ? u0 - 1 : nt - 1];       // row nt - 1 has no +1 edge
+    VD acc = vc;
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      acc[q] -= w0[q] * (q + 1 < R ? vc[q + 1] : vr);
+      acc[q] -= (q > 0 ? w0[q - 1] : wl) * (q > 0 ? vc[q - 1] : vl);
+    }
+#pragma unroll
+    for (int k = 1; k < K; k++) {
+      const int64_t o = a.off[k];
+      const bool f = u0 + o < nt, b = u0 >= o;
+      const VD wf = vload<double, R>(wh + k * nt + u0);   // 0 where u + o is past the end
+      const VD vf = vhat(f ? u0 + o : u0);
+      const VD wb = vload<double, R>(wh + k * nt + (b ? u0 - o : nt - R));   // the last R rows have no +o edge
+      const VD vb = vhat(b ? u0 - o : u0);
+      acc -= wf * vf;
+      acc -= wb * vb;
+    }
+    const VD bv = vload<double, R>(a.b + u0);
+    const VD Dv = vload<double, R>(a.D64 + u0);
+    VT zv;
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const double rh = bv[q] / sqrt(Dv[q]) - acc[q];
+      zv[q] = (T)rh;
+      x[0] += (double)zv[q] * (double)zv[q];
+      x[1] += Dv[q] * rh * rh;
+    }
+    vstore<T, R>(a.z + u0, zv);
+  }
+  write_partials<2>(x, a.partials, kPRep, lds);
+}
+
+// ----------------------------------------------------------------------------
+// Streaming probe: NR input and NW output streams of n doubles (input stream r
+// at in + r n), two rows per thread with 16-byte loads and stores, rows in XCD
+// slabs as the row-slab kernels take them.  Each output row gets the sum of
+// the inputs (plus its stream index), so no load can be dropped.  It measures
+// the bandwidth the GPU sustains for a given mix of streams, the ceiling the
+// CG kernels' rooflines are read against.
+// ----------------------------------------------------------------------------
+template <int NR, int NW>
+__global__ __launch_bounds__(kBlock) void k_stream(const double *__restrict__ in, double *__restrict__ out,
+                                                  int64_t n) {
+  typedef vec_t<double, 2> V;
+  const int64_t ng = n / 2;
+  FOR_ROWS(g, ng) {
+    V acc = vload<double, 2>(in + 2 * g);
+#pragma unroll
+    for (int r = 1; r < NR; r++) acc += vload<double, 2>(in + r * n + 2 * g);
+#pragma unroll
+    for (int w = 0; w < NW; w++) vstore<double, 2>(out + w * n + 2 * g, acc + (double)w);
+  }
+}
+
+template <int NR>
+hipError_t launch_stream_nr(const double *in, double *out, int64_t n, int nw, int grid, hipStream_t st) {
+  if (nw == 1) hipLaunchKernelGGL((k_stream<NR, 1>), dim3(grid), dim3(kBlock), 0, st, in, out, n);
+  else hipLaunchKernelGGL((k_stream<NR, 2>), dim3(grid), dim3(kBlock), 0, st, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_probe(const double *in, double *out, int64_t n, int nr, int nw, int grid, hipStream_t st) {
+  switch (nr) {
+    case 1: return launch_stream_nr<1>(in, out, n, nw, grid, st);
+    case 2: return launch_stream_nr<2>(in, out, n, nw, grid, st);
+    case 3: return launch_stream_nr<3>(in, out, n, nw, grid, st);
+    case 4: return launch_stream_nr<4>(in, out, n, nw, grid, st);
+    case 5: return launch_stream_nr<5>(in, out, n, nw, grid, st);
+    default: return launch_stream_nr<6>(in, out, n, nw, grid, st);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // per-round diagnostics (Section 2.1-2.2): smoothed objective, ||CBx||_1,
 // flow value x^T L x and the flows at s and t (Proposition 3), the range of v
@@ -1528,7 +1657,11 @@ hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_replace_residual(const CGArgs<T> &a, int grid, hipStream_t st) {
-  if (a.K > 0) hipLaunchKernelGGL((k_replace<T, true>), dim3(grid), dim3(kBlock), 0, st, a);
+  constexpr int R = kVecRows<T>;
+  if (a.scaled && a.wh64 && a.D64 && (a.K == 2 || a.K == 3) && vec_ok(a)) {
+    if (a.K == 2) hipLaunchKernelGGL((k_replace_scaled<T, 2, R>), dim3(grid), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_replace_scaled<T, 3, R>), dim3(grid), dim3(kBlock), 0, st, a);
+  } else if (a.K > 0) hipLaunchKernelGGL((k_replace<T, true>), dim3(grid), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_replace<T, false>), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }

@@ -660,6 +660,7 @@ struct irls_mincut_s {
   // working-precision state (double for precision 0, float for 1)
   void *w = nullptr, *D = nullptr, *r = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
   void *wh = nullptr;               // scaled conductances (scaled form only)
+  double *wh64 = nullptr;           // their FP64 values (precision 1, scaled form)
   bool scaled = false;              // CG on D^-1/2 L~ D^-1/2 (Jacobi as symmetric scaling)
   double *partials = nullptr;
   double *vsave = nullptr;         // potentials saved across kernel timing
@@ -785,6 +786,7 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.bj_im = h->bj_im;
   a.bj_g = h->bj_g;
   a.wh = (T *)h->wh;
+  a.wh64 = h->wh64;
   a.scaled = h->scaled ? 1 : 0;
   return a;
 }
@@ -1179,6 +1181,7 @@ irls_status alloc_state(irls_mincut_t h) {
   if (f32) {
     HIPCHK(h, h->dalloc(&h->w64, nw), "alloc");
     HIPCHK(h, h->dalloc(&h->D64, nt), "alloc");
+    if (h->scaled) HIPCHK(h, h->dalloc(&h->wh64, nw), "alloc");
   }
   HIPCHK(h, h->dalloc(&h->partials, (size_t)kNumPSlots * kNumPartial * kMaxGrid), "alloc");
   HIPCHK(h, hipMemset(h->partials, 0, (size_t)kNumPSlots * kNumPartial * kMaxGrid * sizeof(double)), "memset");
@@ -1939,6 +1942,41 @@ irls_status irls_mincut_kernel_timing(irls_mincut_t h, double *ms_working, int64
   if (n_working) *n_working = h->prof_n_work;
   if (ms_all) *ms_all = h->prof_ms_all;
   if (n_all) *n_all = h->prof_n_all;
+  return IRLS_OK;
+}
+
+irls_status irls_stream_probe(int64_t rows, int32_t reads, int32_t writes, int32_t workgroups, int32_t reps,
+                              void *hip_stream, double *avg_ms) {
+  if (!avg_ms) { g_thread_error = "avg_ms must not be NULL"; return IRLS_ERR_NULL; }
+  if (rows < 2 || rows % 2 != 0 || reads < 1 || reads > 6 || writes < 1 || writes > 2 || workgroups < 8 ||
+      workgroups > kMaxGrid || workgroups % 8 != 0 || reps < 1 || reps > 1000) {
+    g_thread_error = "need even rows >= 2, reads 1..6, writes 1..2, workgroups a multiple of 8 in 8..1024, reps 1..1000";
+    return IRLS_ERR_OPTIONS;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  double *in = nullptr, *out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&in, (size_t)reads * rows * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&out, (size_t)writes * rows * sizeof(double));
+  if (e == hipSuccess) e = launch_fill(in, (int64_t)reads * rows, 1.0, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_stream_probe(in, out, rows, reads, writes, workgroups, st);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int i = 0; i < reps && e == hipSuccess; i++) e = launch_stream_probe(in, out, rows, reads, writes, workgroups, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (in) (void)hipFree(in);
+  if (out) (void)hipFree(out);
+  if (e != hipSuccess) {
+    g_thread_error = std::string("stream probe: ") + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? IRLS_ERR_OOM : IRLS_ERR_DEVICE;
+  }
+  *avg_ms = (double)ms / reps;
   return IRLS_OK;
 }
 

@@ -66,6 +66,7 @@ struct CGArgs {
   // scaled direction and product, v holds D^1/2 v during CG, and wh the
   // scaled conductances w_uj / sqrt(D_u D_j) in the diagonal layout.
   T *wh;
+  double *wh64;                   // precision 1, scaled: FP64 scaled conductances (replacement)
   int32_t scaled;
   // reductions
   double *partials;               // [kNumPSlots][kNumPartial][kMaxGrid]
@@ -151,6 +152,9 @@ template <typename T> hipError_t launch_replace_residual(const CGArgs<T> &a, int
                                                          hipStream_t st);
 template <typename T> hipError_t launch_stats(const CGArgs<T> &a, int grid, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double value, hipStream_t st);
+// streaming probe: nr (1..6) input and nw (1..2) output streams of n doubles (n even)
+hipError_t launch_stream_probe(const double *in, double *out, int64_t n, int nr, int nw, int grid,
+                               hipStream_t st);
 
 // two-level rounding (twolevel.hip)
 struct TwoLevelBufs {

@@ -193,3 +193,18 @@ def test_in_solve_kernel_timing(P):
             mc.set_kernel_timing(2)              # the replacement kernel: precision form only
         with pytest.raises(P.IrlsError):
             mc.set_kernel_timing(0, 0)
+
+
+def test_stream_probe(P):
+    """irls_stream_probe: a positive launch time for the SpMV's mix of streams
+    and for a copy; arguments outside its range are refused."""
+    rows = 1 << 22
+    for nr, nw in ((5, 2), (1, 1)):
+        ms = P.stream_probe(rows, nr, nw, 256, 5)
+        gbs = (nr + nw) * rows * 8 / (ms * 1e-3) / 1e9
+        say(f"  {nr} reads + {nw} writes of {rows} doubles: {ms * 1e3:.1f} us, {gbs:.0f} GB/s")
+        assert ms > 0 and gbs < 20000
+    for bad in ((rows + 1, 5, 2, 256), (rows, 7, 2, 256), (rows, 5, 3, 256), (rows, 5, 2, 100)):
+        with pytest.raises(P.IrlsError) as e:
+            P.stream_probe(*bad, reps=1)
+        assert e.value.code == P.ERR_OPTIONS

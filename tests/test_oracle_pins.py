@@ -525,4 +525,77 @@ def test_block_jacobi_same_solution_fewer_iterations(oracle_mod):
         np.testing.assert_allclose(xb, xj, rtol=0, atol=1e-8)
         assert sum(r["cg_iters"] for r in sb) < sum(r["cg_iters"] for r in sj)
     assert oracle_mod.error_code(oracle_mod.irls, g, rounds=1, precond=1, block_size=0) != 0
-    assert oracle_mod.error_code(oracle_mod.irls, g, rounds=1, precond=2) != 0
+    assert oracle_mod.error_code(oracle_mod.irls, g, rounds=1, precond=3) != 0
+
+
+def tile_blocks(nx, ny, nn, tx, ty, tz):
+    """Block id of every node of gen.grid3d_box(nx, ny, nn) (s and t last):
+    tiles of tx * ty * tz nodes in x, y and z."""
+    ids = np.arange(nn + 2, dtype=np.int64)
+    x, y, z = ids % nx, (ids // nx) % ny, ids // (nx * ny)
+    bx, by = (nx + tx - 1) // tx, (ny + ty - 1) // ty
+    return (x // tx) + bx * ((y // ty) + by * (z // tz))
+
+
+def test_block_solvers_by_definition(oracle_mod):
+    """Section 3.1, eq. block-jacobi-subsystem, with the paper's two block
+    solvers, checked against their definitions on a reweighted round of a
+    6x6x4 grid cut into 3x3x2 tiles: applying M^-1 to every unit vector
+    gives M, which is block diagonal over the tiles; the exact solve has
+    M = L~ on every block; ILU(0) has M = L~ exactly on the block's pattern
+    (the defining property (LU)_ij = A_ij there) and fill elsewhere in the
+    block, so the two strategies really differ."""
+    nx, ny, nn = 6, 6, 6 * 6 * 4
+    g = gen.grid3d_box(nx, ny, nn, seed=3)
+    blk = tile_blocks(nx, ny, nn, 3, 3, 2)
+    xs = np.concatenate([rng.uniform(3, 5, np.arange(nn, dtype=np.uint64)), [1.0, 0.0]])
+    eps = 1e-2
+    rp, col, val, _ = oracle_mod.reduced_system(g, xs, eps)
+    nt = g.n - 2
+    A = np.zeros((nt, nt))
+    pat = np.zeros((nt, nt), bool)
+    for i in range(nt):
+        A[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+        pat[i, col[rp[i]:rp[i + 1]]] = True
+    same = blk[:nt, None] == blk[None, :nt]
+    scale = np.max(np.abs(A))
+    for kind in (1, 2):
+        Minv = np.stack([oracle_mod.block_apply(g, np.eye(nt)[j], kind, block_of=blk, x=xs, eps=eps)
+                         for j in range(nt)], axis=1)
+        M = np.linalg.inv(Minv)
+        assert np.max(np.abs(M[~same])) <= 1e-10 * scale            # block diagonal
+        if kind == 1:
+            assert np.max(np.abs(M - A)[same]) <= 1e-10 * scale
+        else:
+            on = same & pat
+            assert np.max(np.abs(M - A)[on]) <= 1e-10 * scale
+            fill = same & ~pat
+            assert np.max(np.abs(M[fill])) >= 1e-4 * scale           # not the exact block
+    # a tridiagonal block (one x-line of a grid) has no fill: ILU(0) is exact
+    r = rng.uniform(9, 1, np.arange(nt, dtype=np.uint64))
+    z1 = oracle_mod.block_apply(g, r, 1, block_size=nx, x=xs, eps=eps)
+    z2 = oracle_mod.block_apply(g, r, 2, block_size=nx, x=xs, eps=eps)
+    np.testing.assert_allclose(z2, z1, rtol=1e-12, atol=1e-14 * np.max(np.abs(z1)))
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.block_apply(g, r, 3, block_size=nx)
+
+
+def test_tile_blocks_same_solution_fewer_iterations(oracle_mod):
+    """Tile blocks (rows not consecutive in the numbering) for both block
+    solvers: every round converges to the potentials of Jacobi-PCG (the
+    preconditioner changes the path, not the system) in fewer CG iterations;
+    the exact blocks take no more iterations than their ILU(0)."""
+    nx, ny, nn = 12, 12, 12 * 12 * 8
+    g = gen.grid3d_box(nx, ny, nn, seed=4)
+    blk = tile_blocks(nx, ny, nn, 4, 4, 4)
+    xj, sj, _ = oracle_mod.irls(g, rounds=12, cg_rtol=1e-12)
+    its = {}
+    for kind in (1, 2):
+        xb, sb, _ = oracle_mod.irls(g, rounds=12, cg_rtol=1e-12, precond=kind, block_of=blk)
+        np.testing.assert_allclose(xb, xj, rtol=0, atol=1e-8)
+        its[kind] = sum(r["cg_iters"] for r in sb)
+    jac = sum(r["cg_iters"] for r in sj)
+    assert its[1] <= its[2] < jac
+    bad = blk.copy()
+    bad[5] = -1
+    assert oracle_mod.error_code(oracle_mod.irls, g, rounds=1, precond=2, block_of=bad) != 0
