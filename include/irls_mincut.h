@@ -175,6 +175,22 @@ irls_status irls_mincut_solve_range(irls_mincut_t h, int32_t start, const double
 irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
                             int64_t *k_star);
 
+/* irls_mincut_cut for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same sweep cut, bit for bit, with its work buffers (sort keys and ids,
+ * ranks, 128-bit deltas, scan partials, the mask) carved from one static
+ * device array of the library, which each GPU holds (about 12 MB) until the
+ * process ends.  It calls no hipMalloc, hipFree or other allocating routine.
+ * Graphs of up to IRLS_NOALLOC_MAX_NONTERMINAL non-terminal nodes; larger
+ * ones get IRLS_ERR_OPTIONS.  Every call on one GPU uses that GPU's array,
+ * whatever the handle or stream: calls that overlap on one GPU race, and the
+ * caller must order them (each call returns after its stream has finished
+ * with the array).  Arguments, results and other errors as irls_mincut_cut;
+ * IRLS_ERR_DEVICE when the array's address cannot be obtained. */
+#define IRLS_NOALLOC_MAX_NONTERMINAL 262144
+irls_status irls_mincut_cut_noalloc(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
+                                    int64_t *k_star);
+
 /* Two-level rounding of the current potentials (Section 3.4, the two-level
  * rounding procedure, and its proposition):
  *   1. K-means with two centres on all n potentials (x_s = 1, x_t = 0

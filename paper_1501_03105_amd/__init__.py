@@ -72,6 +72,7 @@ def lib():
         L.irls_mincut_solve_range.argtypes = [H, C.c_int32, C.c_void_p, C.c_double, C.c_int32,
                                               C.POINTER(RoundStats)]
         L.irls_mincut_cut.argtypes = [H, PU8, PF64, P64]
+        L.irls_mincut_cut_noalloc.argtypes = [H, PU8, PF64, P64]
         L.irls_mincut_cut_two_level.argtypes = [H, PU8, PF64, C.POINTER(TwoLevelInfo)]
         L.irls_mincut_update_capacities.argtypes = [H, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.irls_mincut_cheeger_bracket.argtypes = [H, PF64, PF64]
@@ -100,7 +101,7 @@ def lib():
         P32 = C.POINTER(C.c_int32)
         L.irls_mincut_set_row_lanes.argtypes = [H, P32]
         L.irls_mincut_autotune.argtypes = [H, C.c_int32, C.c_int32, P32]
-        for f in ("create", "solve", "solve_range", "cut", "cut_two_level", "update_capacities",
+        for f in ("create", "solve", "solve_range", "cut", "cut_noalloc", "cut_two_level", "update_capacities",
                   "cheeger_bracket", "potentials",
                   "set_potentials",
                   "info", "time_kernel", "spmv_kernel", "set_kernel_timing", "kernel_timing",
@@ -261,6 +262,18 @@ class MinCut(_RowLanes):
         ks = C.c_int64(0)
         rc = lib().irls_mincut_cut(self.h, mask.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(val),
                                    C.byref(ks))
+        if rc != OK:
+            raise self._err(rc)
+        return mask.astype(bool), val.value, ks.value
+
+    def cut_noalloc(self):
+        """irls_mincut_cut_noalloc: the sweep cut in the library's static
+        scratch (no device allocation). Returns (in_S bool [n], value, k_star)."""
+        mask = np.zeros(self.n, np.uint8)
+        val = C.c_double(0)
+        ks = C.c_int64(0)
+        rc = lib().irls_mincut_cut_noalloc(self.h, mask.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(val),
+                                           C.byref(ks))
         if rc != OK:
             raise self._err(rc)
         return mask.astype(bool), val.value, ks.value

@@ -1481,16 +1481,27 @@ irls_status irls_mincut_solve_range(irls_mincut_t h, int32_t start, const double
   }
 }
 
-irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value, int64_t *k_star) {
+// The sweep cut of the handle's potentials; its work buffers are the
+// handle's (allocated on first use) or, with noalloc, the library's static
+// scratch array.
+static irls_status cut_impl(irls_mincut_t h, bool noalloc, uint8_t *in_source_side, double *cut_value,
+                            int64_t *k_star) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
   if (h->batch) { h->err = "use irls_mincut_cut_batch for a batch handle"; return IRLS_ERR_OPTIONS; }
   if (!h->solved) { h->err = "no potentials yet: call irls_mincut_solve first"; return IRLS_ERR_NOT_SOLVED; }
+  if (noalloc && h->g.nt > IRLS_NOALLOC_MAX_NONTERMINAL) {
+    h->err = "irls_mincut_cut_noalloc takes at most " + std::to_string(IRLS_NOALLOC_MAX_NONTERMINAL) +
+             " non-terminal nodes (this graph has " + std::to_string(h->g.nt) + "): use irls_mincut_cut";
+    return IRLS_ERR_OPTIONS;
+  }
   try {
     GraphDev &g = h->g;
     i128 best = 0;
     int64_t ks = 0;
+    SweepBufs sb_static;
     if (g.nt > 0) {
-      SweepBufs &b = h->sw;
+      if (noalloc) HIPCHK(h, sweep_noalloc_buffers(g.nt, g.n, sb_static), "static scratch");
+      SweepBufs &b = noalloc ? sb_static : h->sw;
       if (!b.keyA) {
         const size_t nb = sweep_sort_blocks(g.nt), sb = sweep_scan_blocks(g.nt);
         HIPCHK(h, h->dalloc(&b.keyA, g.nt), "alloc");
@@ -1530,6 +1541,15 @@ irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cu
     h->err = "unexpected host exception";
     return IRLS_ERR_DEVICE;
   }
+}
+
+irls_status irls_mincut_cut(irls_mincut_t h, uint8_t *in_source_side, double *cut_value, int64_t *k_star) {
+  return cut_impl(h, false, in_source_side, cut_value, k_star);
+}
+
+irls_status irls_mincut_cut_noalloc(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,
+                                    int64_t *k_star) {
+  return cut_impl(h, true, in_source_side, cut_value, k_star);
 }
 
 irls_status irls_mincut_cut_two_level(irls_mincut_t h, uint8_t *in_source_side, double *cut_value,

@@ -284,5 +284,8 @@ struct SweepBatchBufs {
 hipError_t sweep_batch_run(const SweepBatchArgs &a, SweepBufs &b, SweepBatchBufs &bb, hipStream_t st);
 size_t sweep_scan_blocks(int64_t nt);
 size_t sweep_sort_blocks(int64_t nt);
+// sweep_run's buffers in the library's static scratch array on the current
+// device (nt <= IRLS_NOALLOC_MAX_NONTERMINAL); allocates nothing
+hipError_t sweep_noalloc_buffers(int64_t nt, int64_t n, SweepBufs &b);
 
 }  // namespace irls

@@ -14,6 +14,8 @@
 //   5. scan:    prefix sums of the deltas per workgroup, exclusive scan of the
 //               workgroup sums, then per-workgroup minimum and its first index
 //   6. mask:    source-side flag of every node
+#include <mutex>
+
 #include "device_common.h"
 
 namespace irls {
@@ -413,6 +415,94 @@ hipError_t sweep_run(const SweepArgs &a, SweepBufs &b, hipStream_t st) {
                        (const int64_t *)b.kstar, b.mask);
   }
   return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// Static scratch of irls_mincut_cut_noalloc: the work buffers of sweep_run for
+// up to kNoallocRows non-terminal nodes, carved from one file-scope device
+// array (each GPU holds its own copy until the process ends).  Host code uses
+// the array only through the address hipGetSymbolAddress gives on each device.
+// ----------------------------------------------------------------------------
+struct SweepLayout {
+  size_t keyA, keyB, idA, idB, rank, delta, hist, bsum, bmin, barg, best, kstar, mask, total;
+};
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr SweepLayout sweep_layout(int64_t nt, int64_t n) {
+  SweepLayout L{};
+  const size_t nb = (size_t)((nt + kSortTile - 1) / kSortTile), sb = (size_t)((nt + kScanTile - 1) / kScanTile);
+  size_t at = 0;
+  auto place = [&at](size_t bytes) {
+    const size_t off = at;
+    at = align256(at + bytes);
+    return off;
+  };
+  L.keyA = place(8 * (size_t)nt);
+  L.keyB = place(8 * (size_t)nt);
+  L.idA = place(4 * (size_t)nt);
+  L.idB = place(4 * (size_t)nt);
+  L.rank = place(4 * (size_t)nt);
+  L.delta = place(16 * (size_t)nt);
+  L.hist = place(4 * 256 * nb);
+  L.bsum = place(16 * sb);
+  L.bmin = place(16 * sb);
+  L.barg = place(8 * sb);
+  L.best = place(16 * 2);
+  L.kstar = place(8);
+  L.mask = place((size_t)n);
+  L.total = at;
+  return L;
+}
+
+constexpr int64_t kNoallocRows = IRLS_NOALLOC_MAX_NONTERMINAL;
+constexpr size_t kNoallocBytes = sweep_layout(kNoallocRows, kNoallocRows + 2).total;
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// The scratch array's address on the current device, looked up once per
+// device (each GPU holds the array at its own address).
+static hipError_t scratch_address(unsigned char **out) {
+  constexpr int kDevs = 64;
+  static std::mutex mu;
+  static unsigned char *addr[kDevs] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kDevs) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (unsigned char *)p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+hipError_t sweep_noalloc_buffers(int64_t nt, int64_t n, SweepBufs &b) {
+  if (nt > kNoallocRows || n > kNoallocRows + 2) return hipErrorInvalidValue;
+  unsigned char *base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  const SweepLayout L = sweep_layout(nt, n);
+  b.keyA = (uint64_t *)(base + L.keyA);
+  b.keyB = (uint64_t *)(base + L.keyB);
+  b.idA = (uint32_t *)(base + L.idA);
+  b.idB = (uint32_t *)(base + L.idB);
+  b.rank = (uint32_t *)(base + L.rank);
+  b.delta = (__int128 *)(base + L.delta);
+  b.hist = (uint32_t *)(base + L.hist);
+  b.bsum = (__int128 *)(base + L.bsum);
+  b.bmin = (__int128 *)(base + L.bmin);
+  b.barg = (int64_t *)(base + L.barg);
+  b.best = (__int128 *)(base + L.best);
+  b.kstar = (int64_t *)(base + L.kstar);
+  b.mask = base + L.mask;
+  b.sort_blocks = (int)sweep_sort_blocks(nt);
+  b.scan_blocks = (int)sweep_scan_blocks(nt);
+  return hipSuccess;
 }
 
 hipError_t sweep_batch_run(const SweepBatchArgs &a, SweepBufs &b, SweepBatchBufs &bb, hipStream_t st) {
