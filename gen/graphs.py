@@ -346,15 +346,17 @@ def _rmat_one(args):
 
 def rmat_batch(count=512, first_seed=1000, workers=None, **kw):
     """Instances first_seed .. first_seed+count-1 (each a pure function of its
-    seed), generated in parallel worker processes."""
+    seed), generated by a pool of threads in this process (numpy releases the
+    interpreter lock in the heavy steps).  No child process is started, so a
+    GPU or profiled process that calls this stays a single process."""
     seeds = [(first_seed + i, kw) for i in range(count)]
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
     if workers <= 1 or count < 4:
         return [_rmat_one(a) for a in seeds]
-    import multiprocessing as mp
-    with mp.get_context("spawn").Pool(workers) as pool:
-        return pool.map(_rmat_one, seeds, chunksize=1)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as pool:
+        return list(pool.map(_rmat_one, seeds))
 
 
 # ----------------------------------------------------------------------------

@@ -80,9 +80,21 @@ typedef struct {
                                     solved exactly.  Needs a grid (diagonal format, offsets
                                     1 < off[1] < ...), FP64 and the multi-workgroup solver;
                                     a block then lies inside one line of offset-1 edges, so
-                                    it is tridiagonal */
+                                    it is tridiagonal;
+                                 2: block-Jacobi over cubic tiles of a 3-D grid
+                                    (block_size^3 rows: block_size consecutive rows of
+                                    block_size lines of block_size planes), each block
+                                    solved by ILU(0) in its natural row order (Section 3.1's
+                                    second strategy: L unit lower and U upper triangular on
+                                    the block's pattern, (LU)_ij = L~_ij there), factored
+                                    once per round.  Needs a 3-D grid (diagonal format,
+                                    offsets 1, N, P with N and the P / N lines of a plane
+                                    multiples of block_size, whole planes), FP64 and the
+                                    multi-workgroup solver; tiles past the last plane are
+                                    cut short */
   int32_t block_size;         /* precond 1: rows per block, even, 2..128 and at most
-                                 off[1]; 0 = min(off[1], 128) rounded down to even */
+                                 off[1]; 0 = min(off[1], 128) rounded down to even.
+                                 precond 2: the tile edge, 2 or 4; 0 = 4 */
   int32_t unscaled_cg;        /* 0 (default): where the marching SpMV runs (3-D grids) with
                                  point Jacobi, CG runs on the symmetrically scaled system
                                  D^-1/2 L~ D^-1/2 -- in exact arithmetic the same iterates as

@@ -1089,6 +1089,149 @@ __global__ __launch_bounds__(kBlock) void k_bj_apply(CGArgs<T> a, int slot) {
   write_partials<1>(x, a.partials, slot, lds);
 }
 
+// ----------------------------------------------------------------------------
+// Block-Jacobi with ILU(0) blocks (Section 3.1, the second block strategy): the
+// blocks are cubic tiles of B x B x B rows of a 3-D grid in its natural order
+// (x fastest, then y, then z).  A grid graph has no triangles, so ILU(0) of a
+// tile leaves every off-diagonal entry as it is (U_ij = A_ij, L_ik = A_ik / d_k)
+// and changes only the pivots:
+//   d_i = D_i - sum over the tile's lower neighbours k (z-1, y-1, x-1 in that
+//         order) of (A_ik / d_k) A_ki,       A_ik = -w_ik.
+// z = (LU)^-1 r by forward substitution y_i = r_i - sum_k (A_ik / d_k) y_k and
+// backward substitution z_i = (y_i - sum_j A_ij z_j) / d_i over the upper
+// neighbours j (x+1, y+1, z+1).  One thread per tile; it moves the tile's x
+// segments (B consecutive rows) as vectors and keeps y in registers.  Tiles
+// are numbered x fastest, so a wavefront's segments are contiguous.  Since
+// U = D L^T here, r^T z = y^T D^-1 y comes out of the forward pass.
+// ----------------------------------------------------------------------------
+struct IluTiles {
+  int64_t N, P, nz, tx, ty, tiles;
+};
+
+__device__ __forceinline__ IluTiles ilu_tiles(const CGArgs<double> &a, int B) {
+  IluTiles t;
+  t.N = a.off[1];
+  t.P = a.off[2];
+  t.nz = a.nt / t.P;
+  t.tx = t.N / B;
+  t.ty = t.P / t.N / B;
+  t.tiles = t.tx * t.ty * ((t.nz + B - 1) / B);
+  return t;
+}
+
+// first row of tile k's segment (dy, dz), and whether that plane exists
+__device__ __forceinline__ int64_t ilu_seg(const IluTiles &t, int B, int64_t k, int dy, int dz, bool &ok) {
+  const int64_t x = (k % t.tx) * B, y = ((k / t.tx) % t.ty) * B + dy, z = (k / (t.tx * t.ty)) * B + dz;
+  ok = z < t.nz;
+  return z * t.P + y * t.N + x;
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_ilu_factor(CGArgs<double> a) {
+  typedef vec_t<double, B> V;
+  const IluTiles tl = ilu_tiles(a, B);
+  const int64_t nt = a.nt;
+  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  for (int64_t k = row_begin(); k < tl.tiles; k += row_stride()) {
+    V d[B][B];                                     // pivots by (dz, dy), x in the vector
+#pragma unroll
+    for (int dz = 0; dz < B; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < B; dy++) {
+        bool ok;
+        const int64_t u = ilu_seg(tl, B, k, dy, dz, ok);
+        if (!ok) continue;
+        const V D = vload<double, B>(a.D + u);
+        const V wx = vload<double, B>(w0 + u);     // wx[i] couples rows i and i + 1
+        const V wy = dy > 0 ? vload<double, B>(w1 + u - tl.N) : V(0.0);
+        const V wz = dz > 0 ? vload<double, B>(w2 + u - tl.P) : V(0.0);
+        V piv;
+#pragma unroll
+        for (int i = 0; i < B; i++) {
+          double p = D[i];
+          if (dz > 0) p -= (-wz[i] / d[dz - 1][dy][i]) * (-wz[i]);
+          if (dy > 0) p -= (-wy[i] / d[dz][dy - 1][i]) * (-wy[i]);
+          if (i > 0) p -= (-wx[i - 1] / piv[i - 1]) * (-wx[i - 1]);
+          piv[i] = p;
+        }
+        d[dz][dy] = piv;
+        vstore<double, B>(a.bj_im + u, piv);
+      }
+    }
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_ilu_apply(CGArgs<double> a, int slot) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  if (block_done(a.sc)) return;
+  typedef vec_t<double, B> V;
+  const IluTiles tl = ilu_tiles(a, B);
+  const int64_t nt = a.nt;
+  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  double x[1] = {0.0};
+  for (int64_t k = row_begin(); k < tl.tiles; k += row_stride()) {
+    V y[B][B];
+    // forward: y_i = r_i - sum_k (A_ik / d_k) y_k over the lower neighbours
+#pragma unroll
+    for (int dz = 0; dz < B; dz++) {
+#pragma unroll
+      for (int dy = 0; dy < B; dy++) {
+        bool ok;
+        const int64_t u = ilu_seg(tl, B, k, dy, dz, ok);
+        if (!ok) continue;
+        const V r = vload<double, B>(a.rbuf + u);
+        const V d = vload<double, B>(a.bj_im + u);
+        const V wx = vload<double, B>(w0 + u);
+        const V wy = dy > 0 ? vload<double, B>(w1 + u - tl.N) : V(0.0);
+        const V wz = dz > 0 ? vload<double, B>(w2 + u - tl.P) : V(0.0);
+        const V dyp = dy > 0 ? vload<double, B>(a.bj_im + u - tl.N) : V(1.0);
+        const V dzp = dz > 0 ? vload<double, B>(a.bj_im + u - tl.P) : V(1.0);
+        V yv;
+#pragma unroll
+        for (int i = 0; i < B; i++) {
+          double v = r[i];
+          if (dz > 0) v -= (-wz[i] / dzp[i]) * y[dz - 1][dy][i];
+          if (dy > 0) v -= (-wy[i] / dyp[i]) * y[dz][dy - 1][i];
+          if (i > 0) v -= (-wx[i - 1] / d[i - 1]) * yv[i - 1];
+          yv[i] = v;
+          x[0] += v * v / d[i];
+        }
+        y[dz][dy] = yv;
+      }
+    }
+    // backward: z_i = (y_i - sum_j A_ij z_j) / d_i over the upper neighbours
+#pragma unroll
+    for (int dz = B - 1; dz >= 0; dz--) {
+#pragma unroll
+      for (int dy = B - 1; dy >= 0; dy--) {
+        bool ok;
+        const int64_t u = ilu_seg(tl, B, k, dy, dz, ok);
+        if (!ok) continue;
+        bool okz;
+        (void)ilu_seg(tl, B, k, dy, dz + 1 < B ? dz + 1 : dz, okz);
+        const bool up_z = dz + 1 < B && okz;
+        const V d = vload<double, B>(a.bj_im + u);
+        const V wx = vload<double, B>(w0 + u);
+        const V wy = dy + 1 < B ? vload<double, B>(w1 + u) : V(0.0);
+        const V wz = up_z ? vload<double, B>(w2 + u) : V(0.0);
+        V zv;
+#pragma unroll
+        for (int i = B - 1; i >= 0; i--) {
+          double v = y[dz][dy][i];
+          if (i + 1 < B) v -= (-wx[i]) * zv[i + 1];
+          if (dy + 1 < B) v -= (-wy[i]) * y[dz][dy + 1][i];
+          if (up_z) v -= (-wz[i]) * y[dz + 1][dy][i];
+          zv[i] = v / d[i];
+        }
+        y[dz][dy] = zv;                              // z overwrites y, which is no longer needed
+        vstore<double, B>(a.z + u, zv);
+      }
+    }
+  }
+  write_partials<1>(x, a.partials, slot, lds);
+}
+
 // vector update with the residual kept explicitly (block-Jacobi):
 // v += alpha p, r -= alpha q; partial sums [0, ||r||^2] (k_bj_apply fills r^T z)
 template <typename T>
@@ -1630,12 +1773,26 @@ hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    if (a.bj_kind == 2) {
+      if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_factor<2>), dim3(grid), dim3(kBlock), 0, st, a);
+      else hipLaunchKernelGGL((k_ilu_factor<4>), dim3(grid), dim3(kBlock), 0, st, a);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_bj_factor<T>), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    if (a.bj_kind == 2) {
+      if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_apply<2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      else hipLaunchKernelGGL((k_ilu_apply<4>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_bj_apply<T>), dim3(grid), dim3(kBlock), 0, st, a, slot);
   return hipGetLastError();
 }

@@ -540,13 +540,14 @@ irls_status check_options(const irls_options &o, std::string &err) {
       o.chunk < 0 || (o.warm_start != 0 && o.warm_start != 1) ||
       (o.inputs_on_device != 0 && o.inputs_on_device != 1) || o.rows_per_wave < 0 ||
       o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0 || o.precond < 0 ||
-      o.precond > 1 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0 ||
+      o.precond > 2 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0 ||
+      (o.precond == 2 && o.block_size != 0 && o.block_size != 2 && o.block_size != 4) ||
       (o.unscaled_cg != 0 && o.unscaled_cg != 1) || !(o.stop_gap >= 0.0) || !(o.stop_gap < 1.0)) {
     err = "an option is out of range";
     return IRLS_ERR_OPTIONS;
   }
   if (o.precision == 1 && o.solver == 2) { err = "the resident solver runs in FP64 only"; return IRLS_ERR_OPTIONS; }
-  if (o.precond == 1 && (o.precision != 0 || o.solver == 2 || o.format == 1)) {
+  if (o.precond >= 1 && (o.precision != 0 || o.solver == 2 || o.format == 1)) {
     err = "block-Jacobi runs in FP64 on the multi-workgroup solver in the diagonal format";
     return IRLS_ERR_OPTIONS;
   }
@@ -669,6 +670,7 @@ struct irls_mincut_s {
   int64_t stats_cap = 0;            // records dstats holds
   int64_t last_iters = 0;           // CG iterations of the last round solved (chunk sizing)
   int32_t bj_block = 0;             // block-Jacobi rows per block (0: Jacobi)
+  int32_t bj_kind = 0, bj_tile = 0; // 1 line blocks (exact), 2 ILU(0) of cubic tiles
   double *bj_r = nullptr, *bj_f = nullptr, *bj_im = nullptr, *bj_g = nullptr;
   // resident solver: heavy-row chunks (device) and the single graph's record
   int32_t *hv_crow = nullptr, *hv_cbeg = nullptr, *hv_cend = nullptr;
@@ -781,6 +783,8 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.march_ty = h->march_ty;
   spmv_layout(a, h->grid);
   a.bj_block = h->bj_block;
+  a.bj_kind = h->bj_kind;
+  a.bj_tile = h->bj_tile;
   a.rbuf = h->bj_r;
   a.bj_f = h->bj_f;
   a.bj_im = h->bj_im;
@@ -1341,6 +1345,24 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
         return IRLS_ERR_OPTIONS;
       }
       h->bj_block = B;
+      h->bj_kind = 1;
+    }
+    if (o.precond == 2) {
+      // cubic tiles of a 3-D grid: offsets 1, N, P with N and P / N multiples
+      // of the tile edge, and whole planes
+      const int32_t B = o.block_size ? o.block_size : 4;
+      const bool grid3 = use_dia && hg.K == 3 && hg.off[0] == 1 && hg.off[1] > 0 &&
+                         hg.off[2] % hg.off[1] == 0 && hg.off[1] % B == 0 && (hg.off[2] / hg.off[1]) % B == 0 &&
+                         hg.nt % hg.off[2] == 0;
+      if (!grid3) {
+        g_thread_error = "ILU(0) tiles need a 3-D grid in the diagonal format whose lines and planes "
+                         "are multiples of the tile edge, with whole planes";
+        delete h;
+        return IRLS_ERR_OPTIONS;
+      }
+      h->bj_block = B * B * B;
+      h->bj_kind = 2;
+      h->bj_tile = B;
     }
     h->grid = grid_for(hg.nt);
     // Jacobi as symmetric scaling wherever the marching SpMV runs with point

@@ -84,6 +84,9 @@ struct CGArgs {
   // tridiagonal LU factors; bj_block rows per block (0: Jacobi)
   double *rbuf, *bj_f, *bj_im, *bj_g;
   int32_t bj_block;
+  // bj_kind 2: ILU(0) of cubic tiles of a 3-D grid (bj_tile rows on a side,
+  // bj_block = bj_tile^3); bj_im then holds the ILU(0) pivot of each row
+  int32_t bj_kind, bj_tile;
   int32_t grid_main;              // workgroups of the init / update / replacement kernels
   int32_t grid_spmv;              // workgroups of the SpMV kernel (its partial-sum count)
   int32_t csr_lanes;              // CSR per-round kernels: lanes per row (the SpMV's)

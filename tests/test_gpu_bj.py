@@ -1,6 +1,9 @@
-"""Block-Jacobi preconditioning (Section 3.1) on the GPU against the oracle's
-block-Jacobi PCG: blocks of consecutive rows inside one line of offset-1
-edges (tridiagonal), factored once per round and applied by wavefront scans."""
+"""Block-Jacobi preconditioning (Section 3.1, eq. block-jacobi-subsystem) on
+the GPU against the oracle's block-Jacobi PCG, with the paper's two block
+solvers: exact solves of blocks of consecutive rows inside one line of
+offset-1 edges (tridiagonal), applied by wavefront scans; and ILU(0) of
+cubic tiles of 3-D grids (precond 2), against the oracle's ILU(0) of the same
+tiles given as block ids."""
 import numpy as np
 import pytest
 
@@ -60,3 +63,53 @@ def test_block_jacobi_option_errors(P):
         assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=1, **kw) == P.ERR_OPTIONS, kw
     h = gen.gnp(16, 0.3, seed=2)                       # no diagonal layout
     assert P.create_error(h.n, h.eu, h.ev, h.cap, h.s, h.t, precond=1) == P.ERR_OPTIONS
+
+
+def tile_ids(nx, ny, nn, B):
+    """Block id of every node of gen.grid3d_box(nx, ny, nn) (s, t last): cubic
+    tiles of B rows on a side, x fastest (the oracle's blocks)."""
+    ids = np.arange(nn + 2, dtype=np.int64)
+    x, y, z = ids % nx, (ids // nx) % ny, ids // (nx * ny)
+    return (x // B) + (nx // B) * ((y // B) + (ny // B) * (z // B))
+
+
+ILU_CASES = [("box 16x12x10, tiles of 4 (a short top tile)", 16, 12, 10, 4),
+             ("box 16x12x9, tiles of 2 (a short top tile)", 16, 12, 9, 2),
+             ("box 32x32x24, tiles of 4 (the marching SpMV)", 32, 32, 24, 4)]
+
+
+@pytest.mark.parametrize("case", range(len(ILU_CASES)))
+def test_ilu0_tiles_match_oracle(P, oracle_mod, case):
+    name, nx, ny, nz, B = ILU_CASES[case]
+    g = gen.grid3d_box(nx, ny, nx * ny * nz, seed=5 + case)
+    blk = tile_ids(nx, ny, nx * ny * nz, B)
+    say(f"ILU(0) block-Jacobi: {name}")
+    xo, so, _ = oracle_mod.irls(g, precond=2, block_of=blk, **OPTS)
+    So, vo, _, _ = oracle_mod.sweep(g, xo)
+    _, sj, _ = oracle_mod.irls(g, **OPTS)
+    with P.MinCut.from_graph(g, precond=2, block_size=B, **OPTS) as mc:
+        assert mc.info()["solver"] == 1 and mc.info()["format"] == 2
+        rc, st = mc.solve()
+        x = mc.potentials()
+        S, v, _ = mc.cut()
+    err = max_pot_err(x, xo)
+    it_g = [r["cg_iters"] for r in st]
+    it_o = [r["cg_iters"] for r in so]
+    say(f"  potential error {err:.2e}; CG iterations {sum(it_g)} (oracle {sum(it_o)}, Jacobi "
+        f"{sum(r['cg_iters'] for r in sj)})")
+    assert rc == P.OK
+    assert err <= 1e-8
+    assert v == vo and np.array_equal(S, So)
+    assert all(abs(a - b) <= max(3, 0.02 * b) for a, b in zip(it_g, it_o))
+    assert all(r["true_rel_res"] <= 1e-9 for r in st)
+
+
+def test_ilu0_tile_option_errors(P):
+    ok = gen.grid3d_box(16, 12, 16 * 12 * 4, seed=1)
+    assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2) == P.OK
+    for g, kw in ((ok, dict(block_size=8)), (ok, dict(block_size=6)), (ok, dict(precision=1)),
+                  (ok, dict(format=1)), (ok, dict(solver=2)),
+                  (gen.grid3d_box(18, 12, 18 * 12 * 4, seed=1), {}),        # lines not a multiple of 4
+                  (gen.grid3d_box(16, 12, 16 * 12 * 4 + 5, seed=1), {}),    # a partial plane
+                  (gen.grid2d(64, 64, seed=0), {})):                       # not a 3-D grid
+        assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=2, **kw) == P.ERR_OPTIONS, kw
