@@ -48,6 +48,15 @@ WORKLOADS = {
     "seg128-bj": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8, precond=1),
                   "3-D 128^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi "
                   "preconditioner (x-lines of 128 rows, tridiagonal blocks)"),
+    "seg128-ilu": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=4),
+                   "3-D 128^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
+                   "(4x4x4 tiles, each block by ILU(0))"),
+    "seg256-ilu": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=4),
+                   "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
+                   "(4x4x4 tiles, each block by ILU(0))"),
+    "seg256-bj": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=1),
+                  "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi "
+                  "preconditioner (x-lines of 128 rows, tridiagonal blocks solved exactly)"),
     "gnn192": (dict(kind="gnn", train64=24, train128=4, eval_n=192, eval_seeds=8),
                dict(rounds=40, cg_rtol=1e-8),
                "learned warm start: network trained on 64^3 and 128^3 segmentation grids, "
@@ -114,8 +123,13 @@ def profiled_traffic(kernel, workload):
 
 
 def golden_run(workload):
-    """The oracle's full run of this workload, if one is stored (written on the
-    CPU by tests/golden/make_golden_fullsize.py, which calls only the oracle)."""
+    """The oracle's full FP64 Jacobi run of this workload's instance, if one is
+    stored (written on the CPU by tests/golden/make_golden_fullsize.py, which
+    calls only the oracle); the precision form and the block-Jacobi forms of
+    an instance are compared with it too."""
+    for suffix in ("-mixed", "-ilu", "-bj"):
+        if workload.endswith(suffix):
+            workload = workload[: -len(suffix)]
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle.json")
     if not os.path.exists(path):
         return None
@@ -385,6 +399,9 @@ def main():
                     help="also time the certified-gap stopping rule (stop_gap) on the same instance; 0: skip")
     ap.add_argument("--precision-form", type=int, default=1,
                     help="1: also time the precision form on the same instance; 0: skip")
+    ap.add_argument("--kernel-breakdown", type=int, default=1,
+                    help="1: one extra step per other CG kernel (update; residual replacement; "
+                         "block-Jacobi apply) timed in the solve as the SpMV is; 0: skip")
     ap.add_argument("--stream-probe", type=int, default=1,
                     help="1: also measure the GPU's streaming ceiling for the SpMV's mix of five read and "
                          "two write streams of n_nonterminal doubles (irls_stream_probe); 0: skip")
@@ -451,6 +468,24 @@ def main():
     ktime = mc.kernel_timing() if events else None
     if events:
         mc.set_kernel_timing(-1)
+    # the other CG kernels' in-solve launch times, one extra step each (after
+    # the timed steps, which stay as they are)
+    breakdown = {}
+    if events and args.kernel_breakdown:
+        kinds = [(1, "update")]
+        if opts.get("precision", 0) == 1:
+            kinds.append((2, "residual_replacement"))
+        if opts.get("precond", 0) >= 1:
+            kinds.append((3, "block_jacobi_apply"))
+        for which, nm in kinds:
+            mc.set_kernel_timing(which, args.kernel_events)
+            step()
+            kt = mc.kernel_timing()
+            mc.set_kernel_timing(-1)
+            if kt["n_working"]:
+                breakdown[nm] = {"mean_ms": round(kt["ms_working"] / kt["n_working"], 5),
+                                 "sampled_launches": kt["n_working"]}
+        print(f"[bench] in-solve kernel means: {breakdown}", file=sys.stderr, flush=True)
     iters = sum(r["cg_iters"] for r in st)
     ms_step = 1000.0 * dt / args.steps
     # the two-level rounding of the same potentials, timed on its own (it is
@@ -490,7 +525,7 @@ def main():
                 "traffic": profiled_traffic(kname, args.workload), "kernel": kname,
                 "bytes_per_launch": nbytes, "avg_launch_ms": round(spmv_ms, 5), "launch_time": how,
                 "back_to_back_launch_ms": round(b2b_ms, 5), "workgroups": spmv_grid,
-                "update_kernel_ms": round(upd_ms, 5)}
+                "update_kernel_ms_back_to_back": round(upd_ms, 5), "other_kernels_in_solve": breakdown}
         print(f"[bench] spmv {spmv_ms*1e3:.1f} us in the solve ({achieved:.0f} GB/s; back to back "
               f"{b2b_ms*1e3:.1f} us), update {upd_ms*1e3:.1f} us", file=sys.stderr, flush=True)
     mc.close()

@@ -81,20 +81,25 @@ typedef struct {
                                     1 < off[1] < ...), FP64 and the multi-workgroup solver;
                                     a block then lies inside one line of offset-1 edges, so
                                     it is tridiagonal;
-                                 2: block-Jacobi over cubic tiles of a 3-D grid
+                                 2: block-Jacobi with every block solved by ILU(0) in
+                                    ascending row order (Section 3.1's second strategy: L
+                                    unit lower and U upper triangular on the block's
+                                    pattern, (LU)_ij = L~_ij there), factored once per
+                                    round; FP64 and the multi-workgroup solver.  In the
+                                    diagonal format the blocks are cubic tiles of a 3-D grid
                                     (block_size^3 rows: block_size consecutive rows of
-                                    block_size lines of block_size planes), each block
-                                    solved by ILU(0) in its natural row order (Section 3.1's
-                                    second strategy: L unit lower and U upper triangular on
-                                    the block's pattern, (LU)_ij = L~_ij there), factored
-                                    once per round.  Needs a 3-D grid (diagonal format,
-                                    offsets 1, N, P with N and the P / N lines of a plane
-                                    multiples of block_size, whole planes), FP64 and the
-                                    multi-workgroup solver; tiles past the last plane are
-                                    cut short */
+                                    block_size lines of block_size planes; offsets 1, N, P
+                                    with N and the P / N lines of a plane multiples of
+                                    block_size, whole planes; tiles past the last plane are
+                                    cut short).  In CSR (any graph; format 1 forces it) a
+                                    block is block_size consecutive positions of a
+                                    breadth-first ordering of the non-terminal rows (from
+                                    the smallest unvisited row, neighbours in ascending
+                                    order) */
   int32_t block_size;         /* precond 1: rows per block, even, 2..128 and at most
                                  off[1]; 0 = min(off[1], 128) rounded down to even.
-                                 precond 2: the tile edge, 2 or 4; 0 = 4 */
+                                 precond 2: tiles: the tile edge, 2 or 4 (0 = 4); CSR:
+                                 rows per block, even, 2..128 (0 = 32) */
   int32_t unscaled_cg;        /* 0 (default): where the marching SpMV runs (3-D grids) with
                                  point Jacobi, CG runs on the symmetrically scaled system
                                  D^-1/2 L~ D^-1/2 -- in exact arithmetic the same iterates as
@@ -339,12 +344,13 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
  * 2 * every, ... of each round with a HIP event pair on the handle's stream,
  * and the totals are reset:
  *   which  -1 off, 0 the SpMV (with its fused direction update), 1 the vector
- *          update, 2 the FP64 residual replacement of the precision form
+ *          update, 2 the FP64 residual replacement of the precision form, 3 the
+ *          block-Jacobi application z = M^-1 r (precond 1 or 2)
  *   every  >= 1: the sampling stride (each event pair adds a marker before and
  *          after its launch, a few microseconds; a stride keeps that small)
- * Needs a single-graph handle on the multi-workgroup solver (solver 1), and
- * precision 1 for which = 2; IRLS_ERR_OPTIONS otherwise.  The solve's results
- * are unchanged. */
+ * Needs a single-graph handle on the multi-workgroup solver (solver 1),
+ * precision 1 for which = 2 and a block-Jacobi preconditioner for which = 3;
+ * IRLS_ERR_OPTIONS otherwise.  The solve's results are unchanged. */
 irls_status irls_mincut_set_kernel_timing(irls_mincut_t h, int32_t which, int32_t every);
 
 /* Totals of the in-solve timing since irls_mincut_set_kernel_timing: the

@@ -371,7 +371,8 @@ class MinCut(_RowLanes):
 
     def set_kernel_timing(self, which, every=1):
         """irls_mincut_set_kernel_timing: -1 off, 0 SpMV, 1 update, 2 residual
-        replacement; launches of iterations 0, every, 2 * every, ... are timed."""
+        replacement, 3 block-Jacobi apply; launches of iterations 0, every,
+        2 * every, ... are timed."""
         rc = lib().irls_mincut_set_kernel_timing(self.h, which, every)
         if rc != OK:
             raise self._err(rc)

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libirls_mincut.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["host.cpp", "cg.hip", "sweep.hip", "resident.hip", "twolevel.hip", "gnn.hip", "gnn_host.cpp"]
+SOURCES = ["host.cpp", "host_graph.cpp", "cg.hip", "sweep.hip", "resident.hip", "twolevel.hip", "gnn.hip", "gnn_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

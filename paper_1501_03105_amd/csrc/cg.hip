@@ -1232,6 +1232,89 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply(CGArgs<double> a, int slot
   write_partials<1>(x, a.partials, slot, lds);
 }
 
+// ----------------------------------------------------------------------------
+// ILU(0) of general blocks of a CSR graph (bj_kind 3): block k is the rows
+// blk_rows[blk_ptr[k] .. blk_ptr[k+1]) in ascending order (a piece of a
+// breadth-first ordering, chosen on the host).  Saad's row-wise ILU(0) on the
+// block's pattern: for each row i, for each lower entry k of row i in the
+// block (ascending), l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for every
+// entry j > k of row i that row k also holds (the diagonal included: the
+// pivot).  One thread per block; ilu_f holds l_ik (k < i) and u_ij (j > i) per
+// CSR entry, 0 for entries to other blocks, and bj_im the pivots u_ii.
+// ----------------------------------------------------------------------------
+// u_kj of row k (k's entry for column j), or the pivot when j == k; 0 if row k
+// has no entry j
+__device__ __forceinline__ double ilu_u(const CGArgs<double> &a, int64_t k, int64_t j) {
+  if (j == k) return a.bj_im[k];
+  int32_t lo = a.rowptr[k], hi = a.rowptr[k + 1];
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (a.col[mid] < j) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < a.rowptr[k + 1] && a.col[lo] == j ? a.ilu_f[lo] : 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_csr_factor(CGArgs<double> a) {
+  for (int64_t b = row_begin(); b < a.nblk; b += row_stride()) {
+    const int32_t r0 = a.blk_ptr[b], r1 = a.blk_ptr[b + 1];
+    for (int32_t q = r0; q < r1; q++) {
+      const int64_t i = a.blk_rows[q];
+      const int32_t e0 = a.rowptr[i], e1 = a.rowptr[i + 1];
+      for (int32_t e = e0; e < e1; e++)                     // the block's part of row i of L~
+        a.ilu_f[e] = a.row_blk[a.col[e]] == b ? -(double)a.w[e] : 0.0;
+      double piv = a.D[i];
+      for (int32_t e = e0; e < e1; e++) {
+        const int64_t k = a.col[e];
+        if (k >= i) break;
+        if (a.row_blk[k] != b) continue;                    // another block
+        const double l = a.ilu_f[e] / a.bj_im[k];
+        a.ilu_f[e] = l;
+        for (int32_t e2 = e + 1; e2 < e1; e2++) {           // entries j > k of row i
+          const int64_t j = a.col[e2];
+          if (a.row_blk[j] != b) continue;
+          a.ilu_f[e2] -= l * ilu_u(a, k, j);
+        }
+        piv -= l * ilu_u(a, k, i);                          // j = i: the pivot
+      }
+      a.bj_im[i] = piv;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_csr_apply(CGArgs<double> a, int slot) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  if (block_done(a.sc)) return;
+  double x[1] = {0.0};
+  for (int64_t b = row_begin(); b < a.nblk; b += row_stride()) {
+    const int32_t r0 = a.blk_ptr[b], r1 = a.blk_ptr[b + 1];
+    for (int32_t q = r0; q < r1; q++) {                     // y = L^-1 r, L unit lower
+      const int64_t i = a.blk_rows[q];
+      double v = a.rbuf[i];
+      for (int32_t e = a.rowptr[i]; e < a.rowptr[i + 1]; e++) {
+        const int64_t k = a.col[e];
+        if (k >= i) break;
+        const double f = a.ilu_f[e];
+        if (f != 0.0) v -= f * a.z[k];
+      }
+      a.z[i] = v;
+      x[0] += v * v / a.bj_im[i];                           // r^T z = y^T D^-1 y (U = D L^T)
+    }
+    for (int32_t q = r1 - 1; q >= r0; q--) {                // z = U^-1 y
+      const int64_t i = a.blk_rows[q];
+      double v = a.z[i];
+      for (int32_t e = a.rowptr[i + 1] - 1; e >= a.rowptr[i]; e--) {
+        const int64_t j = a.col[e];
+        if (j <= i) break;
+        const double f = a.ilu_f[e];
+        if (f != 0.0) v -= f * a.z[j];
+      }
+      a.z[i] = v / a.bj_im[i];
+    }
+  }
+  write_partials<1>(x, a.partials, slot, lds);
+}
+
 // vector update with the residual kept explicitly (block-Jacobi):
 // v += alpha p, r -= alpha q; partial sums [0, ||r||^2] (k_bj_apply fills r^T z)
 template <typename T>
@@ -1774,6 +1857,10 @@ hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st) {
 template <typename T>
 hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {
+    if (a.bj_kind == 3) {
+      hipLaunchKernelGGL(k_ilu_csr_factor, dim3(grid), dim3(kBlock), 0, st, a);
+      return hipGetLastError();
+    }
     if (a.bj_kind == 2) {
       if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_factor<2>), dim3(grid), dim3(kBlock), 0, st, a);
       else hipLaunchKernelGGL((k_ilu_factor<4>), dim3(grid), dim3(kBlock), 0, st, a);
@@ -1787,6 +1874,10 @@ hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st) {
 template <typename T>
 hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
   if constexpr (sizeof(T) == 8) {
+    if (a.bj_kind == 3) {
+      hipLaunchKernelGGL(k_ilu_csr_apply, dim3(grid), dim3(kBlock), 0, st, a, slot);
+      return hipGetLastError();
+    }
     if (a.bj_kind == 2) {
       if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_apply<2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
       else hipLaunchKernelGGL((k_ilu_apply<4>), dim3(grid), dim3(kBlock), 0, st, a, slot);

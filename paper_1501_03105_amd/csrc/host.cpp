@@ -18,541 +18,15 @@
 #include <thread>
 #include <vector>
 
+#include "host_graph.h"
 #include "internal.h"
 
 using namespace irls;
-typedef __int128 i128;
+using namespace irls_host;
 
 namespace {
 
 thread_local std::string g_thread_error;
-
-// ----------------------------------------------------------------------------
-// exact fixed point for cut values (host side of the sweep)
-// ----------------------------------------------------------------------------
-int fx_scale_of(double cmax, int64_t merged_edges) {
-  int e2 = 0;
-  if (cmax > 0.0) std::frexp(cmax, &e2);       // cmax = f 2^e2, f in [0.5, 1)
-  int L = 0;
-  while (L < 62 && ((int64_t)1 << L) < merged_edges + 1) L++;
-  return 125 - e2 - L;                          // sum of all capacities < 2^125
-}
-
-i128 fx_round_host(double c, int k) {
-  if (!(c > 0.0)) return 0;
-  uint64_t bits;
-  std::memcpy(&bits, &c, 8);
-  int ef = (int)((bits >> 52) & 0x7FF);
-  uint64_t mant = bits & ((1ull << 52) - 1);
-  int e2;
-  if (ef == 0) { e2 = -1074; } else { mant |= 1ull << 52; e2 = ef - 1075; }
-  int sh = e2 + k;
-  if (sh >= 0) return ((i128)mant) << sh;
-  int r = -sh;
-  if (r >= 64) return 0;
-  uint64_t q = mant >> r, rem = mant & ((1ull << r) - 1), half = 1ull << (r - 1);
-  if (rem > half || (rem == half && (q & 1ull))) q++;
-  return (i128)q;
-}
-
-// round-to-nearest-even conversion of a 128-bit integer, then scaling by 2^-k
-double fx_to_double(i128 v, int k) {
-  bool neg = v < 0;
-  unsigned __int128 a = neg ? (unsigned __int128)(-(v + 1)) + 1u : (unsigned __int128)v;
-  if (a == 0) return 0.0;
-  int msb = 127;
-  while (!((a >> msb) & 1u)) msb--;
-  double r;
-  if (msb <= 52) {
-    r = (double)(uint64_t)a;
-  } else {
-    int sh = msb - 52;
-    unsigned __int128 mant = a >> sh;
-    unsigned __int128 rem = a & ((((unsigned __int128)1) << sh) - 1u);
-    unsigned __int128 half = ((unsigned __int128)1) << (sh - 1);
-    if (rem > half || (rem == half && (mant & 1u))) mant++;
-    if (mant >> 53) { mant >>= 1; sh++; }
-    r = std::ldexp((double)(uint64_t)mant, sh);
-  }
-  r = std::ldexp(r, -k);
-  return neg ? -r : r;
-}
-
-// ----------------------------------------------------------------------------
-// host graph
-// ----------------------------------------------------------------------------
-struct HostGraph {
-  int64_t n = 0, s = 0, t = 0, nt = 0;
-  std::vector<int32_t> rowptr, col;
-  std::vector<double> ccap, cs, ct, dcap;
-  double cst = 0.0, cmax = 0.0;
-  int64_t merged = 0, interior = 0;
-  int32_t K = 0;
-  int32_t off[kMaxDiag] = {0};
-  bool dia_ok = false;
-  int32_t fx_k = 0;
-  i128 D0 = 0;
-  bool no_source_edges = true;
-};
-
-inline int64_t nid_of(int64_t u, int64_t s, int64_t t) { return u - (u > s) - (u > t); }
-inline int64_t orig_of(int64_t i, int64_t s, int64_t t) {
-  int64_t lo = std::min(s, t), hi = std::max(s, t);
-  if (i >= lo) i++;
-  if (i >= hi) i++;
-  return i;
-}
-
-struct UnionFind {
-  std::vector<int64_t> p;
-  explicit UnionFind(int64_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
-  int64_t find(int64_t x) {
-    while (p[x] != x) { p[x] = p[p[x]]; x = p[x]; }
-    return x;
-  }
-  void unite(int64_t a, int64_t b) {
-    a = find(a); b = find(b);
-    if (a != b) p[std::max(a, b)] = std::min(a, b);
-  }
-};
-
-irls_status build_host_graph(HostGraph &g, int64_t n, int64_t m, const int64_t *eu,
-                             const int64_t *ev, const double *cap, int64_t s, int64_t t,
-                             std::string &err) {
-  if (m > 0 && (!eu || !ev || !cap)) { err = "edge arrays must not be NULL"; return IRLS_ERR_NULL; }
-  if (n < 2 || m < 0 || s < 0 || s >= n || t < 0 || t >= n || s == t) {
-    err = "need n >= 2, m >= 0, s and t distinct nodes in [0,n)";
-    return IRLS_ERR_RANGE;
-  }
-  if (n - 2 >= (int64_t)INT32_MAX) { err = "too many nodes for 32-bit device indices"; return IRLS_ERR_RANGE; }
-  g.n = n; g.s = s; g.t = t; g.nt = n - 2;
-  const int64_t nt = g.nt;
-  for (int64_t e = 0; e < m; e++) {
-    if (eu[e] < 0 || eu[e] >= n || ev[e] < 0 || ev[e] >= n) {
-      err = "edge " + std::to_string(e) + " has an endpoint outside [0,n)";
-      return IRLS_ERR_RANGE;
-    }
-    if (!(cap[e] > 0.0) || !std::isfinite(cap[e])) {
-      err = "edge " + std::to_string(e) + " has a capacity that is not finite and positive";
-      return IRLS_ERR_CAPACITY;
-    }
-  }
-  g.cs.assign(nt, 0.0);
-  g.ct.assign(nt, 0.0);
-  // terminal edges are merged per node by a left-to-right sum in input order;
-  // interior edges are collected as (row a, row b), a < b
-  std::vector<int32_t> ia, ib;
-  std::vector<double> ic;
-  ia.reserve(m); ib.reserve(m); ic.reserve(m);
-  bool sorted = true;
-  uint64_t last = 0;
-  for (int64_t e = 0; e < m; e++) {
-    int64_t u = eu[e], v = ev[e];
-    if (u == v) continue;
-    double c = cap[e];
-    bool us = (u == s) || (v == s), ut = (u == t) || (v == t);
-    if (us && ut) { g.cst += c; continue; }
-    if (us) { g.cs[nid_of(u == s ? v : u, s, t)] += c; continue; }
-    if (ut) { g.ct[nid_of(u == t ? v : u, s, t)] += c; continue; }
-    int32_t a = (int32_t)nid_of(std::min(u, v), s, t), b = (int32_t)nid_of(std::max(u, v), s, t);
-    uint64_t key = ((uint64_t)a << 32) | (uint32_t)b;
-    if (!ia.empty() && key <= last) sorted = false;
-    last = key;
-    ia.push_back(a); ib.push_back(b); ic.push_back(c);
-  }
-  // merge parallel interior edges (stable by input order inside a key)
-  if (!sorted) {
-    std::vector<int64_t> idx(ia.size());
-    std::iota(idx.begin(), idx.end(), 0);
-    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
-      return ia[x] != ia[y] ? ia[x] < ia[y] : ib[x] < ib[y];
-    });
-    std::vector<int32_t> na, nb;
-    std::vector<double> nc;
-    na.reserve(idx.size()); nb.reserve(idx.size()); nc.reserve(idx.size());
-    for (int64_t j : idx) {
-      if (!na.empty() && na.back() == ia[j] && nb.back() == ib[j]) { nc.back() += ic[j]; continue; }
-      na.push_back(ia[j]); nb.push_back(ib[j]); nc.push_back(ic[j]);
-    }
-    ia.swap(na); ib.swap(nb); ic.swap(nc);
-  }
-  const int64_t mi = (int64_t)ia.size();
-  g.interior = mi;
-  if (2 * mi >= (int64_t)INT32_MAX) { err = "too many edges for 32-bit device indices"; return IRLS_ERR_RANGE; }
-
-  // connectivity (Proposition 1 needs G connected)
-  {
-    UnionFind uf(n);
-    for (int64_t i = 0; i < nt; i++) {
-      if (g.cs[i] > 0.0) uf.unite(orig_of(i, s, t), s);
-      if (g.ct[i] > 0.0) uf.unite(orig_of(i, s, t), t);
-    }
-    if (g.cst > 0.0) uf.unite(s, t);
-    for (int64_t e = 0; e < mi; e++) uf.unite(orig_of(ia[e], s, t), orig_of(ib[e], s, t));
-    int64_t root = uf.find(s);
-    for (int64_t u = 0; u < n; u++)
-      if (uf.find(u) != root) { err = "graph is not connected"; return IRLS_ERR_DISCONNECTED; }
-  }
-
-  // CSR over non-terminal rows, columns ascending
-  g.rowptr.assign(nt + 1, 0);
-  for (int64_t e = 0; e < mi; e++) { g.rowptr[ia[e] + 1]++; g.rowptr[ib[e] + 1]++; }
-  for (int64_t i = 0; i < nt; i++) g.rowptr[i + 1] += g.rowptr[i];
-  g.col.resize(2 * mi);
-  g.ccap.resize(2 * mi);
-  {
-    std::vector<int32_t> pos(g.rowptr.begin(), g.rowptr.end() - 1);
-    for (int64_t e = 0; e < mi; e++) { int32_t r = ib[e]; g.col[pos[r]] = ia[e]; g.ccap[pos[r]++] = ic[e]; }
-    for (int64_t e = 0; e < mi; e++) { int32_t r = ia[e]; g.col[pos[r]] = ib[e]; g.ccap[pos[r]++] = ic[e]; }
-  }
-
-  // diagonal format: few distinct offsets b - a and at least half of the slots used
-  {
-    int32_t offs[kMaxDiag + 1];
-    int K = 0;
-    bool ok = true;
-    for (int64_t e = 0; e < mi && ok; e++) {
-      int32_t d = ib[e] - ia[e];
-      int k = 0;
-      while (k < K && offs[k] != d) k++;
-      if (k == K) {
-        if (K == kMaxDiag) ok = false;
-        else offs[K++] = d;
-      }
-    }
-    if (ok && K > 0 && 2 * mi >= (int64_t)K * nt) {
-      std::sort(offs, offs + K);
-      g.K = K;
-      for (int k = 0; k < K; k++) g.off[k] = offs[k];
-      g.dia_ok = true;
-    }
-  }
-  if (g.dia_ok) {
-    g.dcap.assign((size_t)g.K * nt, 0.0);
-    for (int64_t e = 0; e < mi; e++) {
-      int32_t d = ib[e] - ia[e];
-      int k = 0;
-      while (g.off[k] != d) k++;
-      g.dcap[(size_t)k * nt + ia[e]] = ic[e];
-    }
-  }
-
-  // fixed-point scale of exact cut values and the cut of S_0 = {s}
-  double cmax = g.cst;
-  int64_t merged = mi + (g.cst > 0.0);
-  for (int64_t e = 0; e < mi; e++) cmax = std::max(cmax, ic[e]);
-  for (int64_t i = 0; i < nt; i++) {
-    if (g.cs[i] > 0.0) { merged++; cmax = std::max(cmax, g.cs[i]); g.no_source_edges = false; }
-    if (g.ct[i] > 0.0) { merged++; cmax = std::max(cmax, g.ct[i]); }
-  }
-  g.cmax = cmax;
-  g.merged = merged;
-  g.fx_k = fx_scale_of(cmax, merged);
-  g.D0 = fx_round_host(g.cst, g.fx_k);
-  for (int64_t i = 0; i < nt; i++) g.D0 += fx_round_host(g.cs[i], g.fx_k);
-  return IRLS_OK;
-}
-
-// ----------------------------------------------------------------------------
-// Exact maximum flow / minimum cut of an undirected graph with 128-bit
-// integer capacities (the coarse graph of the two-level rounding): the first
-// phase of push-relabel, which ends in a maximum preflow.  Active nodes are
-// discharged highest label first; labels are reset to exact residual
-// distances to t by a reverse breadth-first search at the start and after
-// work proportional to the graph, and the gap heuristic lifts every node
-// above an emptied label to n (such nodes cannot reach t).
-// The returned source side is the set of nodes that cannot reach t in the
-// residual graph of the preflow.  Nodes that reach t hold no excess at the
-// end, so the preflow saturates every arc into that set and carries nothing
-// out of it.  Returning the excess to s (the second phase) would only change
-// arcs outside it, so it is also the set a maximum flow gives: the largest
-// minimum-cut source side.
-// ----------------------------------------------------------------------------
-struct FlowGraph {
-  int64_t n = 0;
-  std::vector<int64_t> first;     // [n+1] arcs of node v
-  std::vector<int64_t> to, mate;  // [arcs]
-  std::vector<i128> res;          // residual capacity
-};
-
-FlowGraph flow_graph(int64_t n, const std::vector<int64_t> &a, const std::vector<int64_t> &b,
-                     const std::vector<i128> &c) {
-  FlowGraph F;
-  F.n = n;
-  F.first.assign(n + 1, 0);
-  for (size_t e = 0; e < a.size(); e++) { F.first[a[e] + 1]++; F.first[b[e] + 1]++; }
-  for (int64_t v = 0; v < n; v++) F.first[v + 1] += F.first[v];
-  const int64_t na = F.first[n];
-  F.to.resize(na);
-  F.mate.resize(na);
-  F.res.resize(na);
-  std::vector<int64_t> fill(F.first.begin(), F.first.end() - 1);
-  for (size_t e = 0; e < a.size(); e++) {           // an undirected edge: two arcs of capacity c
-    const int64_t x = fill[a[e]]++, y = fill[b[e]]++;
-    F.to[x] = b[e]; F.res[x] = c[e]; F.mate[x] = y;
-    F.to[y] = a[e]; F.res[y] = c[e]; F.mate[y] = x;
-  }
-  return F;
-}
-
-i128 max_flow(FlowGraph &F, int64_t s, int64_t t, std::vector<uint8_t> &source_side) {
-  const int64_t n = F.n;
-  std::vector<int64_t> d(n, n), cur(n), queue(n);
-  std::vector<i128> ex(n, 0);
-  std::vector<int64_t> anext(n, -1), ahead(n + 1, -1);               // active nodes by label
-  std::vector<int64_t> lnext(n, -1), lprev(n, -1), lhead(n + 1, -1);  // all nodes by label (< n)
-  int64_t amax = -1, lmax = -1;
-  auto list_insert = [&](int64_t v) {
-    const int64_t h = lhead[d[v]];
-    lnext[v] = h;
-    lprev[v] = -1;
-    if (h >= 0) lprev[h] = v;
-    lhead[d[v]] = v;
-    lmax = std::max(lmax, d[v]);
-  };
-  auto list_remove = [&](int64_t v) {
-    if (lprev[v] >= 0) lnext[lprev[v]] = lnext[v];
-    else lhead[d[v]] = lnext[v];
-    if (lnext[v] >= 0) lprev[lnext[v]] = lprev[v];
-  };
-  auto activate = [&](int64_t v) {
-    anext[v] = ahead[d[v]];
-    ahead[d[v]] = v;
-    amax = std::max(amax, d[v]);
-  };
-  auto global_relabel = [&]() {
-    std::fill(d.begin(), d.end(), n);
-    std::fill(ahead.begin(), ahead.end(), -1);
-    std::fill(lhead.begin(), lhead.end(), -1);
-    amax = lmax = -1;
-    int64_t qh = 0, qt = 0;
-    d[t] = 0;
-    queue[qt++] = t;
-    while (qh < qt) {
-      const int64_t y = queue[qh++];
-      for (int64_t a = F.first[y]; a < F.first[y + 1]; a++) {
-        const int64_t x = F.to[a];
-        if (x != s && d[x] == n && F.res[F.mate[a]] > 0) { d[x] = d[y] + 1; queue[qt++] = x; }
-      }
-    }
-    for (int64_t v = 0; v < n; v++) {
-      if (v == s || v == t || d[v] >= n) continue;
-      cur[v] = F.first[v];
-      list_insert(v);
-      if (ex[v] > 0) activate(v);
-    }
-  };
-  for (int64_t a = F.first[s]; a < F.first[s + 1]; a++) {      // saturate every arc out of s
-    const i128 c = F.res[a];
-    if (c <= 0) continue;
-    F.res[a] = 0;
-    F.res[F.mate[a]] += c;
-    ex[F.to[a]] += c;
-  }
-  global_relabel();
-  int64_t work = 0;
-  const int64_t work_limit = 6 * n + (int64_t)F.to.size();
-  while (amax >= 0) {
-    const int64_t v = ahead[amax];
-    if (v < 0) { amax--; continue; }
-    ahead[amax] = anext[v];
-    if (d[v] != amax || ex[v] <= 0) continue;         // lifted by a gap after it was queued
-    while (ex[v] > 0) {
-      if (cur[v] == F.first[v + 1]) {                  // no admissible arc left: relabel
-        const int64_t old = d[v];
-        list_remove(v);
-        if (lhead[old] < 0) {                          // gap at `old`
-          for (int64_t L = old + 1; L <= lmax; L++) {
-            for (int64_t x = lhead[L]; x >= 0; x = lnext[x]) d[x] = n;
-            lhead[L] = -1;
-          }
-          lmax = old - 1;
-          d[v] = n;
-          break;
-        }
-        int64_t m = n;
-        for (int64_t a = F.first[v]; a < F.first[v + 1]; a++)
-          if (F.res[a] > 0) m = std::min(m, d[F.to[a]] + 1);
-        work += 12 + (F.first[v + 1] - F.first[v]);
-        d[v] = m;
-        if (m >= n) break;
-        cur[v] = F.first[v];
-        list_insert(v);
-        continue;
-      }
-      const int64_t a = cur[v], w = F.to[a];
-      if (F.res[a] > 0 && d[w] == d[v] - 1) {          // push along an admissible arc
-        const i128 delta = std::min(ex[v], F.res[a]);
-        F.res[a] -= delta;
-        F.res[F.mate[a]] += delta;
-        ex[v] -= delta;
-        if (w != t && ex[w] == 0) activate(w);
-        ex[w] += delta;
-      } else {
-        cur[v]++;
-      }
-    }
-    if (work > work_limit) {
-      global_relabel();
-      work = 0;
-    }
-  }
-  // nodes that reach t through residual arcs form the sink side
-  std::vector<uint8_t> reach(n, 0);
-  int64_t qh = 0, qt = 0;
-  reach[t] = 1;
-  queue[qt++] = t;
-  while (qh < qt) {
-    const int64_t y = queue[qh++];
-    for (int64_t a = F.first[y]; a < F.first[y + 1]; a++) {
-      const int64_t x = F.to[a];
-      if (!reach[x] && F.res[F.mate[a]] > 0) { reach[x] = 1; queue[qt++] = x; }
-    }
-  }
-  source_side.assign(n, 0);
-  for (int64_t v = 0; v < n; v++) source_side[v] = reach[v] ? 0 : 1;
-  return ex[t];
-}
-
-// Minimum s_c-t_c cut of the coarse graph: nodes 0..nc-1 with capacity ws[u]
-// to s_c = nc and wt[u] to t_c = nc + 1, edges (eu, ev, ecap) among them, and
-// st between s_c and t_c.
-//   * The flow along s_c - u - t_c (min(ws, wt) per node) and along s_c - t_c
-//     is taken first, so each node keeps at most one terminal edge.  The arcs
-//     into s_c and out of t_c this leaves out lie on no augmenting path.
-//   * The rest splits into the connected components of the Sc-Sc edges:
-//     they share only s_c and t_c, so each is a max-flow problem of its own
-//     (a node reaching t_c through s_c would contradict maximality).  The
-//     components run on host threads, largest first.
-// Returns the flow (= the cut value) and the largest source side (nc + 2
-// entries): the nodes that cannot reach t_c in the residual graph.
-i128 coarse_min_cut(int64_t nc, const std::vector<int32_t> &eu, const std::vector<int32_t> &ev,
-                    const std::vector<i128> &ecap, const std::vector<i128> &ws, const std::vector<i128> &wt,
-                    i128 st, std::vector<uint8_t> &side) {
-  i128 flow = st;
-  std::vector<i128> rs(nc), rt(nc);
-  for (int64_t u = 0; u < nc; u++) {
-    const i128 d = std::min(ws[u], wt[u]);
-    flow += d;
-    rs[u] = ws[u] - d;
-    rt[u] = wt[u] - d;
-  }
-  side.assign(nc + 2, 0);
-  side[nc] = 1;
-  if (nc == 0) return flow;
-  UnionFind uf(nc);
-  for (size_t e = 0; e < eu.size(); e++) uf.unite(eu[e], ev[e]);
-  // components: dense ids, members in ascending order, edges grouped
-  std::vector<int64_t> comp(nc), cstart, pos(nc);
-  int64_t ncomp = 0;
-  {
-    std::vector<int64_t> id_of_root(nc, -1);
-    for (int64_t u = 0; u < nc; u++) {
-      const int64_t r = uf.find(u);
-      if (id_of_root[r] < 0) id_of_root[r] = ncomp++;
-      comp[u] = id_of_root[r];
-    }
-  }
-  cstart.assign(ncomp + 1, 0);
-  for (int64_t u = 0; u < nc; u++) cstart[comp[u] + 1]++;
-  for (int64_t c = 0; c < ncomp; c++) cstart[c + 1] += cstart[c];
-  std::vector<int64_t> members(nc), fillm(cstart.begin(), cstart.end() - 1);
-  for (int64_t u = 0; u < nc; u++) { pos[u] = fillm[comp[u]] - cstart[comp[u]]; members[fillm[comp[u]]++] = u; }
-  std::vector<int64_t> estart(ncomp + 1, 0), edges(eu.size());
-  for (size_t e = 0; e < eu.size(); e++) estart[comp[eu[e]] + 1]++;
-  for (int64_t c = 0; c < ncomp; c++) estart[c + 1] += estart[c];
-  std::vector<int64_t> fille(estart.begin(), estart.end() - 1);
-  for (size_t e = 0; e < eu.size(); e++) edges[fille[comp[eu[e]]]++] = (int64_t)e;
-  std::vector<int64_t> order(ncomp);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-    return cstart[x + 1] - cstart[x] > cstart[y + 1] - cstart[y];
-  });
-  auto solve = [&](int64_t c) -> i128 {
-    const int64_t k = cstart[c + 1] - cstart[c];
-    const int64_t *mem = members.data() + cstart[c];
-    if (estart[c + 1] == estart[c]) {                 // a lone node: no path through it
-      for (int64_t i = 0; i < k; i++) side[mem[i]] = rt[mem[i]] > 0 ? 0 : 1;
-      return 0;
-    }
-    std::vector<int64_t> fa, fb;
-    std::vector<i128> fc;
-    for (int64_t q = estart[c]; q < estart[c + 1]; q++) {
-      const int64_t e = edges[q];
-      fa.push_back(pos[eu[e]]); fb.push_back(pos[ev[e]]); fc.push_back(ecap[e]);
-    }
-    for (int64_t i = 0; i < k; i++) {
-      const int64_t u = mem[i];
-      if (rs[u] > 0) { fa.push_back(k); fb.push_back(i); fc.push_back(rs[u]); }
-      if (rt[u] > 0) { fa.push_back(i); fb.push_back(k + 1); fc.push_back(rt[u]); }
-    }
-    FlowGraph F = flow_graph(k + 2, fa, fb, fc);
-    std::vector<uint8_t> ls;
-    const i128 f = max_flow(F, k, k + 1, ls);
-    for (int64_t i = 0; i < k; i++) side[mem[i]] = ls[i];
-    return f;
-  };
-  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const int nth = (int)std::min<int64_t>({(int64_t)std::min(hw, 16u), ncomp, nc / 4096 + 1});
-  std::vector<i128> part(nth, 0);
-  std::atomic<int64_t> next{0};
-  // an exception in a worker (an allocation failure) stops the others from
-  // taking more components and is rethrown here, after every thread joined
-  std::vector<std::exception_ptr> errs(nth);
-  auto worker = [&](int tid) {
-    try {
-      for (int64_t q; (q = next.fetch_add(1)) < ncomp;) part[tid] += solve(order[q]);
-    } catch (...) {
-      errs[tid] = std::current_exception();
-      next.store(ncomp);
-    }
-  };
-  std::vector<std::thread> pool;
-  try {
-    for (int tid = 1; tid < nth; tid++) pool.emplace_back(worker, tid);
-  } catch (const std::system_error &) {
-    // fewer threads than asked for: the running ones take the remaining work
-  }
-  worker(0);
-  for (auto &th : pool) th.join();
-  for (const std::exception_ptr &e : errs)
-    if (e) std::rethrow_exception(e);
-  for (const i128 f : part) flow += f;
-  return flow;
-}
-
-// C = 2 * (sum of all merged capacities): interior edges are stored in both
-// rows of the CSR, terminal edges once per node, and the s-t edge once.
-double total_capacity2(const HostGraph &g) {
-  double c = 0.0;
-  for (double x : g.ccap) c += x;
-  for (double x : g.cs) c += 2.0 * x;
-  for (double x : g.ct) c += 2.0 * x;
-  return c + 2.0 * g.cst;
-}
-
-irls_status check_options(const irls_options &o, std::string &err) {
-  if (o.struct_size != (int32_t)sizeof(irls_options)) { err = "irls_options.struct_size mismatch"; return IRLS_ERR_OPTIONS; }
-  if (o.rounds < 0 || o.weight_form < 0 || o.weight_form > 1 || o.init < 0 || o.init > 2 ||
-      !(o.cg_rtol > 0.0) || o.cg_maxit < 1 || (o.rounds > 0 && !(o.eps0 > 0.0)) ||
-      !(o.eps_factor > 0.0) || o.eps_factor > 1.0 || o.precision < 0 || o.precision > 1 ||
-      o.refine_every < 0 || o.format < 0 || o.format > 2 || o.solver < 0 || o.solver > 2 ||
-      o.chunk < 0 || (o.warm_start != 0 && o.warm_start != 1) ||
-      (o.inputs_on_device != 0 && o.inputs_on_device != 1) || o.rows_per_wave < 0 ||
-      o.rows_per_wave > 64 || (o.rows_per_wave & (o.rows_per_wave - 1)) != 0 || o.precond < 0 ||
-      o.precond > 2 || o.block_size < 0 || o.block_size > 128 || (o.block_size & 1) != 0 ||
-      (o.precond == 2 && o.block_size != 0 && o.block_size != 2 && o.block_size != 4) ||
-      (o.unscaled_cg != 0 && o.unscaled_cg != 1) || !(o.stop_gap >= 0.0) || !(o.stop_gap < 1.0)) {
-    err = "an option is out of range";
-    return IRLS_ERR_OPTIONS;
-  }
-  if (o.precision == 1 && o.solver == 2) { err = "the resident solver runs in FP64 only"; return IRLS_ERR_OPTIONS; }
-  if (o.precond >= 1 && (o.precision != 0 || o.solver == 2 || o.format == 1)) {
-    err = "block-Jacobi runs in FP64 on the multi-workgroup solver in the diagonal format";
-    return IRLS_ERR_OPTIONS;
-  }
-  return IRLS_OK;
-}
 
 // workgroups of the streaming kernels: a multiple of the 8 XCDs (see slab_rows)
 int grid_for(int64_t rows) {
@@ -670,7 +144,11 @@ struct irls_mincut_s {
   int64_t stats_cap = 0;            // records dstats holds
   int64_t last_iters = 0;           // CG iterations of the last round solved (chunk sizing)
   int32_t bj_block = 0;             // block-Jacobi rows per block (0: Jacobi)
-  int32_t bj_kind = 0, bj_tile = 0; // 1 line blocks (exact), 2 ILU(0) of cubic tiles
+  int32_t bj_kind = 0, bj_tile = 0; // 1 line blocks (exact), 2 ILU(0) of cubic tiles,
+                                    // 3 ILU(0) of CSR blocks of a breadth-first ordering
+  int64_t nblk = 0;
+  int32_t *blk_ptr = nullptr, *blk_rows = nullptr, *row_blk = nullptr;
+  double *ilu_f = nullptr;
   double *bj_r = nullptr, *bj_f = nullptr, *bj_im = nullptr, *bj_g = nullptr;
   // resident solver: heavy-row chunks (device) and the single graph's record
   int32_t *hv_crow = nullptr, *hv_cbeg = nullptr, *hv_cend = nullptr;
@@ -785,6 +263,11 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.bj_block = h->bj_block;
   a.bj_kind = h->bj_kind;
   a.bj_tile = h->bj_tile;
+  a.nblk = h->nblk;
+  a.blk_ptr = h->blk_ptr;
+  a.blk_rows = h->blk_rows;
+  a.row_blk = h->row_blk;
+  a.ilu_f = h->ilu_f;
   a.rbuf = h->bj_r;
   a.bj_f = h->bj_f;
   a.bj_im = h->bj_im;
@@ -836,7 +319,8 @@ hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a0, int64_t first
     if (e == hipSuccess)
       e = timed_launch(h, 0, a.it_hint, [&] { return launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream); });
     if (e == hipSuccess) e = timed_launch(h, 1, a.it_hint, [&] { return launch_update(a, h->grid, h->stream); });
-    if (e == hipSuccess && a.bj_block > 0) e = launch_bj_apply(a, h->grid, kPUpd, h->stream);
+    if (e == hipSuccess && a.bj_block > 0)
+      e = timed_launch(h, 3, a.it_hint, [&] { return launch_bj_apply(a, h->grid, kPUpd, h->stream); });
     if (e == hipSuccess && h->opt.precision == 1)
       e = timed_launch(h, 2, a.it_hint, [&] { return launch_replace_residual(a, h->grid, h->stream); });
   }
@@ -1168,6 +652,7 @@ irls_status alloc_state(irls_mincut_t h) {
   };
   HIPCHK(h, h->dalloc(&h->v, nt), "alloc");
   HIPCHK(h, h->dalloc(&h->b, nt), "alloc");
+  if (h->bj_kind == 3) HIPCHK(h, h->dalloc(&h->ilu_f, h->g.nnz), "alloc");
   if (h->bj_block > 0) {
     HIPCHK(h, h->dalloc(&h->bj_r, nt), "alloc");
     HIPCHK(h, h->dalloc(&h->bj_f, nt), "alloc");
@@ -1245,31 +730,6 @@ hipStream_t handle_stream(irls_mincut_t h) { return h->stream; }
 // ----------------------------------------------------------------------------
 extern "C" {
 
-void irls_options_default(irls_options *o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->struct_size = (int32_t)sizeof(irls_options);
-  o->rounds = 30;
-  o->eps0 = 0.1;
-  o->eps_factor = 0.5;
-  o->weight_form = 0;
-  o->init = 0;
-  o->warm_start = 1;
-  o->cg_rtol = 1e-10;
-  o->cg_maxit = 100000;
-  o->precision = 0;
-  o->refine_every = 20;
-  o->fp64_weights_below_eps = 1e-4;
-  o->format = 0;
-  o->solver = 0;
-  o->chunk = 0;
-  o->inputs_on_device = 0;
-  o->rows_per_wave = 0;
-  o->precond = 0;
-  o->block_size = 0;
-  o->unscaled_cg = 0;
-  o->stop_gap = 0.0;
-}
 
 irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const int64_t *edge_u,
                                const int64_t *edge_v, const double *cap, int64_t s, int64_t t,
@@ -1347,16 +807,53 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
       h->bj_block = B;
       h->bj_kind = 1;
     }
-    if (o.precond == 2) {
+    std::vector<int32_t> blk_ptr, blk_rows, row_blk;
+    if (o.precond == 2 && !use_dia) {
+      // CSR: blocks of B consecutive positions of a breadth-first ordering
+      // (from the smallest unvisited row, neighbours in ascending order), each
+      // block's rows taken in ascending order
+      const int32_t B = o.block_size ? o.block_size : 32;
+      const int64_t nt = hg.nt;
+      std::vector<int32_t> order;
+      order.reserve(nt);
+      std::vector<uint8_t> seen(nt, 0);
+      for (int64_t r = 0; r < nt; r++) {
+        if (seen[r]) continue;
+        size_t head = order.size();
+        seen[r] = 1;
+        order.push_back((int32_t)r);
+        while (head < order.size()) {
+          const int32_t u = order[head++];
+          for (int32_t e = hg.rowptr[u]; e < hg.rowptr[u + 1]; e++) {
+            const int32_t v = hg.col[e];
+            if (!seen[v]) { seen[v] = 1; order.push_back(v); }
+          }
+        }
+      }
+      const int64_t nb = (nt + B - 1) / B;
+      blk_ptr.resize(nb + 1);
+      row_blk.resize(nt);
+      for (int64_t k = 0; k <= nb; k++) blk_ptr[k] = (int32_t)std::min<int64_t>(k * B, nt);
+      blk_rows = order;
+      for (int64_t k = 0; k < nb; k++) {
+        std::sort(blk_rows.begin() + blk_ptr[k], blk_rows.begin() + blk_ptr[k + 1]);
+        for (int32_t q = blk_ptr[k]; q < blk_ptr[k + 1]; q++) row_blk[blk_rows[q]] = (int32_t)k;
+      }
+      h->bj_block = B;
+      h->bj_kind = 3;
+      h->nblk = nb;
+    }
+    if (o.precond == 2 && use_dia) {
       // cubic tiles of a 3-D grid: offsets 1, N, P with N and P / N multiples
       // of the tile edge, and whole planes
       const int32_t B = o.block_size ? o.block_size : 4;
-      const bool grid3 = use_dia && hg.K == 3 && hg.off[0] == 1 && hg.off[1] > 0 &&
+      const bool grid3 = (B == 2 || B == 4) && hg.K == 3 && hg.off[0] == 1 && hg.off[1] > 0 &&
                          hg.off[2] % hg.off[1] == 0 && hg.off[1] % B == 0 && (hg.off[2] / hg.off[1]) % B == 0 &&
                          hg.nt % hg.off[2] == 0;
       if (!grid3) {
-        g_thread_error = "ILU(0) tiles need a 3-D grid in the diagonal format whose lines and planes "
-                         "are multiples of the tile edge, with whole planes";
+        g_thread_error = "ILU(0) tiles need a tile edge of 2 or 4 and a 3-D grid in the diagonal format "
+                         "whose lines and planes are multiples of it, with whole planes (format 1 gives "
+                         "CSR blocks instead)";
         delete h;
         return IRLS_ERR_OPTIONS;
       }
@@ -1384,6 +881,9 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
         (rc = upload(h, &g.cs, hg.cs)) != IRLS_OK ||
         (rc = upload(h, &g.ct, hg.ct)) != IRLS_OK ||
         (use_dia && (rc = upload(h, &g.dcap, hg.dcap)) != IRLS_OK) ||
+        (h->bj_kind == 3 && ((rc = upload(h, &h->blk_ptr, blk_ptr)) != IRLS_OK ||
+                             (rc = upload(h, &h->blk_rows, blk_rows)) != IRLS_OK ||
+                             (rc = upload(h, &h->row_blk, row_blk)) != IRLS_OK)) ||
         (rc = upload_heavy(h, H)) != IRLS_OK ||
         (rc = alloc_state(h)) != IRLS_OK) {
       g_thread_error = h->err;
@@ -1964,10 +1464,11 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
 
 irls_status irls_mincut_set_kernel_timing(irls_mincut_t h, int32_t which, int32_t every) {
   if (!h) { g_thread_error = "handle must not be NULL"; return IRLS_ERR_NULL; }
-  if (which < -1 || which > 2) { h->err = "which must be -1, 0, 1 or 2"; return IRLS_ERR_OPTIONS; }
+  if (which < -1 || which > 3) { h->err = "which must be -1, 0, 1, 2 or 3"; return IRLS_ERR_OPTIONS; }
   if (every < 1) { h->err = "every must be at least 1"; return IRLS_ERR_OPTIONS; }
   if (h->batch || h->solver != 1) { h->err = "kernel timing needs the multi-workgroup solver"; return IRLS_ERR_OPTIONS; }
   if (which == 2 && h->opt.precision != 1) { h->err = "which = 2 needs the precision form"; return IRLS_ERR_OPTIONS; }
+  if (which == 3 && h->bj_block == 0) { h->err = "which = 3 needs a block-Jacobi preconditioner"; return IRLS_ERR_OPTIONS; }
   h->prof_which = which;
   h->prof_every = every;
   h->prof_rounds.clear();

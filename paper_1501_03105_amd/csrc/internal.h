@@ -7,13 +7,14 @@
 #include <vector>
 
 #include "../../include/irls_mincut.h"
+#include "host_graph.h"
 
 namespace irls {
 
 constexpr int kBlock = 256;          // threads per workgroup of the streaming kernels
 constexpr int kMaxBlock = 512;       // largest workgroup (the marching SpMV's wide tiles)
 constexpr int kMaxGrid = 1024;       // workgroups of the streaming kernels (grid-stride)
-constexpr int kMaxDiag = 8;          // most index offsets the diagonal format stores
+using irls_host::kMaxDiag;            // most index offsets the diagonal format stores
 constexpr int kNumPartial = 11;      // reduction slots per workgroup
 
 // CG state shared between consecutive kernels of one solve, in device memory.
@@ -85,8 +86,14 @@ struct CGArgs {
   double *rbuf, *bj_f, *bj_im, *bj_g;
   int32_t bj_block;
   // bj_kind 2: ILU(0) of cubic tiles of a 3-D grid (bj_tile rows on a side,
-  // bj_block = bj_tile^3); bj_im then holds the ILU(0) pivot of each row
+  // bj_block = bj_tile^3); bj_im then holds the ILU(0) pivot of each row.
+  // bj_kind 3: ILU(0) of CSR blocks (nblk of them; rows blk_rows[blk_ptr[k] ..
+  // blk_ptr[k+1]) ascending), factor values per CSR entry in ilu_f (0 for
+  // entries leaving the block), pivots in bj_im
   int32_t bj_kind, bj_tile;
+  int64_t nblk;
+  const int32_t *blk_ptr, *blk_rows, *row_blk;
+  double *ilu_f;
   int32_t grid_main;              // workgroups of the init / update / replacement kernels
   int32_t grid_spmv;              // workgroups of the SpMV kernel (its partial-sum count)
   int32_t csr_lanes;              // CSR per-round kernels: lanes per row (the SpMV's)

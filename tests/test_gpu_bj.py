@@ -107,9 +107,86 @@ def test_ilu0_tiles_match_oracle(P, oracle_mod, case):
 def test_ilu0_tile_option_errors(P):
     ok = gen.grid3d_box(16, 12, 16 * 12 * 4, seed=1)
     assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2) == P.OK
+    # format 1 on the same grid is allowed: CSR blocks instead of tiles
+    assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2, format=1, solver=1) == P.OK
     for g, kw in ((ok, dict(block_size=8)), (ok, dict(block_size=6)), (ok, dict(precision=1)),
-                  (ok, dict(format=1)), (ok, dict(solver=2)),
+                  (ok, dict(solver=2)),
                   (gen.grid3d_box(18, 12, 18 * 12 * 4, seed=1), {}),        # lines not a multiple of 4
                   (gen.grid3d_box(16, 12, 16 * 12 * 4 + 5, seed=1), {}),    # a partial plane
                   (gen.grid2d(64, 64, seed=0), {})):                       # not a 3-D grid
+        assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=2, **kw) == P.ERR_OPTIONS, kw
+
+
+def bfs_blocks(g, B):
+    """Block ids of the CSR ILU(0) blocks by their stated rule, written out
+    here on its own: the non-terminal nodes in ascending id are the rows; a
+    breadth-first ordering of the rows over the interior edges, from the
+    smallest unvisited row with neighbours in ascending order; block q is
+    positions q*B .. q*B + B - 1 of that ordering."""
+    n, s, t = g.n, g.s, g.t
+    row = np.full(n, -1, np.int64)
+    nts = [u for u in range(n) if u != s and u != t]
+    row[nts] = np.arange(len(nts))
+    nbrs = [set() for _ in nts]
+    for a, b in zip(g.eu.tolist(), g.ev.tolist()):
+        if a != b and row[a] >= 0 and row[b] >= 0:
+            nbrs[row[a]].add(int(row[b]))
+            nbrs[row[b]].add(int(row[a]))
+    seen = [False] * len(nts)
+    order = []
+    for r in range(len(nts)):
+        if seen[r]:
+            continue
+        seen[r] = True
+        q = [r]
+        head = 0
+        while head < len(q):
+            u = q[head]
+            head += 1
+            for v in sorted(nbrs[u]):
+                if not seen[v]:
+                    seen[v] = True
+                    q.append(v)
+        order += q
+    blk = np.zeros(n, np.int64)
+    for pos, r in enumerate(order):
+        blk[nts[r]] = pos // B
+    return blk
+
+
+CSR_CASES = [("R-MAT (FlowImprove), blocks of 32", lambda: gen.rmat_flowimprove(2003, log2_lo=9.0, log2_hi=10.0), 32),
+             ("G(60, 0.1), blocks of 8", lambda: gen.gnp(60, 0.1, seed=4), 8),
+             ("grid2d 40x30 as CSR, blocks of 16", lambda: gen.grid2d(40, 30, seed=2), 16)]
+
+
+@pytest.mark.parametrize("case", range(len(CSR_CASES)))
+def test_ilu0_csr_blocks_match_oracle(P, oracle_mod, case):
+    name, make, B = CSR_CASES[case]
+    g = make()
+    blk = bfs_blocks(g, B)
+    say(f"ILU(0) CSR blocks: {name} (n = {g.n})")
+    xo, so, _ = oracle_mod.irls(g, precond=2, block_of=blk, **OPTS)
+    So, vo, _, _ = oracle_mod.sweep(g, xo)
+    _, sj, _ = oracle_mod.irls(g, **OPTS)
+    with P.MinCut.from_graph(g, precond=2, block_size=B, format=1, solver=1, **OPTS) as mc:
+        assert mc.info()["format"] == 1
+        rc, st = mc.solve()
+        x = mc.potentials()
+        S, v, _ = mc.cut()
+    err = max_pot_err(x, xo)
+    it_g = [r["cg_iters"] for r in st]
+    it_o = [r["cg_iters"] for r in so]
+    say(f"  potential error {err:.2e}; CG iterations {sum(it_g)} (oracle {sum(it_o)}, Jacobi "
+        f"{sum(r['cg_iters'] for r in sj)})")
+    assert rc == P.OK
+    assert err <= 1e-8
+    assert v == vo and np.array_equal(S, So)
+    assert all(abs(a - b) <= max(3, 0.02 * b) for a, b in zip(it_g, it_o))
+    assert all(r["true_rel_res"] <= 1e-9 for r in st)
+
+
+def test_ilu0_csr_option_errors(P):
+    g = gen.gnp(40, 0.15, seed=3)
+    assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=2, solver=1) == P.OK
+    for kw in (dict(block_size=3), dict(block_size=130), dict(precision=1), dict(solver=2)):
         assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=2, **kw) == P.ERR_OPTIONS, kw
