@@ -36,8 +36,9 @@ WORKLOADS = {
     "seg256": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8),
                "3-D 6-connected 256^3 segmentation grid, FP64 (plain), 40 rounds, CG to 1e-8"),
     "rmat512": (dict(kind="rmat", count=512, seed=1000), dict(rounds=30, cg_rtol=1e-8),
-                "512 R-MAT FlowImprove-style instances (2^10..2^17 nodes drawn, isolated nodes "
-                "dropped, average degree ~13), FP64, 30 rounds, CG to 1e-8, one persistent launch"),
+                "512 R-MAT FlowImprove-style instances (2^10..2^17 nodes drawn, average degree 8 before "
+                "the isolated nodes are dropped, about 14.5 after), FP64, 30 rounds, CG to 1e-8, one "
+                "persistent launch"),
     "seg256-mixed": (dict(kind="seg", N=256, seed=2),
                      dict(rounds=40, cg_rtol=1e-8, precision=1, refine_every=20),
                      "3-D 256^3 segmentation grid, FP32 conductances/SpMV/CG vectors, FP64 "
@@ -57,7 +58,7 @@ WORKLOADS = {
     "seg256-bj": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=1),
                   "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi "
                   "preconditioner (x-lines of 128 rows, tridiagonal blocks solved exactly)"),
-    "gnn192": (dict(kind="gnn", train64=24, train128=4, eval_n=192, eval_seeds=8),
+    "gnn192": (dict(kind="gnn", train64=96, train128=16, cost_graphs=48, eval_n=192, eval_seeds=8),
                dict(rounds=40, cg_rtol=1e-8),
                "learned warm start: network trained on 64^3 and 128^3 segmentation grids, "
                "evaluated on held-out 192^3 grids (seeds 20000..); time-to-cut at relative cut "
@@ -263,6 +264,33 @@ def bench_batch(args, spec, opts, desc):
           f"({plain_rate:.1f} cuts/s); largest cut difference from the batch {worst:.1e}",
           file=sys.stderr, flush=True)
     rate = len(gs) * args.steps / dt
+    # roofline of the persistent launch: its algorithmic bytes (per CG
+    # iteration of a graph 12 B per stored CSR entry and 104 B per row, the
+    # count of the multi-workgroup CSR path's SpMV, direction and update
+    # kernels) over the batch's time per step (the launch plus the batched
+    # sweep, a few per cent of it)
+    nnz = [2 * g.meta["interior"] for g in gs]
+    rows = [g.n - 2 for g in gs]
+    batch_bytes = sum(it * (12 * z + 104 * r) for it, z, r in zip(iters, nnz, rows))
+    achieved = batch_bytes / (dt / args.steps) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_resident",
+            "bytes_per_launch": int(batch_bytes), "avg_launch_ms": round(1000 * dt / args.steps, 3),
+            "note": "one launch solves every round of every graph; the largest graphs, one workgroup each, "
+                    "set its length, so it is bound by their memory latency, not by bandwidth"}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample_b = order[::32]
+        t0 = time.perf_counter()
+        for i in sample_b:
+            oracle.irls(gs[i], rounds=opts["rounds"], cg_rtol=opts["cg_rtol"], allow_maxit=True)
+        t_orc = time.perf_counter() - t0
+        cpu = {"value": len(sample_b) / t_orc, "unit": "cuts/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "sample": f"oracle IRLS ({opts['rounds']} rounds, CG to {opts['cg_rtol']}) of every 32nd graph "
+                         f"in size order ({len(sample_b)} graphs) in {t_orc:.1f} s, one after another"}
+        print(f"[bench] oracle on {len(sample_b)} sampled graphs: {t_orc:.1f} s", file=sys.stderr, flush=True)
     out = {
         "metric": "IRLS s-t min-cut throughput of the batched form (cuts per second)",
         "value": round(rate, 3), "unit": "cuts/s", "n_gpus": 1,
@@ -272,6 +300,9 @@ def bench_batch(args, spec, opts, desc):
         "config": {"workload": desc, "name": args.workload, "graphs": len(gs),
                    "nodes": int(sum(g.n for g in gs)),
                    "interior_edges": int(sum(g.meta["interior"] for g in gs)),
+                   "average_degree_after_isolated_nodes_dropped":
+                       round(2 * sum(g.meta["interior"] for g in gs) / sum(g.n - 2 for g in gs), 2),
+                   "arithmetic": "FP64 (conductances, SpMV, CG vectors and dots)",
                    "cg_iters_total": int(sum(iters)), "cg_iters_max_graph": int(max(iters)),
                    "setup_s": round(t_setup, 3),
                    "autotune": {"lanes_per_row_by_bin": lanes, "seconds": round(t_tune, 3),
@@ -288,14 +319,17 @@ def bench_batch(args, spec, opts, desc):
                        "sample": f"every 16th graph in size order ({len(sample)} graphs), "
                                  "multi-workgroup FP64 solver, solve + sweep each; the rate is the "
                                  "faster of its default and autotuned rows per wavefront"}},
-        "roofline": None, "cpu_baseline": None,
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
 def bench_gnn(args, spec, opts, desc):
-    """Learned warm start: train, then time-to-cut on held-out 192^3 grids
-    with and without the network (per-round sweeps only decide when to stop)."""
+    """Learned warm start: train, then time-to-cut on held-out 192^3 grids for
+    the plain start, the best constant first eps (chosen on the training
+    graphs, no network) and the network's start.  Every start runs its rounds
+    down to the plain schedule's last eps and is then cut (nothing knows the
+    answer); its cut is then compared with the plain start's."""
     import numpy as np
     import torch
 
@@ -316,66 +350,82 @@ def bench_gnn(args, spec, opts, desc):
         for i in range(cnt):
             g, I = seg(N, base + i)
             ex.append(W.make_example(g, I, opts, stream=stream))
-            say(f"training graph {N}^3 seed {base + i}: cut {ex[-1].ref_cut:.8g}")
+            if (i + 1) % 8 == 0:
+                say(f"{i + 1} of {cnt} training graphs of {N}^3 solved")
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
-    net, gamma, costs = W.fit(ex, args.gnn_epochs, args.gnn_epochs // 2, stream=stream, log=say)
+    net, gamma, costs = W.fit(ex, args.gnn_epochs, args.gnn_epochs // 2, stream=stream, log=say,
+                              max_cost_graphs=spec["cost_graphs"])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    # the no-network baseline: the best constant first eps on (the same
+    # subset of) the training graphs
+    t0 = time.perf_counter()
+    sub = [ex[int(i)] for i in np.linspace(0, len(ex) - 1, min(len(ex), spec["cost_graphs"]))]
+    eps_c, table = W.best_constant_eps(sub, stream=stream, log=say)
+    t_const = time.perf_counter() - t0
+    say(f"best constant first eps on the training graphs: {eps_c:.3g} ({ {f'{k:.0e}': v for k, v in table.items()} })")
     for e in ex:
         e.mc.close()
     del ex
     rows = []
+    tol = 1e-6
     for k in range(spec["eval_seeds"]):
         sd = 20000 + k
         g, I = seg(spec["eval_n"], sd)
         mc = P.MinCut.from_graph(g, stream=stream, solver=1, **opts)
-        mc.solve()
-        _, ref, _ = mc.cut()
-        plain = W.time_to_cut(mc, ref, 1e-6, 2 * opts["rounds"], stream=stream)
-        warm = W.time_to_cut(mc, ref, 1e-6, 2 * opts["rounds"], net=net, gamma=gamma, intensity=I,
-                             stream=stream)
+        W.time_to_final(mc, stream=stream)                  # warm-up
+        plain = W.time_to_final(mc, stream=stream)          # the plain schedule: its cut is the reference
+        ref = plain["cut"]
+        const = W.time_to_final(mc, eps_first=eps_c, stream=stream)
+        warm = W.time_to_final(mc, net=net, gamma=gamma, intensity=I, stream=stream)
+        # hindsight: the best constant for this graph (context, not a baseline)
+        best_h = min((W.time_to_final(mc, eps_first=e, stream=stream) for e in W.EPS_GRID),
+                     key=lambda r: (r["cut"] > ref * (1 + tol), r["seconds"]))
         mc.close()
-        # the learned start on the precision form (FP32 SpMV and vectors), same reference cut
         mc32 = P.MinCut.from_graph(g, stream=stream, solver=1, precision=1, refine_every=20, **opts)
-        W.time_to_cut(mc32, ref, 1e-6, 2 * opts["rounds"], net=net, gamma=gamma, intensity=I,
-                      stream=stream)                         # warm-up of the FP32 kernels
-        both = W.time_to_cut(mc32, ref, 1e-6, 2 * opts["rounds"], net=net, gamma=gamma, intensity=I,
-                             stream=stream)
+        W.time_to_final(mc32, net=net, gamma=gamma, intensity=I, stream=stream)     # warm-up
+        both = W.time_to_final(mc32, net=net, gamma=gamma, intensity=I, stream=stream)
         mc32.close()
-        rows.append((sd, ref, plain, warm, both))
-        say(f"eval {spec['eval_n']}^3 seed {sd}: plain {plain['rounds']} rounds {plain['cg_iters']} CG "
-            f"{plain['seconds']:.3f}s | warm {warm['rounds']} rounds {warm['cg_iters']} CG "
-            f"{warm['seconds']:.3f}s eps_1 {warm['eps_first']:.2e} reached {warm['reached']} | "
-            f"warm+FP32 {both['seconds']:.3f}s reached {both['reached']}")
-    sp = sum(r[2]["seconds"] for r in rows)
-    sw = sum(r[3]["seconds"] for r in rows)
-    sb = sum(r[4]["seconds"] for r in rows)
+        for r in (const, warm, best_h, both):
+            r["rel_cut_error"] = (r["cut"] - ref) / ref
+        rows.append((sd, ref, plain, const, warm, best_h, both))
+        say(f"eval {spec['eval_n']}^3 seed {sd}: plain {plain['cg_iters']} CG {plain['seconds']:.3f}s | "
+            f"constant eps_1 {eps_c:.2g} {const['cg_iters']} CG {const['seconds']:.3f}s err {const['rel_cut_error']:.1e} | "
+            f"warm eps_1 {warm['eps_first']:.2g} {warm['cg_iters']} CG {warm['seconds']:.3f}s "
+            f"err {warm['rel_cut_error']:.1e} | warm+FP32 {both['seconds']:.3f}s err {both['rel_cut_error']:.1e}")
+    tot = lambda j: sum(r[j]["seconds"] for r in rows)
+    its = lambda j: sum(r[j]["cg_iters"] for r in rows)
+    ok = lambda j: all(r[j]["rel_cut_error"] <= tol for r in rows)
+    sp, sc, sw, sh, sb = tot(2), tot(3), tot(4), tot(5), tot(6)
     out = {
-        "metric": "learned warm start: end-to-end time-to-cut speedup vs the plain start at cut "
-                  "relative error <= 1e-6",
-        "value": round(sp / sw, 4), "unit": "x", "n_gpus": 1, "steps": len(rows), "warmup": 0,
+        "metric": "learned warm start: end-to-end time-to-cut speedup vs the plain start (rounds down to the "
+                  "plain schedule's last eps, then the sweep cut; cut relative error vs the plain start's)",
+        "value": round(sp / sw, 4), "unit": "x", "n_gpus": 1, "steps": len(rows), "warmup": 1,
         "ms_per_step": round(1000 * sw / len(rows), 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 solve, bf16/f32 network", "data": "synthetic",
         "config": {"workload": desc, "name": args.workload,
-                   "train_graphs": {"64^3": spec["train64"], "128^3": spec["train128"]},
+                   "train_graphs": {"64^3": spec["train64"], "128^3": spec["train128"],
+                                    "start_costs_and_eps_targets_on": len(sub)},
                    "epochs": [args.gnn_epochs, args.gnn_epochs // 2], "gamma": gamma,
-                   "data_s": round(t_data, 1), "train_s": round(t_train, 1),
-                   "all_reached": all(r[3]["reached"] for r in rows),
-                   "warm_start_with_precision_form": {
-                       "speedup_vs_plain_fp64": round(sp / sb, 4),
-                       "all_reached": all(r[4]["reached"] for r in rows),
-                       "cg_iters": sum(r[4]["cg_iters"] for r in rows),
-                       "rounds": sum(r[4]["rounds"] for r in rows)},
-                   "rounds": {"plain": sum(r[2]["rounds"] for r in rows),
-                              "warm": sum(r[3]["rounds"] for r in rows)},
-                   "cg_iters": {"plain": sum(r[2]["cg_iters"] for r in rows),
-                                "warm": sum(r[3]["cg_iters"] for r in rows)},
+                   "data_s": round(t_data, 1), "train_s": round(t_train, 1), "constant_choice_s": round(t_const, 1),
+                   "speedup_vs_best_constant_eps": round(sc / sw, 4),
+                   "best_constant_eps": eps_c,
+                   "best_constant": {"speedup_vs_plain": round(sp / sc, 4), "cg_iters": its(3),
+                                     "all_within_1e-6": ok(3)},
+                   "warm": {"cg_iters": its(4), "all_within_1e-6": ok(4),
+                            "max_rel_cut_error": max(r[4]["rel_cut_error"] for r in rows)},
+                   "hindsight_best_constant_per_graph": {"speedup_vs_plain": round(sp / sh, 4),
+                                                         "all_within_1e-6": ok(5)},
+                   "warm_start_with_precision_form": {"speedup_vs_plain_fp64": round(sp / sb, 4),
+                                                      "all_within_1e-6": ok(6), "cg_iters": its(6)},
+                   "plain": {"cg_iters": its(2), "rounds": rows[0][2]["rounds"]},
                    "per_graph": [{"seed": r[0], "cut": r[1], "plain_s": round(r[2]["seconds"], 4),
-                                  "warm_s": round(r[3]["seconds"], 4), "plain_cg": r[2]["cg_iters"],
-                                  "warm_cg": r[3]["cg_iters"], "warm_rounds": r[3]["rounds"],
-                                  "plain_rounds": r[2]["rounds"], "eps_1": r[3]["eps_first"],
-                                  "reached": r[3]["reached"]} for r in rows]},
+                                  "const_s": round(r[3]["seconds"], 4), "warm_s": round(r[4]["seconds"], 4),
+                                  "plain_cg": r[2]["cg_iters"], "const_cg": r[3]["cg_iters"],
+                                  "warm_cg": r[4]["cg_iters"], "warm_eps_1": r[4]["eps_first"],
+                                  "warm_err": r[4]["rel_cut_error"], "const_err": r[3]["rel_cut_error"]}
+                                 for r in rows]},
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))
@@ -399,6 +449,9 @@ def main():
                     help="also time the certified-gap stopping rule (stop_gap) on the same instance; 0: skip")
     ap.add_argument("--precision-form", type=int, default=1,
                     help="1: also time the precision form on the same instance; 0: skip")
+    ap.add_argument("--march-tile", default="", metavar="THREADS,LINES",
+                    help="tile shape of the marching SpMV (irls_mincut_set_march_tile); default: the "
+                         "library's")
     ap.add_argument("--kernel-breakdown", type=int, default=1,
                     help="1: one extra step per other CG kernel (update; residual replacement; "
                          "block-Jacobi apply) timed in the solve as the SpMV is; 0: skip")
@@ -436,6 +489,9 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     info = mc.info()
+    if args.march_tile:
+        mc.set_march_tile(*[int(v) for v in args.march_tile.split(",")])
+    mc_tile = mc.march_tile() if info["solver"] == 1 else None
     print(f"[bench] create {t_setup:.1f}s info {info}", file=sys.stderr, flush=True)
 
     def step():
@@ -633,6 +689,7 @@ def main():
         "dtype": "f32+f64" if opts.get("precision", 0) == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "name": args.workload, "n_nonterminal": info["n_nonterminal"],
+                   "march_tile": list(mc_tile) if mc_tile else None,
                    "interior_edges": info["nnz_offdiag"] // 2, "format": info["format"],
                    "solver": info["solver"], "cg_iters_per_cut": iters,
                    "step_ms": [round(t, 3) for t in step_ms],

@@ -1232,6 +1232,96 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply(CGArgs<double> a, int slot
   write_partials<1>(x, a.partials, slot, lds);
 }
 
+// The same ILU(0) application for 4x4x4 tiles, a wavefront per four tiles
+// that are neighbours in x: lane (q, y, z) = 16 q + 4 z + y owns the x
+// segment (4 rows, one 32-byte vector per array) at (y, z) of tile q.  Each
+// lane loads its own segment once: r, the pivots, and its edges to x + 1,
+// y + 1 and z + 1; the edges from below and the neighbours' values come from
+// the lanes one and four below (or above) by shuffles.  The substitutions run
+// as wavefronts over the anti-diagonals y + z (seven steps each way); within a
+// segment the x recurrence runs in the lane.  The order of every sum is the
+// thread-per-tile kernel's.
+__device__ __forceinline__ vec_t<double, 4> shfl4(vec_t<double, 4> v, int src) {
+  vec_t<double, 4> o;
+#pragma unroll
+  for (int i = 0; i < 4; i++) o[i] = __shfl(v[i], src, 64);
+  return o;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int slot) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  if (block_done(a.sc)) return;
+  typedef vec_t<double, 4> V;
+  const IluTiles tl = ilu_tiles(a, 4);
+  const int64_t nt = a.nt;
+  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  const int lane = threadIdx.x & 63, q = lane >> 4, y = lane & 3, z = (lane >> 2) & 3;
+  const int lo_y = lane > 0 ? lane - 1 : 0, lo_z = lane >= 4 ? lane - 4 : 0;
+  const int up_y = lane < 63 ? lane + 1 : 63, up_z = lane < 60 ? lane + 4 : 63;
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const V zero = 0.0;
+  double x[1] = {0.0};
+  for (int64_t tb = wv * 4; tb < tl.tiles; tb += nwv * 4) {     // the same trip count on every lane
+    const int64_t k = tb + q;
+    bool ok = false;
+    int64_t u = 0;
+    if (k < tl.tiles) u = ilu_seg(tl, 4, k, y, z, ok);
+    const V r = ok ? vload<double, 4>(a.rbuf + u) : zero;
+    const V d = ok ? vload<double, 4>(a.bj_im + u) : V(1.0);
+    const V wx = ok ? vload<double, 4>(w0 + u) : zero;          // wx[i] couples rows i and i + 1
+    const V wy = ok ? vload<double, 4>(w1 + u) : zero;          // edges to y + 1
+    const V wz = ok ? vload<double, 4>(w2 + u) : zero;          // edges to z + 1
+    const V wy_lo = shfl4(wy, lo_y), wz_lo = shfl4(wz, lo_z);   // edges from y - 1, z - 1
+    const V d_ylo = shfl4(d, lo_y), d_zlo = shfl4(d, lo_z);
+    // every lane takes part in the shuffles (a shuffle inside a condition
+    // would read lanes that skipped it)
+    const int ok_up_y = __shfl((int)ok, up_y, 64), ok_up_z = __shfl((int)ok, up_z, 64);
+    const bool ok_yup = y < 3 && ok_up_y != 0;
+    const bool ok_zup = z < 3 && ok_up_z != 0;
+    // forward: y_i = r_i - sum_k (A_ik / d_k) y_k over z - 1, y - 1, x - 1
+    V yv = zero;
+    for (int st = 0; st <= 6; st++) {
+      const V yy = shfl4(yv, lo_y), yz = shfl4(yv, lo_z);
+      if (ok && y + z == st) {
+        V t;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          double v = r[i];
+          if (z > 0) v -= (-wz_lo[i] / d_zlo[i]) * yz[i];
+          if (y > 0) v -= (-wy_lo[i] / d_ylo[i]) * yy[i];
+          if (i > 0) v -= (-wx[i - 1] / d[i - 1]) * t[i - 1];
+          t[i] = v;
+        }
+        yv = t;
+      }
+    }
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < 4; i++) x[0] += yv[i] * yv[i] / d[i];          // r^T z = y^T D^-1 y
+    }
+    // backward: z_i = (y_i - sum_j A_ij z_j) / d_i over x + 1, y + 1, z + 1
+    V zv = zero;
+    for (int st = 6; st >= 0; st--) {
+      const V zy = shfl4(zv, up_y), zz = shfl4(zv, up_z);
+      if (ok && y + z == st) {
+        V t;
+#pragma unroll
+        for (int i = 3; i >= 0; i--) {
+          double v = yv[i];
+          if (i < 3) v -= (-wx[i]) * t[i + 1];
+          if (ok_yup) v -= (-wy[i]) * zy[i];
+          if (ok_zup) v -= (-wz[i]) * zz[i];
+          t[i] = v / d[i];
+        }
+        zv = t;
+      }
+    }
+    if (ok) vstore<double, 4>(a.z + u, zv);
+  }
+  write_partials<1>(x, a.partials, slot, lds);
+}
+
 // ----------------------------------------------------------------------------
 // ILU(0) of general blocks of a CSR graph (bj_kind 3): block k is the rows
 // blk_rows[blk_ptr[k] .. blk_ptr[k+1]) in ascending order (a piece of a
@@ -1880,7 +1970,7 @@ hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t s
     }
     if (a.bj_kind == 2) {
       if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_apply<2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
-      else hipLaunchKernelGGL((k_ilu_apply<4>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      else hipLaunchKernelGGL(k_ilu_apply4w, dim3(grid), dim3(kBlock), 0, st, a, slot);
       return hipGetLastError();
     }
   }

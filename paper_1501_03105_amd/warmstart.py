@@ -1,6 +1,7 @@
 """Learned warm start: training examples, training, the choice of how the
-prediction enters the start, and the round-by-round solves that measure what
-the network saves.
+prediction enters the start, the no-network baseline (the best constant first
+eps, chosen on the training graphs), and the solves that measure what the
+network saves.
 
 Every computation runs in the library (irls_gnn_* for the network,
 irls_mincut_* for IRLS); this module only sequences the calls.
@@ -40,23 +41,57 @@ def _sync(stream):
         stream.synchronize()
 
 
-def run_rounds(mc, ref_cut, tol, eps_first, factor, max_rounds, stream=None):
-    """Reweighted rounds from the potentials mc holds, one at a time, until the
-    sweep cut is within tol (relative) of ref_cut or max_rounds are done.
-    Returns (rounds, CG iterations, seconds in the solves, last cut)."""
-    rounds, iters, sec = 0, 0, 0.0
+def schedule_rounds(eps_first, eps_last, factor):
+    """Rounds from eps_first down to eps_last (inclusive) at the given factor."""
+    return max(1, int(np.floor(np.log(eps_last / eps_first) / np.log(factor) + 1e-9)) + 1)
+
+
+def time_to_final(mc, eps_first=None, net=None, gamma=0.0, intensity=None, stream=None):
+    """Round 0, then (with a network) the warm start, then the reweighted
+    rounds from the first round's eps down to the plain schedule's last eps
+    (eps0 * factor^(T-1)) in one solve, then the sweep cut: a start that skips
+    the early rounds ends at the same smoothing as the plain start, and
+    nothing here knows the answer.  eps_first: the first round's eps (default:
+    the options' eps0, or the network's prediction snapped to the schedule).
+    Returns rounds, CG iterations, seconds (all of it timed) and the cut."""
+    o = mc.opt
+    eps_last = o.eps0 * o.eps_factor ** (o.rounds - 1)
+    _sync(stream)
+    t0 = time.perf_counter()
+    _, st0 = mc.solve_range(0, 0)
+    le = None
+    if net is not None:
+        le = net.warm_start(mc, gamma, intensity)
+    if eps_first is None:
+        eps_first = o.eps0 if le is None else snap_eps(le, o.eps0, o.eps_factor, min(EPS_GRID))
+    k = schedule_rounds(eps_first, eps_last, o.eps_factor)
+    _, st = mc.solve_range(1, k, eps_first=eps_first)
     _, val, _ = mc.cut()
-    eps = eps_first
-    while val > ref_cut * (1.0 + tol) and rounds < max_rounds:
-        t0 = time.perf_counter()
-        _, st = mc.solve_range(1, 1, eps_first=eps)
-        _sync(stream)
-        sec += time.perf_counter() - t0
-        iters += st[1]["cg_iters"]
-        rounds += 1
-        eps *= factor
-        _, val, _ = mc.cut()
-    return rounds, iters, sec, val
+    _sync(stream)
+    sec = time.perf_counter() - t0
+    return dict(rounds=k, cg_iters=int(st0[0]["cg_iters"] + sum(r["cg_iters"] for r in st[1:])),
+                seconds=sec, cut=val, eps_first=eps_first, log_eps=le)
+
+
+def best_constant_eps(examples, eps_grid=EPS_GRID, tol=1e-6, stream=None, log=None):
+    """The no-network baseline: the first eps (from eps_grid and the options'
+    eps0) with the least total CG work over the training graphs, among those
+    whose cut is within tol of every graph's reference under time_to_final.
+    Returns (eps, {eps: (total CG iterations, all reached)})."""
+    table = {}
+    cands = sorted(set(eps_grid) | {examples[0].mc.opt.eps0}, reverse=True)
+    for eps in cands:
+        tot, ok = 0, True
+        for e in examples:
+            r = time_to_final(e.mc, eps_first=eps, stream=stream)
+            tot += r["cg_iters"]
+            ok &= r["cut"] <= e.ref_cut * (1.0 + tol)
+        table[eps] = (tot, ok)
+        if log:
+            log(f"constant first eps {eps:.3g}: {tot} CG iterations, all cuts reached: {ok}")
+    feasible = [eps for eps in cands if table[eps][1]]
+    best = min(feasible, key=lambda eps: table[eps][0]) if feasible else examples[0].mc.opt.eps0
+    return best, table
 
 
 def make_example(g, intensity, opts, stream=None):
@@ -91,37 +126,50 @@ def train(gnn, examples, epochs, lr=1e-3, lam=0.01, seed=0, log=None):
 
 
 def start_costs(gnn, e, gammas=GAMMAS, eps_grid=EPS_GRID, tol=1e-6, stream=None):
-    """CG iterations to reach the example's cut from every (gamma, eps_1)
-    start (inf where max rounds do not reach it)."""
+    """CG iterations of the rounds from every (gamma, eps_1) start down to the
+    plain schedule's last eps (inf where the cut is not within tol of the
+    example's).  The blend x_r0 + gamma (xhat - x_r0) is formed on the device
+    by irls_gnn_warm_start."""
     o = e.mc.opt
-    xh, _ = gnn.predict(e.mc, e.intensity, x_start=e.x_r0)
+    eps_last = o.eps0 * o.eps_factor ** (o.rounds - 1)
     out = np.full((len(gammas), len(eps_grid)), np.inf)
     for i, gam in enumerate(gammas):
-        x0 = e.x_r0 + gam * (xh - e.x_r0)
         for j, eps in enumerate(eps_grid):
-            e.mc.solve_range(2, 0, x0=x0)
-            _, it, _, val = run_rounds(e.mc, e.ref_cut, tol, eps, o.eps_factor, o.rounds, stream)
+            e.mc.set_potentials(e.x_r0)
+            gnn.warm_start(e.mc, gam, e.intensity)
+            _, st = e.mc.solve_range(1, schedule_rounds(eps, eps_last, o.eps_factor), eps_first=eps)
+            _, val, _ = e.mc.cut()
             if val <= e.ref_cut * (1.0 + tol):
-                out[i, j] = it
+                out[i, j] = sum(r["cg_iters"] for r in st[1:])
+    _sync(stream)
     return out
 
 
 def fit(examples, epochs_x, epochs_eps, lr=1e-3, seed=0, gammas=GAMMAS, eps_grid=EPS_GRID, stream=None,
-        log=None):
-    """Two stages.  (1) Train on the converged potentials.  (2) With that x
-    head, measure every (gamma, eps_1) start on the training graphs; gamma is
-    the one with the least total CG work, each graph's eps target is its best
-    eps_1 under that gamma; train on, now with the eps term weighted in.
-    Returns (network, gamma, cost table [graphs, gammas, eps])."""
+        log=None, max_cost_graphs=None):
+    """Two stages.  (1) Train on the converged potentials of every example.
+    (2) With that x head, measure every (gamma, eps_1) start on the training
+    graphs (at most max_cost_graphs of them, evenly spaced); gamma is the one
+    with the least total CG work, each measured graph's eps target is its best
+    eps_1 under that gamma; train on those graphs, now with the eps term
+    weighted in.  Returns (network, gamma, cost table [graphs, gammas, eps])."""
     net = Gnn(seed=seed)
-    h1 = train(net, examples, epochs_x, lr=lr, lam=0.0, seed=seed)
-    costs = np.stack([start_costs(net, e, gammas, eps_grid, stream=stream) for e in examples])
+    h1 = train(net, examples, epochs_x, lr=lr, lam=0.0, seed=seed, log=log)
+    sub = examples
+    if max_cost_graphs and len(examples) > max_cost_graphs:
+        sub = [examples[int(i)] for i in np.linspace(0, len(examples) - 1, max_cost_graphs)]
+    rows = []
+    for j, e in enumerate(sub):
+        rows.append(start_costs(net, e, gammas, eps_grid, stream=stream))
+        if log and (j + 1) % 8 == 0:
+            log(f"start costs measured on {j + 1} of {len(sub)} graphs")
+    costs = np.stack(rows)
     best_per = costs.min(axis=2)                           # [graphs, gammas]
     total = np.where(np.isfinite(best_per), best_per, 1e30).sum(axis=0)
     gi = int(np.argmin(total))
-    for e, c in zip(examples, costs[:, gi, :]):
+    for e, c in zip(sub, costs[:, gi, :]):
         e.t = float(np.log(eps_grid[int(np.argmin(c))] if np.isfinite(c).any() else e.mc.opt.eps0))
-    h2 = train(net, examples, epochs_eps, lr=lr, lam=1.0, seed=seed + 1)
+    h2 = train(net, sub, epochs_eps, lr=lr, lam=1.0, seed=seed + 1, log=log)
     if log:
         log(f"x stage loss {h1[0]:.4f} -> {h1[-1]:.4f}; gamma {gammas[gi]}; "
             f"eps stage loss {h2[0]:.4f} -> {h2[-1]:.4f}")
@@ -134,28 +182,3 @@ def snap_eps(log_eps, eps0, factor, lo):
     eps = min(max(eps, lo), eps0)
     k = int(round(np.log(eps / eps0) / np.log(factor)))
     return eps0 * factor ** max(k, 0)
-
-
-def time_to_cut(mc, ref_cut, tol, max_rounds, net=None, gamma=0.0, intensity=None, eps_first=None,
-                stream=None):
-    """Round 0, then (with a network) the warm start, then rounds until the
-    sweep cut is within tol of ref_cut.  The per-round sweeps only decide when
-    to stop and are not timed; one final sweep is.  eps_first: the first
-    round's eps (default: the options' eps0, or the network's prediction)."""
-    o = mc.opt
-    t0 = time.perf_counter()
-    _, st = mc.solve_range(0, 0)
-    le = None
-    if net is not None:
-        le = net.warm_start(mc, gamma, intensity)
-    _sync(stream)
-    sec = time.perf_counter() - t0
-    if eps_first is None:
-        eps_first = o.eps0 if le is None else snap_eps(le, o.eps0, o.eps_factor, min(EPS_GRID))
-    r, it, s2, val = run_rounds(mc, ref_cut, tol, eps_first, o.eps_factor, max_rounds, stream)
-    t0 = time.perf_counter()
-    mc.cut()
-    _sync(stream)
-    sec += s2 + time.perf_counter() - t0
-    return dict(rounds=r, cg_iters=it + st[0]["cg_iters"], seconds=sec, cut=val, eps_first=eps_first,
-                log_eps=le, reached=val <= ref_cut * (1.0 + tol))
