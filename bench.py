@@ -55,6 +55,12 @@ WORKLOADS = {
     "seg256-ilu": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=4),
                    "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
                    "(4x4x4 tiles, each block by ILU(0))"),
+    "seg128-ilu8": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=8),
+                    "3-D 128^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
+                    "(8x8x8 tiles, each block by ILU(0))"),
+    "seg256-ilu8": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=8),
+                    "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
+                    "(8x8x8 tiles, each block by ILU(0))"),
     "seg256-bj": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=1),
                   "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi "
                   "preconditioner (x-lines of 128 rows, tridiagonal blocks solved exactly)"),
@@ -128,7 +134,7 @@ def golden_run(workload):
     stored (written on the CPU by tests/golden/make_golden_fullsize.py, which
     calls only the oracle); the precision form and the block-Jacobi forms of
     an instance are compared with it too."""
-    for suffix in ("-mixed", "-ilu", "-bj"):
+    for suffix in ("-mixed", "-ilu8", "-ilu", "-bj"):
         if workload.endswith(suffix):
             workload = workload[: -len(suffix)]
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_oracle.json")
@@ -528,10 +534,13 @@ def main():
     # the timed steps, which stay as they are)
     breakdown = {}
     if events and args.kernel_breakdown:
-        kinds = [(1, "update")]
+        # with ILU(0) of 4x4x4 tiles (the default tile) the application runs
+        # inside the update kernel
+        fused = opts.get("precond", 0) == 2 and opts.get("block_size", 0) in (0, 4) and info["format"] == 2
+        kinds = [(1, "update_with_ilu0_apply" if fused else "update")]
         if opts.get("precision", 0) == 1:
             kinds.append((2, "residual_replacement"))
-        if opts.get("precond", 0) >= 1:
+        if opts.get("precond", 0) >= 1 and not fused:
             kinds.append((3, "block_jacobi_apply"))
         for which, nm in kinds:
             mc.set_kernel_timing(which, args.kernel_events)
@@ -634,8 +643,10 @@ def main():
     # The precision form (FP32 conductances, SpMV and CG vectors; FP64
     # potentials, dots and residual replacement) on the same instance, beside
     # the configured FP64 run: its time-to-cut and its cut against the FP64 cut.
+    # Block-Jacobi runs in FP64 only, so its workloads have no precision form.
     precision = None
-    if args.precision_form and info["solver"] == 1 and opts.get("precision", 0) == 0:
+    if (args.precision_form and info["solver"] == 1 and opts.get("precision", 0) == 0
+            and opts.get("precond", 0) == 0):
         with P.MinCut.from_graph(g, stream=stream, precision=1, refine_every=20, **opts) as mp:
             mp.solve()
             torch.cuda.synchronize()

@@ -98,7 +98,7 @@ typedef struct {
                                     order) */
   int32_t block_size;         /* precond 1: rows per block, even, 2..128 and at most
                                  off[1]; 0 = min(off[1], 128) rounded down to even.
-                                 precond 2: tiles: the tile edge, 2 or 4 (0 = 4); CSR:
+                                 precond 2: tiles: the tile edge, 2, 4 or 8 (0 = 4); CSR:
                                  rows per block, even, 2..128 (0 = 32) */
   int32_t unscaled_cg;        /* 0 (default): where the marching SpMV runs (3-D grids) with
                                  point Jacobi, CG runs on the symmetrically scaled system
@@ -345,7 +345,9 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
  * and the totals are reset:
  *   which  -1 off, 0 the SpMV (with its fused direction update), 1 the vector
  *          update, 2 the FP64 residual replacement of the precision form, 3 the
- *          block-Jacobi application z = M^-1 r (precond 1 or 2)
+ *          block-Jacobi application z = M^-1 r (precond 1 or 2; with ILU(0) of
+ *          4x4x4 tiles the application runs inside the vector update, so
+ *          which = 1 times both and which = 3 is refused)
  *   every  >= 1: the sampling stride (each event pair adds a marker before and
  *          after its launch, a few microseconds; a stride keeps that small)
  * Needs a single-graph handle on the multi-workgroup solver (solver 1),

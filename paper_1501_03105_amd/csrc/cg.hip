@@ -1237,60 +1237,124 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply(CGArgs<double> a, int slot
 // segment (4 rows, one 32-byte vector per array) at (y, z) of tile q.  Each
 // lane loads its own segment once: r, the pivots, and its edges to x + 1,
 // y + 1 and z + 1; the edges from below and the neighbours' values come from
-// the lanes one and four below (or above) by shuffles.  The substitutions run
-// as wavefronts over the anti-diagonals y + z (seven steps each way); within a
-// segment the x recurrence runs in the lane.  The order of every sum is the
-// thread-per-tile kernel's.
-__device__ __forceinline__ vec_t<double, 4> shfl4(vec_t<double, 4> v, int src) {
+// the lanes one and four below (or above), which lie in the same row of 16
+// lanes, by DPP row shifts.  The substitutions run as wavefronts over the
+// anti-diagonals y + z (seven steps each way); within a segment the x
+// recurrence runs in the lane.  Every lane forms 1/d and the forward
+// multipliers A_ik / d_k once, before the steps, so the steps (where at most
+// four lanes in sixteen are active) hold only fused multiply-adds.  The sums
+// are the thread-per-tile kernel's, in its order, except that it divides by
+// d where this kernel multiplies by 1/d.
+//
+// DPP row shifts: with row_shr:S lane i reads lane i - S, with row_shl:S lane
+// i + S, both within lane i's row of 16; a lane whose source lies outside its
+// row reads 0.
+constexpr int kDppRowShl1 = 0x101, kDppRowShl4 = 0x104, kDppRowShr1 = 0x111, kDppRowShr4 = 0x114;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_int<CTRL>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_int<CTRL>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ vec_t<double, 4> dpp4(vec_t<double, 4> v) {
   vec_t<double, 4> o;
 #pragma unroll
-  for (int i = 0; i < 4; i++) o[i] = __shfl(v[i], src, 64);
+  for (int i = 0; i < 4; i++) o[i] = dpp_double<CTRL>(v[i]);
   return o;
 }
 
+// UPD: the CG vector update of the iteration is fused in (v += alpha p,
+// r -= alpha q on each lane's own segment, then the application to the new
+// r), so r is not read back, and the kernel writes the partial sums
+// [r^T z, ||r||^2] that k_update_bj and this application write separately.
+template <bool UPD>
 __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int slot) {
   __shared__ double lds[4 * (kBlock / 64)];
-  if (block_done(a.sc)) return;
+  __shared__ double bc[4];
+  int64_t it = 0;
+  double alpha = 0.0, pq = 0.0;
+  if constexpr (UPD) {
+    if (!cg_update_start(a, lds, bc, it, alpha, pq)) return;
+  } else {
+    if (block_done(a.sc)) return;
+  }
   typedef vec_t<double, 4> V;
   const IluTiles tl = ilu_tiles(a, 4);
   const int64_t nt = a.nt;
   const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  const double *__restrict__ pdir = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;   // the SpMV's direction
   const int lane = threadIdx.x & 63, q = lane >> 4, y = lane & 3, z = (lane >> 2) & 3;
-  const int lo_y = lane > 0 ? lane - 1 : 0, lo_z = lane >= 4 ? lane - 4 : 0;
-  const int up_y = lane < 63 ? lane + 1 : 63, up_z = lane < 60 ? lane + 4 : 63;
   const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const V zero = 0.0;
-  double x[1] = {0.0};
+  double x[2] = {0.0, 0.0};
   for (int64_t tb = wv * 4; tb < tl.tiles; tb += nwv * 4) {     // the same trip count on every lane
     const int64_t k = tb + q;
     bool ok = false;
     int64_t u = 0;
     if (k < tl.tiles) u = ilu_seg(tl, 4, k, y, z, ok);
-    const V r = ok ? vload<double, 4>(a.rbuf + u) : zero;
+    V r;
+    if constexpr (UPD) {
+      if (ok) {
+        const V r0 = vload<double, 4>(a.rbuf + u), qv = vload<double, 4>(a.q + u);
+        const V pv = vload<double, 4>(pdir + u);
+        V vv = vload<double, 4>(a.v + u);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          vv[i] += alpha * pv[i];
+          r[i] = r0[i] - alpha * qv[i];
+          x[1] += r[i] * r[i];
+        }
+        vstore<double, 4>(a.v + u, vv);
+        vstore<double, 4>(a.rbuf + u, r);
+      } else {
+        r = zero;
+      }
+    } else {
+      r = ok ? vload<double, 4>(a.rbuf + u) : zero;
+    }
     const V d = ok ? vload<double, 4>(a.bj_im + u) : V(1.0);
     const V wx = ok ? vload<double, 4>(w0 + u) : zero;          // wx[i] couples rows i and i + 1
     const V wy = ok ? vload<double, 4>(w1 + u) : zero;          // edges to y + 1
     const V wz = ok ? vload<double, 4>(w2 + u) : zero;          // edges to z + 1
-    const V wy_lo = shfl4(wy, lo_y), wz_lo = shfl4(wz, lo_z);   // edges from y - 1, z - 1
-    const V d_ylo = shfl4(d, lo_y), d_zlo = shfl4(d, lo_z);
-    // every lane takes part in the shuffles (a shuffle inside a condition
+    V di;
+#pragma unroll
+    for (int i = 0; i < 4; i++) di[i] = 1.0 / d[i];
+    // every lane takes part in the row shifts (a shift inside a condition
     // would read lanes that skipped it)
-    const int ok_up_y = __shfl((int)ok, up_y, 64), ok_up_z = __shfl((int)ok, up_z, 64);
+    const V wy_lo = dpp4<kDppRowShr1>(wy), wz_lo = dpp4<kDppRowShr4>(wz);   // edges from y - 1, z - 1
+    const V di_ylo = dpp4<kDppRowShr1>(di), di_zlo = dpp4<kDppRowShr4>(di);
+    V ly, lz, lx;                                                // -L_ik = w_ik / d_k
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      ly[i] = wy_lo[i] * di_ylo[i];
+      lz[i] = wz_lo[i] * di_zlo[i];
+      lx[i] = i > 0 ? wx[i - 1] * di[i - 1] : 0.0;
+    }
+    const int ok_up_y = dpp_int<kDppRowShl1>((int)ok), ok_up_z = dpp_int<kDppRowShl4>((int)ok);
     const bool ok_yup = y < 3 && ok_up_y != 0;
     const bool ok_zup = z < 3 && ok_up_z != 0;
     // forward: y_i = r_i - sum_k (A_ik / d_k) y_k over z - 1, y - 1, x - 1
     V yv = zero;
     for (int st = 0; st <= 6; st++) {
-      const V yy = shfl4(yv, lo_y), yz = shfl4(yv, lo_z);
+      const V yy = dpp4<kDppRowShr1>(yv), yz = dpp4<kDppRowShr4>(yv);
       if (ok && y + z == st) {
         V t;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           double v = r[i];
-          if (z > 0) v -= (-wz_lo[i] / d_zlo[i]) * yz[i];
-          if (y > 0) v -= (-wy_lo[i] / d_ylo[i]) * yy[i];
-          if (i > 0) v -= (-wx[i - 1] / d[i - 1]) * t[i - 1];
+          if (z > 0) v += lz[i] * yz[i];
+          if (y > 0) v += ly[i] * yy[i];
+          if (i > 0) v += lx[i] * t[i - 1];
           t[i] = v;
         }
         yv = t;
@@ -1298,26 +1362,219 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int sl
     }
     if (ok) {
 #pragma unroll
-      for (int i = 0; i < 4; i++) x[0] += yv[i] * yv[i] / d[i];          // r^T z = y^T D^-1 y
+      for (int i = 0; i < 4; i++) x[0] += yv[i] * yv[i] * di[i];         // r^T z = y^T D^-1 y
     }
     // backward: z_i = (y_i - sum_j A_ij z_j) / d_i over x + 1, y + 1, z + 1
     V zv = zero;
     for (int st = 6; st >= 0; st--) {
-      const V zy = shfl4(zv, up_y), zz = shfl4(zv, up_z);
+      const V zy = dpp4<kDppRowShl1>(zv), zz = dpp4<kDppRowShl4>(zv);
       if (ok && y + z == st) {
         V t;
 #pragma unroll
         for (int i = 3; i >= 0; i--) {
           double v = yv[i];
-          if (i < 3) v -= (-wx[i]) * t[i + 1];
-          if (ok_yup) v -= (-wy[i]) * zy[i];
-          if (ok_zup) v -= (-wz[i]) * zz[i];
-          t[i] = v / d[i];
+          if (i < 3) v += wx[i] * t[i + 1];
+          if (ok_yup) v += wy[i] * zy[i];
+          if (ok_zup) v += wz[i] * zz[i];
+          t[i] = v * di[i];
         }
         zv = t;
       }
     }
     if (ok) vstore<double, 4>(a.z + u, zv);
+  }
+  if constexpr (UPD) {
+    write_partials<2>(x, a.partials, kPUpd, lds);
+    if (first_thread()) {
+      a.sc->iter_b = it + 1;
+      a.sc->alpha = alpha;
+      a.sc->pq = pq;
+    }
+  } else {
+    double x1[1] = {x[0]};
+    write_partials<1>(x1, a.partials, slot, lds);
+  }
+}
+
+// ILU(0) of 8x8x8 tiles, a wavefront per tile: lane y + 8 z owns the x
+// segment (8 rows) at (y, z).  Its y neighbours are the lanes one below and
+// one above, in the same row of 16 lanes (DPP row shifts); its z neighbours
+// are eight lanes away, in the next row of 16 for half of the lanes, and come
+// by __shfl.  The wavefront steps run over the anti-diagonals y + z (fifteen
+// each way).  The factorisation has the same wavefront form as the forward
+// substitution: a pivot needs the pivots of its lower neighbours.  The sums
+// are those of the thread-per-tile kernels, in their order (the application
+// multiplies by 1/d where they divide by d).
+__device__ __forceinline__ void load8(const double *p, double (&v)[8]) {
+  const vec_t<double, 4> lo = vload<double, 4>(p), hi = vload<double, 4>(p + 4);
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    v[i] = lo[i];
+    v[i + 4] = hi[i];
+  }
+}
+
+__device__ __forceinline__ void store8(double *p, const double (&v)[8]) {
+  vec_t<double, 4> lo, hi;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    lo[i] = v[i];
+    hi[i] = v[i + 4];
+  }
+  vstore<double, 4>(p, lo);
+  vstore<double, 4>(p + 4, hi);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void dpp8(const double (&v)[8], double (&o)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) o[i] = dpp_double<CTRL>(v[i]);
+}
+
+__device__ __forceinline__ void shfl8(const double (&v)[8], int src, double (&o)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; i++) o[i] = __shfl(v[i], src, 64);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_factor8w(CGArgs<double> a) {
+  const IluTiles tl = ilu_tiles(a, 8);
+  const int64_t nt = a.nt;
+  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  const int lane = threadIdx.x & 63, y = lane & 7, z = lane >> 3;
+  const int lo_z = lane >= 8 ? lane - 8 : lane;
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t k = wv; k < tl.tiles; k += nwv) {                // uniform across the wavefront
+    bool ok;
+    const int64_t u = ilu_seg(tl, 8, k, y, z, ok);
+    double D[8], wx[8], wy[8], wz[8];
+    if (ok) {
+      load8(a.D + u, D);
+      load8(w0 + u, wx);                                        // wx[i] couples rows i and i + 1
+      load8(w1 + u, wy);                                        // edges to y + 1
+      load8(w2 + u, wz);                                        // edges to z + 1
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        D[i] = 1.0;
+        wx[i] = wy[i] = wz[i] = 0.0;
+      }
+    }
+    double wy_lo[8], wz_lo[8];                                  // edges from y - 1, z - 1
+    dpp8<kDppRowShr1>(wy, wy_lo);
+    shfl8(wz, lo_z, wz_lo);
+    double piv[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) piv[i] = 1.0;
+    for (int st = 0; st <= 14; st++) {
+      double dy[8], dz[8];
+      dpp8<kDppRowShr1>(piv, dy);
+      shfl8(piv, lo_z, dz);
+      if (ok && y + z == st) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          double p = D[i];
+          if (z > 0) p -= (-wz_lo[i] / dz[i]) * (-wz_lo[i]);
+          if (y > 0) p -= (-wy_lo[i] / dy[i]) * (-wy_lo[i]);
+          if (i > 0) p -= (-wx[i - 1] / piv[i - 1]) * (-wx[i - 1]);
+          piv[i] = p;
+        }
+      }
+    }
+    if (ok) store8(a.bj_im + u, piv);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_apply8w(CGArgs<double> a, int slot) {
+  __shared__ double lds[4 * (kBlock / 64)];
+  if (block_done(a.sc)) return;
+  const IluTiles tl = ilu_tiles(a, 8);
+  const int64_t nt = a.nt;
+  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  const int lane = threadIdx.x & 63, y = lane & 7, z = lane >> 3;
+  const int lo_z = lane >= 8 ? lane - 8 : lane, up_z = lane < 56 ? lane + 8 : lane;
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  double x[1] = {0.0};
+  for (int64_t k = wv; k < tl.tiles; k += nwv) {                // uniform across the wavefront
+    bool ok;
+    const int64_t u = ilu_seg(tl, 8, k, y, z, ok);
+    double r[8], di[8], wx[8], wy[8], wz[8];
+    if (ok) {
+      load8(a.rbuf + u, r);
+      load8(a.bj_im + u, di);
+      load8(w0 + u, wx);
+      load8(w1 + u, wy);
+      load8(w2 + u, wz);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        r[i] = wx[i] = wy[i] = wz[i] = 0.0;
+        di[i] = 1.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) di[i] = 1.0 / di[i];
+    // every lane takes part in the shifts and shuffles (one inside a
+    // condition would read lanes that skipped it)
+    double wy_lo[8], wz_lo[8], di_ylo[8], di_zlo[8];
+    dpp8<kDppRowShr1>(wy, wy_lo);
+    shfl8(wz, lo_z, wz_lo);
+    dpp8<kDppRowShr1>(di, di_ylo);
+    shfl8(di, lo_z, di_zlo);
+    double ly[8], lz[8], lx[8];                                 // -L_ik = w_ik / d_k
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      ly[i] = wy_lo[i] * di_ylo[i];
+      lz[i] = wz_lo[i] * di_zlo[i];
+      lx[i] = i > 0 ? wx[i - 1] * di[i - 1] : 0.0;
+    }
+    const int ok_up_y = dpp_int<kDppRowShl1>((int)ok), ok_up_z = __shfl((int)ok, up_z, 64);
+    const bool ok_yup = y < 7 && ok_up_y != 0;
+    const bool ok_zup = z < 7 && ok_up_z != 0;
+    // forward: y_i = r_i - sum_k (A_ik / d_k) y_k over z - 1, y - 1, x - 1
+    double yv[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) yv[i] = 0.0;
+    for (int st = 0; st <= 14; st++) {
+      double yy[8], yz[8];
+      dpp8<kDppRowShr1>(yv, yy);
+      shfl8(yv, lo_z, yz);
+      if (ok && y + z == st) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+          double v = r[i];
+          if (z > 0) v += lz[i] * yz[i];
+          if (y > 0) v += ly[i] * yy[i];
+          if (i > 0) v += lx[i] * yv[i - 1];
+          yv[i] = v;
+        }
+      }
+    }
+    if (ok) {
+#pragma unroll
+      for (int i = 0; i < 8; i++) x[0] += yv[i] * yv[i] * di[i];       // r^T z = y^T D^-1 y
+    }
+    // backward: z_i = (y_i - sum_j A_ij z_j) / d_i over x + 1, y + 1, z + 1
+    double zv[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) zv[i] = 0.0;
+    for (int st = 14; st >= 0; st--) {
+      double zy[8], zz[8];
+      dpp8<kDppRowShl1>(zv, zy);
+      shfl8(zv, up_z, zz);
+      if (ok && y + z == st) {
+#pragma unroll
+        for (int i = 7; i >= 0; i--) {
+          double v = yv[i];
+          if (i < 7) v += wx[i] * zv[i + 1];
+          if (ok_yup) v += wy[i] * zy[i];
+          if (ok_zup) v += wz[i] * zz[i];
+          zv[i] = v * di[i];
+        }
+      }
+    }
+    if (ok) store8(a.z + u, zv);
   }
   write_partials<1>(x, a.partials, slot, lds);
 }
@@ -1953,6 +2210,7 @@ hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st) {
     }
     if (a.bj_kind == 2) {
       if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_factor<2>), dim3(grid), dim3(kBlock), 0, st, a);
+      else if (a.bj_tile == 8) hipLaunchKernelGGL(k_ilu_factor8w, dim3(grid), dim3(kBlock), 0, st, a);
       else hipLaunchKernelGGL((k_ilu_factor<4>), dim3(grid), dim3(kBlock), 0, st, a);
       return hipGetLastError();
     }
@@ -1970,7 +2228,8 @@ hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t s
     }
     if (a.bj_kind == 2) {
       if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_apply<2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
-      else hipLaunchKernelGGL(k_ilu_apply4w, dim3(grid), dim3(kBlock), 0, st, a, slot);
+      else if (a.bj_tile == 8) hipLaunchKernelGGL(k_ilu_apply8w, dim3(grid), dim3(kBlock), 0, st, a, slot);
+      else hipLaunchKernelGGL((k_ilu_apply4w<false>), dim3(grid), dim3(kBlock), 0, st, a, slot);
       return hipGetLastError();
     }
   }
@@ -1980,6 +2239,12 @@ hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t s
 
 template <typename T>
 hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (bj_update_fused(a)) {                    // the update and the ILU(0) application in one kernel
+      hipLaunchKernelGGL((k_ilu_apply4w<true>), dim3(grid), dim3(kBlock), 0, st, a, (int)kPUpd);
+      return hipGetLastError();
+    }
+  }
   if (a.bj_block > 0)
     hipLaunchKernelGGL((k_update_bj<T>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.scaled && (a.it_hint & 1))

@@ -319,7 +319,7 @@ hipError_t launch_iterations(irls_mincut_t h, const CGArgs<T> &a0, int64_t first
     if (e == hipSuccess)
       e = timed_launch(h, 0, a.it_hint, [&] { return launch_spmv(a, h->grid, h->rpw, a.K > 0, h->stream); });
     if (e == hipSuccess) e = timed_launch(h, 1, a.it_hint, [&] { return launch_update(a, h->grid, h->stream); });
-    if (e == hipSuccess && a.bj_block > 0)
+    if (e == hipSuccess && a.bj_block > 0 && !bj_update_fused(a))
       e = timed_launch(h, 3, a.it_hint, [&] { return launch_bj_apply(a, h->grid, kPUpd, h->stream); });
     if (e == hipSuccess && h->opt.precision == 1)
       e = timed_launch(h, 2, a.it_hint, [&] { return launch_replace_residual(a, h->grid, h->stream); });
@@ -847,11 +847,11 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
       // cubic tiles of a 3-D grid: offsets 1, N, P with N and P / N multiples
       // of the tile edge, and whole planes
       const int32_t B = o.block_size ? o.block_size : 4;
-      const bool grid3 = (B == 2 || B == 4) && hg.K == 3 && hg.off[0] == 1 && hg.off[1] > 0 &&
+      const bool grid3 = (B == 2 || B == 4 || B == 8) && hg.K == 3 && hg.off[0] == 1 && hg.off[1] > 0 &&
                          hg.off[2] % hg.off[1] == 0 && hg.off[1] % B == 0 && (hg.off[2] / hg.off[1]) % B == 0 &&
                          hg.nt % hg.off[2] == 0;
       if (!grid3) {
-        g_thread_error = "ILU(0) tiles need a tile edge of 2 or 4 and a 3-D grid in the diagonal format "
+        g_thread_error = "ILU(0) tiles need a tile edge of 2, 4 or 8 and a 3-D grid in the diagonal format "
                          "whose lines and planes are multiples of it, with whole planes (format 1 gives "
                          "CSR blocks instead)";
         delete h;
@@ -1469,6 +1469,10 @@ irls_status irls_mincut_set_kernel_timing(irls_mincut_t h, int32_t which, int32_
   if (h->batch || h->solver != 1) { h->err = "kernel timing needs the multi-workgroup solver"; return IRLS_ERR_OPTIONS; }
   if (which == 2 && h->opt.precision != 1) { h->err = "which = 2 needs the precision form"; return IRLS_ERR_OPTIONS; }
   if (which == 3 && h->bj_block == 0) { h->err = "which = 3 needs a block-Jacobi preconditioner"; return IRLS_ERR_OPTIONS; }
+  if (which == 3 && h->bj_kind == 2 && h->bj_tile == 4) {
+    h->err = "with ILU(0) of 4x4x4 tiles the application runs inside the vector update: time which = 1";
+    return IRLS_ERR_OPTIONS;
+  }
   h->prof_which = which;
   h->prof_every = every;
   h->prof_rounds.clear();

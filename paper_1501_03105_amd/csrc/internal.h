@@ -155,6 +155,10 @@ template <typename T> hipError_t launch_spmv(const CGArgs<T> &a, int grid, int r
                                              bool fused_dia, hipStream_t st);
 template <typename T> hipError_t launch_direction(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st);
+// With ILU(0) of 4x4x4 tiles the CG update and the application z = M^-1 r of
+// an iteration are one kernel, launched by launch_update; the iteration then
+// makes no launch_bj_apply call.
+template <typename T> inline bool bj_update_fused(const CGArgs<T> &a) { return a.bj_kind == 2 && a.bj_tile == 4; }
 // block-Jacobi: factors once per round, and z = M^-1 r with r^T z into partial slot `slot`
 template <typename T> hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st);
 template <typename T> hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t st);

@@ -2,8 +2,8 @@
 the GPU against the oracle's block-Jacobi PCG, with the paper's two block
 solvers: exact solves of blocks of consecutive rows inside one line of
 offset-1 edges (tridiagonal), applied by wavefront scans; and ILU(0) of
-cubic tiles of 3-D grids (precond 2), against the oracle's ILU(0) of the same
-tiles given as block ids."""
+cubic tiles of 3-D grids (precond 2, tile edges 2, 4 and 8), against the oracle's
+ILU(0) of the same tiles given as block ids."""
 import numpy as np
 import pytest
 
@@ -75,7 +75,9 @@ def tile_ids(nx, ny, nn, B):
 
 ILU_CASES = [("box 16x12x10, tiles of 4 (a short top tile)", 16, 12, 10, 4),
              ("box 16x12x9, tiles of 2 (a short top tile)", 16, 12, 9, 2),
-             ("box 32x32x24, tiles of 4 (the marching SpMV)", 32, 32, 24, 4)]
+             ("box 32x32x24, tiles of 4 (the marching SpMV)", 32, 32, 24, 4),
+             ("box 32x24x20, tiles of 8 (a short top tile)", 32, 24, 20, 8),
+             ("box 48x32x24, tiles of 8 (six tiles a plane)", 48, 32, 24, 8)]
 
 
 @pytest.mark.parametrize("case", range(len(ILU_CASES)))
@@ -109,7 +111,10 @@ def test_ilu0_tile_option_errors(P):
     assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2) == P.OK
     # format 1 on the same grid is allowed: CSR blocks instead of tiles
     assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2, format=1, solver=1) == P.OK
-    for g, kw in ((ok, dict(block_size=8)), (ok, dict(block_size=6)), (ok, dict(precision=1)),
+    g16 = gen.grid3d_box(16, 16, 16 * 16 * 3, seed=1)
+    assert P.create_error(g16.n, g16.eu, g16.ev, g16.cap, g16.s, g16.t, precond=2, block_size=8) == P.OK
+    for g, kw in ((ok, dict(block_size=8)),                                  # lines of 12: not a multiple of 8
+                  (ok, dict(block_size=6)), (g16, dict(block_size=16)), (ok, dict(precision=1)),
                   (ok, dict(solver=2)),
                   (gen.grid3d_box(18, 12, 18 * 12 * 4, seed=1), {}),        # lines not a multiple of 4
                   (gen.grid3d_box(16, 12, 16 * 12 * 4 + 5, seed=1), {}),    # a partial plane
@@ -190,3 +195,22 @@ def test_ilu0_csr_option_errors(P):
     assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=2, solver=1) == P.OK
     for kw in (dict(block_size=3), dict(block_size=130), dict(precision=1), dict(solver=2)):
         assert P.create_error(g.n, g.eu, g.ev, g.cap, g.s, g.t, precond=2, **kw) == P.ERR_OPTIONS, kw
+
+
+def test_ilu0_fused_update_timing(P):
+    """With 4x4x4 tiles the vector update and the ILU(0) application are one
+    kernel: in-solve timing of the update (which = 1) sees one launch per CG
+    iteration, and the separate application (which = 3) is refused; with
+    2x2x2 tiles it is a kernel of its own and can be timed."""
+    g = gen.grid3d_box(16, 16, 16 * 16 * 8, seed=2)
+    with P.MinCut.from_graph(g, precond=2, rounds=4, cg_rtol=1e-8) as mc:
+        with pytest.raises(P.IrlsError):
+            mc.set_kernel_timing(3)
+        mc.set_kernel_timing(1, 1)
+        rc, st = mc.solve()
+        t = mc.kernel_timing()
+        assert rc == P.OK and t["n_working"] == sum(r["cg_iters"] for r in st)
+    with P.MinCut.from_graph(g, precond=2, block_size=2, rounds=4, cg_rtol=1e-8) as mc:
+        mc.set_kernel_timing(3, 1)
+        rc, st = mc.solve()
+        assert rc == P.OK and mc.kernel_timing()["n_working"] == sum(r["cg_iters"] for r in st)
