@@ -112,9 +112,10 @@ def code_sha(path):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
-def profiled_traffic(kernel, workload):
+def profiled_traffic(kernel, workload, source="cg.hip"):
     """HBM bytes per launch from the committed rocprofv3 summary, if the kernel
-    code is still the one that was profiled (else None)."""
+    code (the source file that holds it) is still the one that was profiled
+    (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -123,7 +124,7 @@ def profiled_traffic(kernel, workload):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    sha = code_sha(os.path.join(ROOT, "paper_1501_03105_amd", "csrc", "cg.hip"))
+    sha = code_sha(os.path.join(ROOT, "paper_1501_03105_amd", "csrc", source))
     if fields.get("code_sha256_prefix") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
@@ -280,7 +281,7 @@ def bench_batch(args, spec, opts, desc):
     batch_bytes = sum(it * (12 * z + 104 * r) for it, z, r in zip(iters, nnz, rows))
     achieved = batch_bytes / (dt / args.steps) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_resident",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profiled_traffic("k_resident", "rmat512", "resident.hip"), "kernel": "k_resident",
             "bytes_per_launch": int(batch_bytes), "avg_launch_ms": round(1000 * dt / args.steps, 3),
             "note": "one launch solves every round of every graph; the largest graphs, one workgroup each, "
                     "set its length, so it is bound by their memory latency, not by bandwidth"}
