@@ -172,7 +172,7 @@ def test_adam_step_matches_formula(P):
     net.close()
 
 
-def test_trained_network_saves_cg_work(P):
+def test_trained_network_start_reaches_plain_cut(P):
     """Train on 32^3 segmentation grids (converged potentials made by the
     method itself), choose gamma and the eps targets on them, and the
     no-network baseline (the best constant first eps on the same graphs).
