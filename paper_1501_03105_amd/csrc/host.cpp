@@ -1825,9 +1825,13 @@ irls_status irls_mincut_create_batch(irls_mincut_t *out, int32_t G, const int64_
     gd.nt = rows;
     gd.nnz = nnz;
     gd.format = 1;
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
-    h->grid_res = std::max(1, std::min(G, 2 * cus));
+    // as many workgroups as can be resident at once (the kernel's registers
+    // allow one 1024-thread workgroup per CU), each taking graphs from the
+    // queue until it is empty
+    int cus = 256, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    h->grid_res = std::max(1, std::min(G, resident_blocks_per_cu() * cus));
     h->grid = grid_for(rows);
     if ((rc = upload(h, &gd.rowptr, rowptr)) != IRLS_OK || (rc = upload(h, &gd.col, col)) != IRLS_OK ||
         (rc = upload(h, &gd.ccap, ccap)) != IRLS_OK || (rc = upload(h, &gd.cs, cs)) != IRLS_OK ||

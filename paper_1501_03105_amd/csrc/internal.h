@@ -267,6 +267,8 @@ struct ResidentArgs {
                                   // l1 - lower_bound <= stop_gap * l1
 };
 hipError_t launch_resident(const ResidentArgs &a, int grid, int block, hipStream_t st);
+// workgroups of k_resident (1024 threads) that fit on one CU at once (at least 1)
+int resident_blocks_per_cu();
 hipError_t launch_resident_reset(unsigned *next_graph, irls_round_stats *st, int64_t nrec, hipStream_t s);
 
 // sweep

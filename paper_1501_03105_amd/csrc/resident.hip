@@ -469,6 +469,12 @@ hipError_t launch_resident_reset(unsigned *next_graph, irls_round_stats *st, int
   return hipGetLastError();
 }
 
+int resident_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_resident, kResBlock, 0) != hipSuccess || n < 1) return 1;
+  return n;
+}
+
 hipError_t launch_resident(const ResidentArgs &a, int grid, int block, hipStream_t st) {
   hipLaunchKernelGGL(k_resident, dim3(grid), dim3(block), 0, st, a);
   return hipGetLastError();
