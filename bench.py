@@ -602,7 +602,8 @@ def main():
     if roof and args.stream_probe and info["n_nonterminal"] % 2 == 0:
         # the bandwidth a kernel with the SpMV's mix of streams (five arrays
         # read, two written, one row each per step) and nothing else sustains
-        # at this size, and a plain copy; the better of two grid sizes each
+        # at this size, and a plain copy; the best of two grid sizes and of
+        # plain and streaming (non-temporal) accesses
         probe = {}
         for nr, nw in ((5, 2), (1, 1)):
             best = 0.0

@@ -315,12 +315,13 @@ irls_status irls_mincut_march_tile(irls_mincut_t h, int32_t *threads, int32_t *l
 /* Streaming ceiling of the GPU for a mix of memory streams: the bandwidth a
  * kernel that only reads `reads` arrays and writes `writes` arrays of `rows`
  * doubles each (two rows per thread, 16-byte accesses, rows in XCD slabs, no
- * other work) sustains.  The CG kernels (Section 3.1's PCG: the SpMV streams
+ * other work) sustains, with plain accesses and with the streaming
+ * (non-temporal) hint on every access; the faster of the two counts.  The CG kernels (Section 3.1's PCG: the SpMV streams
  * five arrays in and two out per row) are read against it.  Allocates
  * (reads + writes) * rows doubles on the current device for the call, runs
- * one warm-up and `reps` timed launches on hip_stream (NULL: the default
- * stream) with `workgroups` workgroups, and writes the mean launch time
- * (ms).  Bytes moved per launch: (reads + writes) * rows * 8.
+ * one warm-up and `reps` timed launches of each form on hip_stream (NULL:
+ * the default stream) with `workgroups` workgroups, and writes the smaller
+ * of the two mean launch times (ms).  Bytes moved per launch: (reads + writes) * rows * 8.
  * Errors: IRLS_ERR_OPTIONS unless rows is even and >= 2, reads in 1..6,
  * writes in 1..2, workgroups a multiple of 8 in 8..1024, reps in 1..1000;
  * IRLS_ERR_OOM / IRLS_ERR_DEVICE from HIP (text via

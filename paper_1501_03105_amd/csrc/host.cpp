@@ -1508,13 +1508,19 @@ irls_status irls_stream_probe(int64_t rows, int32_t reads, int32_t writes, int32
   if (e == hipSuccess) e = launch_fill(in, (int64_t)reads * rows, 1.0, st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = launch_stream_probe(in, out, rows, reads, writes, workgroups, st);   // warm-up
-  if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int i = 0; i < reps && e == hipSuccess; i++) e = launch_stream_probe(in, out, rows, reads, writes, workgroups, st);
-  if (e == hipSuccess) e = hipEventRecord(e1, st);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
-  float ms = 0.0f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  // both forms of access, plain and streaming; the faster one counts
+  double best = 0.0;
+  for (int nt = 0; nt < 2 && e == hipSuccess; nt++) {
+    e = launch_stream_probe(in, out, rows, reads, writes, workgroups, nt != 0, st);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && e == hipSuccess; i++)
+      e = launch_stream_probe(in, out, rows, reads, writes, workgroups, nt != 0, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && (nt == 0 || (double)ms / reps < best)) best = (double)ms / reps;
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (in) (void)hipFree(in);
@@ -1523,7 +1529,7 @@ irls_status irls_stream_probe(int64_t rows, int32_t reads, int32_t writes, int32
     g_thread_error = std::string("stream probe: ") + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? IRLS_ERR_OOM : IRLS_ERR_DEVICE;
   }
-  *avg_ms = (double)ms / reps;
+  *avg_ms = best;
   return IRLS_OK;
 }
 

@@ -167,7 +167,7 @@ template <typename T> hipError_t launch_replace_residual(const CGArgs<T> &a, int
 template <typename T> hipError_t launch_stats(const CGArgs<T> &a, int grid, hipStream_t st);
 hipError_t launch_fill(double *x, int64_t n, double value, hipStream_t st);
 // streaming probe: nr (1..6) input and nw (1..2) output streams of n doubles (n even)
-hipError_t launch_stream_probe(const double *in, double *out, int64_t n, int nr, int nw, int grid,
+hipError_t launch_stream_probe(const double *in, double *out, int64_t n, int nr, int nw, int grid, bool nt,
                                hipStream_t st);
 
 // two-level rounding (twolevel.hip)
