@@ -430,7 +430,10 @@ __device__ __forceinline__ void vstore(T *p, vec_t<T, R> v) { *reinterpret_cast<
 // Streaming forms (non-temporal hint) for data a kernel touches once: at sizes
 // past the caches they keep such lines from pushing out the ones that are
 // reused (the marching SpMV's neighbour rows).  Measured at 256^3: SpMV
-// 207 -> 192 us, update 145 -> 123 us.
+// 207 -> 192 us, update 145 -> 123 us.  Where a CG iteration's data fit the
+// 256 MB last-level cache they are slower (128^3: SpMV 26 -> 30 us), so the
+// kernels take the choice as a template argument (vload_s / vstore_s) and the
+// host sets it by size.
 template <typename T, int R>
 __device__ __forceinline__ vec_t<T, R> vload_nt(const T *p) {
   return __builtin_nontemporal_load(reinterpret_cast<const vec_t<T, R> *>(p));
@@ -438,6 +441,16 @@ __device__ __forceinline__ vec_t<T, R> vload_nt(const T *p) {
 template <typename T, int R>
 __device__ __forceinline__ void vstore_nt(T *p, vec_t<T, R> v) {
   __builtin_nontemporal_store(v, reinterpret_cast<vec_t<T, R> *>(p));
+}
+template <bool NT, typename T, int R>
+__device__ __forceinline__ vec_t<T, R> vload_s(const T *p) {
+  if constexpr (NT) return vload_nt<T, R>(p);
+  else return vload<T, R>(p);
+}
+template <bool NT, typename T, int R>
+__device__ __forceinline__ void vstore_s(T *p, vec_t<T, R> v) {
+  if constexpr (NT) vstore_nt<T, R>(p, v);
+  else vstore<T, R>(p, v);
 }
 
 // Loads of one R-row group of the vectorised diagonal SpMV, taken before beta
@@ -581,14 +594,14 @@ __device__ __forceinline__ void march_load_p(const CGArgs<T> &a, const T *pin, i
 }
 
 // SC: the scaled form (scaled conductances, unit diagonal: no D load).
-template <typename T, int K, int R, bool SC>
+template <typename T, int K, int R, bool SC, bool NT>
 __device__ __forceinline__ void march_load(const CGArgs<T> &a, const T *pin, int64_t u0, MarchStep<T, K, R> &s) {
   const int64_t nt = a.nt, P = a.off[K - 1];
   const T *__restrict__ w = SC ? a.wh : a.w;
   s.zp = vload<T, R>(a.z + (u0 + P < nt ? u0 + P : u0));
   if constexpr (!SC) s.D = vload<T, R>(a.D + u0);
   s.w0 = vload<T, R>(w + u0);
-  s.wP = vload_nt<T, R>(w + (K - 1) * nt + u0);              // read by this thread only
+  s.wP = vload_s<NT, T, R>(w + (K - 1) * nt + u0);           // read by this thread only
   s.zr = a.z[u0 + R < nt ? u0 + R : u0];
   s.wl = w[u0 > 0 ? u0 - 1 : nt - 1];
   s.zl = a.z[u0 > 0 ? u0 - 1 : u0];
@@ -652,7 +665,7 @@ __host__ __device__ inline MarchTiles march_tiles(int64_t P, int64_t N1, int32_t
 // plane k + 1 loaded, with the streaming hint: each is touched once here, and
 // they should not push the neighbour rows out of the caches.  The summation
 // order per row is that of k_spmv_dia_vec.
-template <typename T, int K, int R, bool SC, int BS>
+template <typename T, int K, int R, bool SC, int BS, bool NT>
 __global__ __launch_bounds__(BS) void k_spmv_dia_march(CGArgs<T> a) {
   __shared__ double lds[4 * (BS / 64)];
   __shared__ double bc[4];
@@ -687,8 +700,8 @@ __global__ __launch_bounds__(BS) void k_spmv_dia_march(CGArgs<T> a) {
       pm = vload<T, R>(pin + u - P);
       wm = vload<T, R>((SC ? a.wh : a.w) + (K - 1) * nt + u - P);
     }
-    march_load<T, K, R, SC>(a, pin, u, s0);
-    if (two) march_load<T, K, R, SC>(a, pin, u + P, s1);
+    march_load<T, K, R, SC, NT>(a, pin, u, s0);
+    if (two) march_load<T, K, R, SC, NT>(a, pin, u + P, s1);
   }
   int64_t it;
   double beta64;
@@ -730,8 +743,8 @@ __global__ __launch_bounds__(BS) void k_spmv_dia_march(CGArgs<T> a) {
     const V dp = dir(st.zp, st.pp);
     if (u0 + P < nt) acc -= st.wP * dp;
     if (k > 0) acc -= wm * dm;
-    vstore_nt<T, R>(pout + u0, pc);
-    vstore_nt<T, R>(a.q + u0, acc);
+    vstore_s<NT, T, R>(pout + u0, pc);
+    vstore_s<NT, T, R>(a.q + u0, acc);
 #pragma unroll
     for (int i = 0; i < R; i++) x[0] += (double)pc[i] * (double)acc[i];
     dm = pc;
@@ -748,10 +761,10 @@ __global__ __launch_bounds__(BS) void k_spmv_dia_march(CGArgs<T> a) {
     int64_t k = k0;
     auto pair = [&]() {
       step(s0, k);
-      march_load<T, K, R, SC>(a, pin, c + P * (k + 2), s0);
+      march_load<T, K, R, SC, NT>(a, pin, c + P * (k + 2), s0);
       __builtin_amdgcn_sched_barrier(0);                // keep the two steps apart
       step(s1, k + 1);
-      march_load<T, K, R, SC>(a, pin, c + P * (k + 3), s1);
+      march_load<T, K, R, SC, NT>(a, pin, c + P * (k + 3), s1);
       __builtin_amdgcn_sched_barrier(0);
       k += 2;
     };
@@ -760,7 +773,7 @@ __global__ __launch_bounds__(BS) void k_spmv_dia_march(CGArgs<T> a) {
       while (k + 3 < kend) pair();
     }
     step(s0, k);
-    if (k + 2 < kend) march_load<T, K, R, SC>(a, pin, c + P * (k + 2), s0);
+    if (k + 2 < kend) march_load<T, K, R, SC, NT>(a, pin, c + P * (k + 2), s0);
     if (k + 1 < kend) step(s1, k + 1);
     if (k + 2 < kend) step(s0, k + 2);
   }
@@ -942,7 +955,7 @@ struct ScaledGroup {
   vec_t<double, R> v;
 };
 
-template <typename T, int R, bool ODD>
+template <typename T, int R, bool ODD, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
@@ -955,9 +968,10 @@ __global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
   const T *__restrict__ p_prev = ODD ? a.p1 : a.p0;
   auto load = [&](int64_t g, ScaledGroup<T, R, ODD> &b) {
     const int64_t u0 = g * R;
-    b.z = vload_nt<T, R>(a.z + u0); b.q = vload_nt<T, R>(a.q + u0); b.D = vload_nt<T, R>(a.D + u0);
+    b.z = vload_s<NT, T, R>(a.z + u0); b.q = vload_s<NT, T, R>(a.q + u0); b.D = vload_s<NT, T, R>(a.D + u0);
     if constexpr (ODD) {
-      b.p = vload_nt<T, R>(p_it + u0); b.pp = vload_nt<T, R>(p_prev + u0); b.v = vload_nt<double, R>(a.v + u0);
+      b.p = vload_s<NT, T, R>(p_it + u0); b.pp = vload_s<NT, T, R>(p_prev + u0);
+      b.v = vload_s<NT, double, R>(a.v + u0);
     }
   };
   ScaledGroup<T, R, ODD> b0, b1;
@@ -982,8 +996,8 @@ __global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
       x[0] += (double)zn[i] * (double)zn[i];
       x[1] += (double)b.D[i] * (double)zn[i] * (double)zn[i];
     }
-    if constexpr (ODD) vstore_nt<double, R>(a.v + g * R, b.v);
-    vstore_nt<T, R>(a.z + g * R, zn);
+    if constexpr (ODD) vstore_s<NT, double, R>(a.v + g * R, b.v);
+    vstore_s<NT, T, R>(a.z + g * R, zn);
   };
   int64_t g = gb;
   if (g + 3 * gs < ge) {
@@ -2102,6 +2116,7 @@ bool vec_ok(const CGArgs<T> &a) {
 // thread (measured faster than two or four per CU on 256^3 grids, and no
 // slower on 128^3, where the longer chunks halve the re-read seams).
 constexpr int kMarchGrid = 256;
+constexpr double kLastLevelCacheBytes = 256.0 * 1024 * 1024;
 
 // Whether a marching launch can take a tile shape: bs threads (256 or 512);
 // ty = 0 (planes of at least one tile), or on 3-D grids ty >= 1 dividing bs,
@@ -2136,6 +2151,9 @@ void spmv_layout(CGArgs<T> &a, int grid_main) {
   a.march_planes = 0;
   a.march_bs = 0;
   a.march_ty = 0;
+  // streaming accesses once a CG iteration's vectors and conductances (about
+  // 104 B a row in FP64, 56 B in FP32) exceed the 256 MB last-level cache
+  a.stream_nt = (double)a.nt * (sizeof(T) == 8 ? 104.0 : 56.0) > kLastLevelCacheBytes;
   if (a.K < 2 || !vec_ok(a)) return;
   if (!march_shape_ok(a, bs, ty)) {
     bs = 256;
@@ -2166,6 +2184,13 @@ int spmv_variant(const CGArgs<T> &a) {
   return vec_ok(a) ? 2 : 1;
 }
 
+template <typename T, int K, bool SC, int BS>
+void launch_march(const CGArgs<T> &a, dim3 g, hipStream_t st) {
+  constexpr int R = kVecRows<T>;
+  if (a.stream_nt) hipLaunchKernelGGL((k_spmv_dia_march<T, K, R, SC, BS, true>), g, dim3(BS), 0, st, a);
+  else hipLaunchKernelGGL((k_spmv_dia_march<T, K, R, SC, BS, false>), g, dim3(BS), 0, st, a);
+}
+
 template <typename T>
 hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hipStream_t st) {
   constexpr int R = kVecRows<T>;
@@ -2173,19 +2198,19 @@ hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hi
     const dim3 g(a.grid_spmv);
     if (a.march_bs == 512) {
       if (a.scaled) {
-        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, true, 512>), g, dim3(512), 0, st, a);
-        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, true, 512>), g, dim3(512), 0, st, a);
+        if (a.K == 2) launch_march<T, 2, true, 512>(a, g, st);
+        else launch_march<T, 3, true, 512>(a, g, st);
       } else {
-        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, false, 512>), g, dim3(512), 0, st, a);
-        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, false, 512>), g, dim3(512), 0, st, a);
+        if (a.K == 2) launch_march<T, 2, false, 512>(a, g, st);
+        else launch_march<T, 3, false, 512>(a, g, st);
       }
     } else {
       if (a.scaled) {
-        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, true, 256>), g, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, true, 256>), g, dim3(256), 0, st, a);
+        if (a.K == 2) launch_march<T, 2, true, 256>(a, g, st);
+        else launch_march<T, 3, true, 256>(a, g, st);
       } else {
-        if (a.K == 2) hipLaunchKernelGGL((k_spmv_dia_march<T, 2, R, false, 256>), g, dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_spmv_dia_march<T, 3, R, false, 256>), g, dim3(256), 0, st, a);
+        if (a.K == 2) launch_march<T, 2, false, 256>(a, g, st);
+        else launch_march<T, 3, false, 256>(a, g, st);
       }
     }
     return hipGetLastError();
@@ -2276,9 +2301,11 @@ hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
   if (a.bj_block > 0)
     hipLaunchKernelGGL((k_update_bj<T>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.scaled && (a.it_hint & 1))
-    hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.stream_nt) hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, true, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, true, false>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.scaled)
-    hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, false>), dim3(grid), dim3(kBlock), 0, st, a);
+    if (a.stream_nt) hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, false, true>), dim3(grid), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_update_scaled<T, kVecRows<T>, false, false>), dim3(grid), dim3(kBlock), 0, st, a);
   else if (a.nt % kVecRows<T> == 0)
     hipLaunchKernelGGL((k_update_vec<T, kVecRows<T>>), dim3(grid), dim3(kBlock), 0, st, a);
   else

@@ -102,6 +102,9 @@ struct CGArgs {
   int32_t march_bs;               // marching SpMV: threads per workgroup (256 or 512)
   int32_t march_ty;               // marching SpMV on 3-D grids: grid lines (offset off[1])
                                   // per tile; a tile is march_bs / march_ty row groups wide
+  int32_t stream_nt;              // 1: the marching SpMV and the scaled update use streaming
+                                  // (non-temporal) accesses for data touched once (set when a
+                                  // CG iteration's data exceed the last-level cache)
   int64_t it_hint;                // CG iteration the host expects this launch to run: picks
                                   // the p buffer for loads issued before the kernel has read
                                   // the scalar block (checked there; a mismatch reloads)
