@@ -815,8 +815,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CGArgs<T> a) {
     const int64_t i = r0 + sub;
     T acc = 0;
     if (i < a.nt) {
-      const int32_t e1 = a.rowptr[i + 1];
-      for (int32_t e = a.rowptr[i] + lid; e < e1; e += L) acc += w[e] * p[col[e]];
+      const int32_t e0 = a.rowptr[i], e1 = a.rowptr[i + 1];
+      const int32_t hf = a.csr_nheavy > 0 ? a.csr_hfirst[i] : 0;
+      if (hf == 0) {
+        for (int32_t e = e0 + lid; e < e1; e += L) acc += w[e] * p[col[e]];
+      } else {                                   // a heavy row: its chunk sums, in order
+        const int32_t c1 = hf - 1 + (e1 - e0 + kCsrChunk - 1) / kCsrChunk;
+        for (int32_t c = hf - 1 + lid; c < c1; c += L) acc += (T)a.csr_cpart[c];
+      }
     }
 #pragma unroll
     for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -828,6 +834,26 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CGArgs<T> a) {
     }
   }
   write_partials<1>(x, a.partials, kPSpmv, lds);
+}
+
+// Heavy rows of the CSR SpMV (rows of more than kCsrHeavy entries, the hubs
+// of power-law graphs), launched before k_spmv_csr: a wavefront sums one
+// chunk of at most kCsrChunk entries, lanes over entries, then a fixed-order
+// reduction across the wavefront.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv_csr_chunks(CGArgs<T> a) {
+  if (block_done(a.sc)) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const T *__restrict__ p = a.p0;
+  for (int64_t c = wave; c < a.csr_nchunks; c += nwaves) {
+    double acc = 0.0;
+    const int32_t e1 = a.csr_cend[c];
+    for (int32_t e = a.csr_cbeg[c] + lane; e < e1; e += 64) acc += (double)(a.w[e] * p[a.col[e]]);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) a.csr_cpart[c] = acc;
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -2235,6 +2261,10 @@ hipError_t launch_spmv(const CGArgs<T> &a, int grid, int rows_per_wave, bool, hi
       default: hipLaunchKernelGGL((k_spmv_dia<T, 8>), dim3(grid), dim3(kBlock), 0, st, a); break;
     }
     return hipGetLastError();
+  }
+  if (a.csr_nheavy > 0) {
+    const int64_t cg = (a.csr_nchunks * 64 + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL((k_spmv_csr_chunks<T>), dim3((unsigned)std::min<int64_t>(cg, kMaxGrid)), dim3(kBlock), 0, st, a);
   }
   switch (rows_per_wave) {
     case 64: hipLaunchKernelGGL((k_spmv_csr<T, 1>), dim3(grid), dim3(kBlock), 0, st, a); break;

@@ -155,6 +155,10 @@ struct irls_mincut_s {
   int32_t *hv_hrow = nullptr, *hv_hc0 = nullptr, *hv_hc1 = nullptr;
   int32_t *hv_brow = nullptr, *hv_bbeg = nullptr, *hv_bend = nullptr;
   double *hv_part = nullptr;
+  // multi-workgroup CSR SpMV: heavy rows cut into chunks (CGArgs::csr_*)
+  int32_t csr_nheavy = 0, csr_nchunks = 0;
+  int32_t *csr_hfirst = nullptr, *csr_cbeg = nullptr, *csr_cend = nullptr;
+  double *csr_cpart = nullptr;
   BatchGraph res_graph;             // single-graph handles with solver 2
   uint32_t lane_code = kDefaultLaneCode;   // resident solver: lanes per light row by bin
   Scalars *pinned = nullptr;
@@ -259,6 +263,12 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.csr_lanes = h->rpw > 0 ? 64 / h->rpw : 64;
   a.march_bs = h->march_bs;
   a.march_ty = h->march_ty;
+  a.csr_nheavy = h->csr_nheavy;
+  a.csr_nchunks = h->csr_nchunks;
+  a.csr_hfirst = h->csr_hfirst;
+  a.csr_cbeg = h->csr_cbeg;
+  a.csr_cend = h->csr_cend;
+  a.csr_cpart = h->csr_cpart;
   spmv_layout(a, h->grid);
   a.bj_block = h->bj_block;
   a.bj_kind = h->bj_kind;
@@ -862,6 +872,23 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
       h->bj_tile = B;
     }
     h->grid = grid_for(hg.nt);
+    // the multi-workgroup CSR SpMV: rows of more than kCsrHeavy entries are
+    // cut into chunks of kCsrChunk (a wavefront each)
+    std::vector<int32_t> csr_hfirst, csr_cbeg, csr_cend;
+    if (!use_dia && h->solver == 1) {
+      for (int64_t i = 0; i < hg.nt; i++) {
+        const int32_t e0 = hg.rowptr[i], e1 = hg.rowptr[i + 1];
+        if (e1 - e0 <= kCsrHeavy) continue;
+        if (csr_hfirst.empty()) csr_hfirst.assign(hg.nt, 0);
+        csr_hfirst[i] = (int32_t)csr_cbeg.size() + 1;
+        h->csr_nheavy++;
+        for (int32_t e = e0; e < e1; e += kCsrChunk) {
+          csr_cbeg.push_back(e);
+          csr_cend.push_back(std::min(e + kCsrChunk, e1));
+        }
+      }
+      h->csr_nchunks = (int32_t)csr_cbeg.size();
+    }
     // Jacobi as symmetric scaling wherever the marching SpMV runs with point
     // Jacobi: that SpMV then reads no diagonal
     if (use_dia && o.precond == 0 && !o.unscaled_cg)
@@ -885,6 +912,10 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
                              (rc = upload(h, &h->blk_rows, blk_rows)) != IRLS_OK ||
                              (rc = upload(h, &h->row_blk, row_blk)) != IRLS_OK)) ||
         (rc = upload_heavy(h, H)) != IRLS_OK ||
+        (h->csr_nheavy > 0 && ((rc = upload(h, &h->csr_hfirst, csr_hfirst)) != IRLS_OK ||
+                               (rc = upload(h, &h->csr_cbeg, csr_cbeg)) != IRLS_OK ||
+                               (rc = upload(h, &h->csr_cend, csr_cend)) != IRLS_OK ||
+                               (rc = upload(h, &h->csr_cpart, std::vector<double>(csr_cbeg.size(), 0.0))) != IRLS_OK)) ||
         (rc = alloc_state(h)) != IRLS_OK) {
       g_thread_error = h->err;
       h->release();

@@ -94,6 +94,14 @@ struct CGArgs {
   int64_t nblk;
   const int32_t *blk_ptr, *blk_rows, *row_blk;
   double *ilu_f;
+  // CSR SpMV of the multi-workgroup path: rows of more than kCsrHeavy entries
+  // (hubs) are cut into chunks of at most kCsrChunk entries, summed a
+  // wavefront each by k_spmv_csr_chunks; the row's lanes in k_spmv_csr then
+  // add its chunk sums instead of its entries
+  int32_t csr_nheavy, csr_nchunks;
+  const int32_t *csr_hfirst;      // [nt] 1 + the first chunk of a heavy row, 0 for the others
+  const int32_t *csr_cbeg, *csr_cend;   // [csr_nchunks] entry range of each chunk
+  double *csr_cpart;              // [csr_nchunks] chunk sums
   int32_t grid_main;              // workgroups of the init / update / replacement kernels
   int32_t grid_spmv;              // workgroups of the SpMV kernel (its partial-sum count)
   int32_t csr_lanes;              // CSR per-round kernels: lanes per row (the SpMV's)
@@ -211,6 +219,8 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
 // into chunks of kChunk (one wavefront each) whose partial sums are then
 // added per row in a fixed order.
 constexpr int32_t kHeavyRow = 128;
+constexpr int32_t kCsrHeavy = 256;       // multi-workgroup CSR SpMV: rows longer than this are chunked
+constexpr int32_t kCsrChunk = 256;
 constexpr int32_t kChunk = 64;
 constexpr int kChunkQ = 4;        // partial sums kept per chunk (the most any pass needs)
 // Light rows are binned by length: bin b holds rows of at most 2^(b+1)
