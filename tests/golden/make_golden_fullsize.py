@@ -2,7 +2,10 @@
 
 * ``seg128_oracle.json``: 128^3 grid, seed 1, 40 rounds, eps 0.1 halved per
   round, Jacobi-PCG to 1e-8;
-* ``seg256_oracle.json``: 256^3 grid, seed 2, the same options.
+* ``seg256_oracle.json``: 256^3 grid, seed 2, the same options;
+* ``seg128-ilu_oracle.json``: the 128^3 instance with block-Jacobi PCG whose
+  blocks are 4x4x4 tiles, each by ILU(0) (Section 3.1's second block
+  strategy), the same rounds and tolerance.
 
 Each file holds every round's record, the sweep cut (value, k*, size of the
 source side, SHA-256 of the packed source-side mask), the potentials at a
@@ -32,7 +35,8 @@ import oracle  # noqa: E402
 FIELDS = ("eps", "cg_iters", "rel_res", "true_rel_res", "s_eps", "l1", "flow", "flow_s", "flow_t",
           "vmin", "vmax", "lower_bound")
 OPTS = dict(rounds=40, cg_rtol=1e-8)
-WORKLOADS = {"seg128": (128, 1), "seg256": (256, 2)}
+# name: (grid edge, seed, ILU(0) tile edge or None for Jacobi)
+WORKLOADS = {"seg128": (128, 1, None), "seg256": (256, 2, None), "seg128-ilu": (128, 1, 4)}
 SAMPLES = 65536
 SAMPLE_STREAM = 77          # the sample's own random stream, distinct from the generator's
 
@@ -60,17 +64,28 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def tile_blocks(N, B):
+    """Block id of every node of an N^3 grid numbered x + N y + N^2 z (s and t
+    last, given ids of their own past the grid): cubic tiles of B rows on a
+    side, numbered x fastest."""
+    ids = np.arange(N ** 3 + 2, dtype=np.int64)
+    x, y, z = ids % N, (ids // N) % N, ids // (N * N)
+    return (x // B) + (N // B) * ((y // B) + (N // B) * (z // B))
+
+
 def run(name):
-    N, seed = WORKLOADS[name]
+    N, seed, tile = WORKLOADS[name]
     g = gen.grid3d_seg(N, seed=seed)
+    pre = dict(precond=2, block_of=tile_blocks(N, tile)) if tile else {}
     t0 = time.perf_counter()
-    x, recs, rc = oracle.irls(g, **OPTS)
+    x, recs, rc = oracle.irls(g, **OPTS, **pre)
     inS, val, k, scale = oracle.sweep(g, x)
     secs = time.perf_counter() - t0
     nt = g.n - 2
     ids = sample_nodes(nt, seed)
     return {
-        "config": f"grid3d_seg {N}^3 seed {seed}, rounds 40, eps0 0.1 halved, cg_rtol 1e-8 (oracle, FP64)",
+        "config": f"grid3d_seg {N}^3 seed {seed}, rounds 40, eps0 0.1 halved, cg_rtol 1e-8 (oracle, FP64)"
+                  + (f", block-Jacobi PCG over {tile}x{tile}x{tile} tiles by ILU(0)" if tile else ", Jacobi PCG"),
         "status": int(rc),
         "rounds": [{f: (int(r[f]) if f == "cg_iters" else float(r[f])) for f in FIELDS} for r in recs],
         "cg_iters_total": int(sum(r["cg_iters"] for r in recs)),
