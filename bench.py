@@ -55,6 +55,16 @@ WORKLOADS = {
     "seg256-ilu": (dict(kind="seg", N=256, seed=2), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=4),
                    "3-D 256^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
                    "(4x4x4 tiles, each block by ILU(0))"),
+    "seg128-ilu-mixed": (dict(kind="seg", N=128, seed=1),
+                         dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=4, precision=1, refine_every=20),
+                         "3-D 128^3 segmentation grid, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
+                         "(4x4x4 tiles, each block by ILU(0)) in the precision form: FP32 conductances, pivots, "
+                         "SpMV and CG vectors, FP64 potentials, dots and residual replacement every 20 CG steps"),
+    "seg256-ilu-mixed": (dict(kind="seg", N=256, seed=2),
+                         dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=4, precision=1, refine_every=20),
+                         "3-D 256^3 segmentation grid, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
+                         "(4x4x4 tiles, each block by ILU(0)) in the precision form: FP32 conductances, pivots, "
+                         "SpMV and CG vectors, FP64 potentials, dots and residual replacement every 20 CG steps"),
     "seg128-ilu8": (dict(kind="seg", N=128, seed=1), dict(rounds=40, cg_rtol=1e-8, precond=2, block_size=8),
                     "3-D 128^3 segmentation grid, FP64, 40 rounds, CG to 1e-8, block-Jacobi preconditioner "
                     "(8x8x8 tiles, each block by ILU(0))"),
@@ -648,10 +658,11 @@ def main():
     # The precision form (FP32 conductances, SpMV and CG vectors; FP64
     # potentials, dots and residual replacement) on the same instance, beside
     # the configured FP64 run: its time-to-cut and its cut against the FP64 cut.
-    # Block-Jacobi runs in FP64 only, so its workloads have no precision form.
+    # Of the block-Jacobi forms only ILU(0) of 4x4x4 tiles has a precision form.
     precision = None
+    ilu4 = opts.get("precond", 0) == 2 and opts.get("block_size", 0) in (0, 4) and info["format"] == 2
     if (args.precision_form and info["solver"] == 1 and opts.get("precision", 0) == 0
-            and opts.get("precond", 0) == 0):
+            and (opts.get("precond", 0) == 0 or ilu4)):
         with P.MinCut.from_graph(g, stream=stream, precision=1, refine_every=20, **opts) as mp:
             mp.solve()
             torch.cuda.synchronize()

@@ -85,7 +85,10 @@ typedef struct {
                                     ascending row order (Section 3.1's second strategy: L
                                     unit lower and U upper triangular on the block's
                                     pattern, (LU)_ij = L~_ij there), factored once per
-                                    round; FP64 and the multi-workgroup solver.  In the
+                                    round; the multi-workgroup solver, FP64 (the precision
+                                    form only with tiles of edge 4: FP32 pivots, residual
+                                    and substitutions; the FP64 residual replacement is
+                                    followed by the application).  In the
                                     diagonal format the blocks are cubic tiles of a 3-D grid
                                     (block_size^3 rows: block_size consecutive rows of
                                     block_size lines of block_size planes; offsets 1, N, P
@@ -345,7 +348,8 @@ irls_status irls_mincut_time_kernel(irls_mincut_t h, int32_t which, int32_t reps
  * 2 * every, ... of each round with a HIP event pair on the handle's stream,
  * and the totals are reset:
  *   which  -1 off, 0 the SpMV (with its fused direction update), 1 the vector
- *          update, 2 the FP64 residual replacement of the precision form, 3 the
+ *          update, 2 the FP64 residual replacement of the precision form (with
+ *          ILU(0) of 4x4x4 tiles, and the application to the new residual), 3 the
  *          block-Jacobi application z = M^-1 r (precond 1 or 2; with ILU(0) of
  *          4x4x4 tiles the application runs inside the vector update, so
  *          which = 1 times both and which = 3 is refused)

@@ -375,6 +375,33 @@ __device__ __forceinline__ bool cg_update_start(const CGArgs<T> &a, double *lds,
   return cg_update_finish(a, l, lds, bc, it_out, alpha_out, pq_out);
 }
 
+// Precision form: whether the FP64 residual replacement runs after the update
+// of iteration i = iter_b - 1 -- every refine_every iterations, and whenever
+// the recursive residual (the update's partial sums) claims convergence, so
+// that the stopping test then uses the true residual.  Every thread gets the
+// same answer; i_out = iter_b.
+template <typename T>
+__device__ __forceinline__ bool replace_due(const CGArgs<T> &a, double *lds, double *bc, int64_t &i_out) {
+  const Scalars *sc = a.sc;
+  const int32_t done = sc->done;
+  const int64_t i = sc->iter_b;
+  const int32_t refine = sc->refine_every;
+  const double bb = sc->bb;
+  double t[3];
+  {
+    double u[2];
+    partial_share<2>(a.partials, kPUpd, a.grid_main, u);
+    t[0] = u[0];
+    t[1] = u[1];
+    t[2] = done != 0 ? 1.0 : 0.0;
+  }
+  block_allreduce<3, 0x4u>(t, lds, bc);
+  if (t[2] != 0.0) return false;
+  const bool conv_rec = sqrt(t[1]) <= a.rtol * sqrt(bb);
+  i_out = i;
+  return conv_rec || i % refine == 0;
+}
+
 // ----------------------------------------------------------------------------
 // SpMV, diagonal format, with the direction update fused in:
 //   p_new = z + beta p_old (z = r / D; p_new = z on the first iteration),
@@ -1162,7 +1189,8 @@ struct IluTiles {
   int64_t N, P, nz, tx, ty, tiles;
 };
 
-__device__ __forceinline__ IluTiles ilu_tiles(const CGArgs<double> &a, int B) {
+template <typename T>
+__device__ __forceinline__ IluTiles ilu_tiles(const CGArgs<T> &a, int B) {
   IluTiles t;
   t.N = a.off[1];
   t.P = a.off[2];
@@ -1180,12 +1208,19 @@ __device__ __forceinline__ int64_t ilu_seg(const IluTiles &t, int B, int64_t k, 
   return z * t.P + y * t.N + x;
 }
 
-template <int B>
-__global__ __launch_bounds__(kBlock) void k_ilu_factor(CGArgs<double> a) {
+// The pivots are formed in FP64 from the working-precision D and w and stored
+// in the working precision (FP32 only in the precision form, 4x4x4 tiles).
+template <typename T, int B>
+__device__ __forceinline__ vec_t<double, B> vload_f64(const T *p) {
+  return __builtin_convertvector(vload<T, B>(p), vec_t<double, B>);
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kBlock) void k_ilu_factor(CGArgs<T> a) {
   typedef vec_t<double, B> V;
   const IluTiles tl = ilu_tiles(a, B);
   const int64_t nt = a.nt;
-  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  const T *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
   for (int64_t k = row_begin(); k < tl.tiles; k += row_stride()) {
     V d[B][B];                                     // pivots by (dz, dy), x in the vector
 #pragma unroll
@@ -1195,10 +1230,10 @@ __global__ __launch_bounds__(kBlock) void k_ilu_factor(CGArgs<double> a) {
         bool ok;
         const int64_t u = ilu_seg(tl, B, k, dy, dz, ok);
         if (!ok) continue;
-        const V D = vload<double, B>(a.D + u);
-        const V wx = vload<double, B>(w0 + u);     // wx[i] couples rows i and i + 1
-        const V wy = dy > 0 ? vload<double, B>(w1 + u - tl.N) : V(0.0);
-        const V wz = dz > 0 ? vload<double, B>(w2 + u - tl.P) : V(0.0);
+        const V D = vload_f64<T, B>(a.D + u);
+        const V wx = vload_f64<T, B>(w0 + u);      // wx[i] couples rows i and i + 1
+        const V wy = dy > 0 ? vload_f64<T, B>(w1 + u - tl.N) : V(0.0);
+        const V wz = dz > 0 ? vload_f64<T, B>(w2 + u - tl.P) : V(0.0);
         V piv;
 #pragma unroll
         for (int i = 0; i < B; i++) {
@@ -1209,7 +1244,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_factor(CGArgs<double> a) {
           piv[i] = p;
         }
         d[dz][dy] = piv;
-        vstore<double, B>(a.bj_im + u, piv);
+        vstore<T, B>(a.bj_im + u, __builtin_convertvector(piv, vec_t<T, B>));
       }
     }
   }
@@ -1318,81 +1353,139 @@ __device__ __forceinline__ double dpp_double(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <int CTRL>
-__device__ __forceinline__ vec_t<double, 4> dpp4(vec_t<double, 4> v) {
-  vec_t<double, 4> o;
+template <int CTRL, typename T, int W>
+__device__ __forceinline__ vec_t<T, W> dppv(vec_t<T, W> v) {
+  vec_t<T, W> o;
 #pragma unroll
-  for (int i = 0; i < 4; i++) o[i] = dpp_double<CTRL>(v[i]);
+  for (int i = 0; i < W; i++) {
+    if constexpr (sizeof(T) == 8) o[i] = dpp_double<CTRL>(v[i]);
+    else o[i] = __int_as_float(dpp_int<CTRL>(__float_as_int(v[i])));
+  }
   return o;
 }
 
-// UPD: the CG vector update of the iteration is fused in (v += alpha p,
+// MODE 0: z = M^-1 r of the residual in rbuf, r^T z into partial slot `slot`.
+// MODE 1: the CG vector update of the iteration is fused in (v += alpha p,
 // r -= alpha q on each lane's own segment, then the application to the new
 // r), so r is not read back, and the kernel writes the partial sums
-// [r^T z, ||r||^2] that k_update_bj and this application write separately.
-template <bool UPD>
-__global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int slot) {
+// [r^T z, ||r||^2] that k_update_bj and the application write separately.
+// MODE 2 (precision form): the FP64 residual replacement of these tiles.  When
+// it is due (replace_due), r = b - L~ v is formed in FP64 from the FP64
+// conductances and potentials, rounded into rbuf, and the application follows;
+// the partial sums are [r^T z, ||r||^2 of the FP64 residual].
+// T is the working precision: the residual, pivots, conductances, direction
+// and z, and the substitutions' arithmetic; the potentials and every sum are
+// FP64.  With T = double the sums are the FP64 kernel's.
+// TPL tiles per lane: with TPL = 2 (FP32, an even number of tiles along x)
+// lane (q, y, z) owns the (y, z) segments of tiles 2q and 2q + 1 of its
+// wavefront's eight, which are adjacent in x: 8 rows, one 32-byte vector per
+// array as in FP64, and two independent recurrences in each step.
+template <typename T, int MODE, int TPL>
+__global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
+  constexpr int S = 4 * TPL;                                     // rows per lane
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   int64_t it = 0;
   double alpha = 0.0, pq = 0.0;
-  if constexpr (UPD) {
+  if constexpr (MODE == 1) {
     if (!cg_update_start(a, lds, bc, it, alpha, pq)) return;
+  } else if constexpr (MODE == 2) {
+    if (!replace_due(a, lds, bc, it)) return;
   } else {
     if (block_done(a.sc)) return;
   }
-  typedef vec_t<double, 4> V;
+  typedef vec_t<T, S> V;
   const IluTiles tl = ilu_tiles(a, 4);
   const int64_t nt = a.nt;
-  const double *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
-  const double *__restrict__ pdir = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;   // the SpMV's direction
+  const T *w0 = a.w, *w1 = a.w + nt, *w2 = a.w + 2 * nt;
+  const T *__restrict__ pdir = (a.K > 0 && (it & 1) == 0) ? a.p1 : a.p0;   // the SpMV's direction
   const int lane = threadIdx.x & 63, q = lane >> 4, y = lane & 3, z = (lane >> 2) & 3;
   const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const V zero = 0.0;
+  const V zero = (T)0;
   double x[2] = {0.0, 0.0};
-  for (int64_t tb = wv * 4; tb < tl.tiles; tb += nwv * 4) {     // the same trip count on every lane
-    const int64_t k = tb + q;
+  for (int64_t tb = wv * 4 * TPL; tb < tl.tiles; tb += nwv * 4 * TPL) {   // the same trip count on every lane
+    const int64_t k = tb + q * TPL;
     bool ok = false;
     int64_t u = 0;
     if (k < tl.tiles) u = ilu_seg(tl, 4, k, y, z, ok);
     V r;
-    if constexpr (UPD) {
+    if constexpr (MODE == 1) {
       if (ok) {
-        const V r0 = vload<double, 4>(a.rbuf + u), qv = vload<double, 4>(a.q + u);
-        const V pv = vload<double, 4>(pdir + u);
-        V vv = vload<double, 4>(a.v + u);
+        const V r0 = vload<T, S>(a.rbuf + u), qv = vload<T, S>(a.q + u);
+        const V pv = vload<T, S>(pdir + u);
+        vec_t<double, S> vv = vload<double, S>(a.v + u);
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-          vv[i] += alpha * pv[i];
-          r[i] = r0[i] - alpha * qv[i];
-          x[1] += r[i] * r[i];
+        for (int i = 0; i < S; i++) {
+          vv[i] += alpha * (double)pv[i];
+          r[i] = (T)((double)r0[i] - alpha * (double)qv[i]);
+          x[1] += (double)r[i] * (double)r[i];
         }
-        vstore<double, 4>(a.v + u, vv);
-        vstore<double, 4>(a.rbuf + u, r);
+        vstore<double, S>(a.v + u, vv);
+        vstore<T, S>(a.rbuf + u, r);
+      } else {
+        r = zero;
+      }
+    } else if constexpr (MODE == 2) {
+      if (ok) {
+        // L~ v on the lane's segment from vector loads: the FP64 conductances
+        // of edges that do not exist are stored as zeros, so every neighbour
+        // term is formed (a neighbour outside the grid reads as 0) and the
+        // sums are row_apply64's, in its order (offsets 1, N, P; the edge
+        // to the higher row, then to the lower one)
+        typedef vec_t<double, S> V64;
+        const double *W = a.w64 ? a.w64 : (const double *)a.w;
+        const double *Dv = a.D64 ? a.D64 : (const double *)a.D;
+        const V64 z64 = 0.0;
+        const V64 vc = vload<double, S>(a.v + u);
+        const double vxm = u >= 1 ? a.v[u - 1] : 0.0, vxp = u + S < nt ? a.v[u + S] : 0.0;
+        const V64 vym = u >= tl.N ? vload<double, S>(a.v + u - tl.N) : z64;
+        const V64 vyp = u + tl.N < nt ? vload<double, S>(a.v + u + tl.N) : z64;
+        const V64 vzm = u >= tl.P ? vload<double, S>(a.v + u - tl.P) : z64;
+        const V64 vzp = u + tl.P < nt ? vload<double, S>(a.v + u + tl.P) : z64;
+        const V64 gx = vload<double, S>(W + u), gy = vload<double, S>(W + nt + u);
+        const V64 gz = vload<double, S>(W + 2 * nt + u);
+        const double gxm = u >= 1 ? W[u - 1] : 0.0;
+        const V64 gym = u >= tl.N ? vload<double, S>(W + nt + u - tl.N) : z64;
+        const V64 gzm = u >= tl.P ? vload<double, S>(W + 2 * nt + u - tl.P) : z64;
+        const V64 dd = vload<double, S>(Dv + u), bv = vload<double, S>(a.b + u);
+#pragma unroll
+        for (int i = 0; i < S; i++) {
+          double acc = dd[i] * vc[i];
+          acc -= gx[i] * (i < S - 1 ? vc[i + 1] : vxp);
+          acc -= (i > 0 ? gx[i - 1] : gxm) * (i > 0 ? vc[i - 1] : vxm);
+          acc -= gy[i] * vyp[i];
+          acc -= gym[i] * vym[i];
+          acc -= gz[i] * vzp[i];
+          acc -= gzm[i] * vzm[i];
+          const double r64 = bv[i] - acc;
+          r[i] = (T)r64;
+          x[1] += r64 * r64;
+        }
+        vstore<T, S>(a.rbuf + u, r);
       } else {
         r = zero;
       }
     } else {
-      r = ok ? vload<double, 4>(a.rbuf + u) : zero;
+      r = ok ? vload<T, S>(a.rbuf + u) : zero;
     }
-    const V d = ok ? vload<double, 4>(a.bj_im + u) : V(1.0);
-    const V wx = ok ? vload<double, 4>(w0 + u) : zero;          // wx[i] couples rows i and i + 1
-    const V wy = ok ? vload<double, 4>(w1 + u) : zero;          // edges to y + 1
-    const V wz = ok ? vload<double, 4>(w2 + u) : zero;          // edges to z + 1
+    const V d = ok ? vload<T, S>(a.bj_im + u) : V((T)1);
+    const V wx = ok ? vload<T, S>(w0 + u) : zero;               // wx[i] couples rows i and i + 1
+    const V wy = ok ? vload<T, S>(w1 + u) : zero;               // edges to y + 1
+    const V wz = ok ? vload<T, S>(w2 + u) : zero;               // edges to z + 1
     V di;
 #pragma unroll
-    for (int i = 0; i < 4; i++) di[i] = 1.0 / d[i];
+    for (int i = 0; i < S; i++) di[i] = (T)1 / d[i];
     // every lane takes part in the row shifts (a shift inside a condition
     // would read lanes that skipped it)
-    const V wy_lo = dpp4<kDppRowShr1>(wy), wz_lo = dpp4<kDppRowShr4>(wz);   // edges from y - 1, z - 1
-    const V di_ylo = dpp4<kDppRowShr1>(di), di_zlo = dpp4<kDppRowShr4>(di);
+    const V wy_lo = dppv<kDppRowShr1>(wy), wz_lo = dppv<kDppRowShr4>(wz);   // edges from y - 1, z - 1
+    const V di_ylo = dppv<kDppRowShr1>(di), di_zlo = dppv<kDppRowShr4>(di);
     V ly, lz, lx;                                                // -L_ik = w_ik / d_k
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < S; i++) {
       ly[i] = wy_lo[i] * di_ylo[i];
       lz[i] = wz_lo[i] * di_zlo[i];
-      lx[i] = i > 0 ? wx[i - 1] * di[i - 1] : 0.0;
+      lx[i] = (i & 3) > 0 ? wx[i - 1] * di[i - 1] : (T)0;        // within the row's own tile
     }
     const int ok_up_y = dpp_int<kDppRowShl1>((int)ok), ok_up_z = dpp_int<kDppRowShl4>((int)ok);
     const bool ok_yup = y < 3 && ok_up_y != 0;
@@ -1400,15 +1493,15 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int sl
     // forward: y_i = r_i - sum_k (A_ik / d_k) y_k over z - 1, y - 1, x - 1
     V yv = zero;
     for (int st = 0; st <= 6; st++) {
-      const V yy = dpp4<kDppRowShr1>(yv), yz = dpp4<kDppRowShr4>(yv);
+      const V yy = dppv<kDppRowShr1>(yv), yz = dppv<kDppRowShr4>(yv);
       if (ok && y + z == st) {
         V t;
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-          double v = r[i];
+        for (int i = 0; i < S; i++) {
+          T v = r[i];
           if (z > 0) v += lz[i] * yz[i];
           if (y > 0) v += ly[i] * yy[i];
-          if (i > 0) v += lx[i] * t[i - 1];
+          if ((i & 3) > 0) v += lx[i] * t[i - 1];
           t[i] = v;
         }
         yv = t;
@@ -1416,18 +1509,18 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int sl
     }
     if (ok) {
 #pragma unroll
-      for (int i = 0; i < 4; i++) x[0] += yv[i] * yv[i] * di[i];         // r^T z = y^T D^-1 y
+      for (int i = 0; i < S; i++) x[0] += (double)yv[i] * (double)yv[i] * (double)di[i];   // r^T z = y^T D^-1 y
     }
     // backward: z_i = (y_i - sum_j A_ij z_j) / d_i over x + 1, y + 1, z + 1
     V zv = zero;
     for (int st = 6; st >= 0; st--) {
-      const V zy = dpp4<kDppRowShl1>(zv), zz = dpp4<kDppRowShl4>(zv);
+      const V zy = dppv<kDppRowShl1>(zv), zz = dppv<kDppRowShl4>(zv);
       if (ok && y + z == st) {
         V t;
 #pragma unroll
-        for (int i = 3; i >= 0; i--) {
-          double v = yv[i];
-          if (i < 3) v += wx[i] * t[i + 1];
+        for (int i = S - 1; i >= 0; i--) {
+          T v = yv[i];
+          if ((i & 3) < 3) v += wx[i] * t[i + 1];
           if (ok_yup) v += wy[i] * zy[i];
           if (ok_zup) v += wz[i] * zz[i];
           t[i] = v * di[i];
@@ -1435,19 +1528,39 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<double> a, int sl
         zv = t;
       }
     }
-    if (ok) vstore<double, 4>(a.z + u, zv);
+    if (ok) vstore<T, S>(a.z + u, zv);
   }
-  if constexpr (UPD) {
+  if constexpr (MODE == 1) {
     write_partials<2>(x, a.partials, kPUpd, lds);
     if (first_thread()) {
       a.sc->iter_b = it + 1;
       a.sc->alpha = alpha;
       a.sc->pq = pq;
     }
+  } else if constexpr (MODE == 2) {
+    write_partials<2>(x, a.partials, kPRep, lds);
   } else {
     double x1[1] = {x[0]};
     write_partials<1>(x1, a.partials, slot, lds);
   }
+}
+
+// Tiles per lane of k_ilu_apply4w: two in FP32 where the tiles along x come
+// in pairs (lines a multiple of 8 rows), else one.
+template <typename T>
+inline int ilu_tpl(const CGArgs<T> &a) {
+  return (sizeof(T) == 4 && (a.off[1] / 4) % 2 == 0) ? 2 : 1;
+}
+
+template <typename T, int MODE>
+void launch_ilu_apply4w(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (ilu_tpl(a) == 2) {
+      hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 1>), dim3(grid), dim3(kBlock), 0, st, a, slot);
 }
 
 // ILU(0) of 8x8x8 tiles, a wavefront per tile: lane y + 8 z owns the x
@@ -1750,22 +1863,8 @@ __global__ __launch_bounds__(kBlock) void k_replace(CGArgs<T> a) {
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   Scalars *sc = a.sc;
-  const int32_t done = sc->done;
-  const int64_t i = sc->iter_b;
-  const int32_t refine = sc->refine_every;
-  const double bb = sc->bb;
-  double t[3];
-  {
-    double u[2];
-    partial_share<2>(a.partials, kPUpd, a.grid_main, u);
-    t[0] = u[0];
-    t[1] = u[1];
-    t[2] = done != 0 ? 1.0 : 0.0;
-  }
-  block_allreduce<3, 0x4u>(t, lds, bc);
-  if (t[2] != 0.0) return;
-  const bool conv_rec = sqrt(t[1]) <= a.rtol * sqrt(bb);
-  if (!(conv_rec || i % refine == 0)) return;
+  int64_t i = 0;
+  if (!replace_due(a, lds, bc, i)) return;
   double x[2] = {0.0, 0.0};
   if (a.scaled) {
     // v holds D^1/2 v, and when the last update was an even iteration its
@@ -2292,11 +2391,14 @@ hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st) {
       return hipGetLastError();
     }
     if (a.bj_kind == 2) {
-      if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_factor<2>), dim3(grid), dim3(kBlock), 0, st, a);
+      if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_factor<double, 2>), dim3(grid), dim3(kBlock), 0, st, a);
       else if (a.bj_tile == 8) hipLaunchKernelGGL(k_ilu_factor8w, dim3(grid), dim3(kBlock), 0, st, a);
-      else hipLaunchKernelGGL((k_ilu_factor<4>), dim3(grid), dim3(kBlock), 0, st, a);
+      else hipLaunchKernelGGL((k_ilu_factor<double, 4>), dim3(grid), dim3(kBlock), 0, st, a);
       return hipGetLastError();
     }
+  } else if (bj_update_fused(a)) {             // the precision form's 4x4x4 tiles
+    hipLaunchKernelGGL((k_ilu_factor<T, 4>), dim3(grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((k_bj_factor<T>), dim3(grid), dim3(kBlock), 0, st, a);
   return hipGetLastError();
@@ -2312,9 +2414,12 @@ hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t s
     if (a.bj_kind == 2) {
       if (a.bj_tile == 2) hipLaunchKernelGGL((k_ilu_apply<2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
       else if (a.bj_tile == 8) hipLaunchKernelGGL(k_ilu_apply8w, dim3(grid), dim3(kBlock), 0, st, a, slot);
-      else hipLaunchKernelGGL((k_ilu_apply4w<false>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      else launch_ilu_apply4w<double, 0>(a, grid, slot, st);
       return hipGetLastError();
     }
+  } else if (bj_update_fused(a)) {
+    launch_ilu_apply4w<T, 0>(a, grid, slot, st);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((k_bj_apply<T>), dim3(grid), dim3(kBlock), 0, st, a, slot);
   return hipGetLastError();
@@ -2322,11 +2427,9 @@ hipError_t launch_bj_apply(const CGArgs<T> &a, int grid, int slot, hipStream_t s
 
 template <typename T>
 hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
-  if constexpr (std::is_same<T, double>::value) {
-    if (bj_update_fused(a)) {                    // the update and the ILU(0) application in one kernel
-      hipLaunchKernelGGL((k_ilu_apply4w<true>), dim3(grid), dim3(kBlock), 0, st, a, (int)kPUpd);
-      return hipGetLastError();
-    }
+  if (bj_update_fused(a)) {                      // the update and the ILU(0) application in one kernel
+    launch_ilu_apply4w<T, 1>(a, grid, (int)kPUpd, st);
+    return hipGetLastError();
   }
   if (a.bj_block > 0)
     hipLaunchKernelGGL((k_update_bj<T>), dim3(grid), dim3(kBlock), 0, st, a);
@@ -2346,6 +2449,10 @@ hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st) {
 template <typename T>
 hipError_t launch_replace_residual(const CGArgs<T> &a, int grid, hipStream_t st) {
   constexpr int R = kVecRows<T>;
+  if (bj_update_fused(a)) {                      // the replacement, then the ILU(0) application
+    launch_ilu_apply4w<T, 2>(a, grid, (int)kPRep, st);
+    return hipGetLastError();
+  }
   if (a.scaled && a.wh64 && a.D64 && (a.K == 2 || a.K == 3) && vec_ok(a)) {
     if (a.K == 2) hipLaunchKernelGGL((k_replace_scaled<T, 2, R>), dim3(grid), dim3(kBlock), 0, st, a);
     else hipLaunchKernelGGL((k_replace_scaled<T, 3, R>), dim3(grid), dim3(kBlock), 0, st, a);

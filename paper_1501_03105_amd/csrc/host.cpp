@@ -149,7 +149,8 @@ struct irls_mincut_s {
   int64_t nblk = 0;
   int32_t *blk_ptr = nullptr, *blk_rows = nullptr, *row_blk = nullptr;
   double *ilu_f = nullptr;
-  double *bj_r = nullptr, *bj_f = nullptr, *bj_im = nullptr, *bj_g = nullptr;
+  void *bj_r = nullptr, *bj_im = nullptr;     // working precision (CGArgs::rbuf, bj_im)
+  double *bj_f = nullptr, *bj_g = nullptr;
   // resident solver: heavy-row chunks (device) and the single graph's record
   int32_t *hv_crow = nullptr, *hv_cbeg = nullptr, *hv_cend = nullptr;
   int32_t *hv_hrow = nullptr, *hv_hc0 = nullptr, *hv_hc1 = nullptr;
@@ -278,9 +279,9 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.blk_rows = h->blk_rows;
   a.row_blk = h->row_blk;
   a.ilu_f = h->ilu_f;
-  a.rbuf = h->bj_r;
+  a.rbuf = (T *)h->bj_r;
   a.bj_f = h->bj_f;
-  a.bj_im = h->bj_im;
+  a.bj_im = (T *)h->bj_im;
   a.bj_g = h->bj_g;
   a.wh = (T *)h->wh;
   a.wh64 = h->wh64;
@@ -664,9 +665,9 @@ irls_status alloc_state(irls_mincut_t h) {
   HIPCHK(h, h->dalloc(&h->b, nt), "alloc");
   if (h->bj_kind == 3) HIPCHK(h, h->dalloc(&h->ilu_f, h->g.nnz), "alloc");
   if (h->bj_block > 0) {
-    HIPCHK(h, h->dalloc(&h->bj_r, nt), "alloc");
+    HIPCHK(h, rawalloc(&h->bj_r, nt * ts), "alloc");
     HIPCHK(h, h->dalloc(&h->bj_f, nt), "alloc");
-    HIPCHK(h, h->dalloc(&h->bj_im, nt), "alloc");
+    HIPCHK(h, rawalloc(&h->bj_im, nt * ts), "alloc");
     HIPCHK(h, h->dalloc(&h->bj_g, nt), "alloc");
   }
   HIPCHK(h, h->dalloc(&h->gt, nt), "alloc");
@@ -870,6 +871,11 @@ irls_status irls_mincut_create(irls_mincut_t *out, int64_t n, int64_t m, const i
       h->bj_block = B * B * B;
       h->bj_kind = 2;
       h->bj_tile = B;
+    }
+    if (o.precond == 2 && o.precision == 1 && !(h->bj_kind == 2 && h->bj_tile == 4)) {
+      g_thread_error = "the precision form takes ILU(0) of 4x4x4 tiles of a 3-D grid only";
+      delete h;
+      return IRLS_ERR_OPTIONS;
     }
     h->grid = grid_for(hg.nt);
     // the multi-workgroup CSR SpMV: rows of more than kCsrHeavy entries are

@@ -494,8 +494,12 @@ irls_status check_options(const irls_options &o, std::string &err) {
     return IRLS_ERR_OPTIONS;
   }
   if (o.precision == 1 && o.solver == 2) { err = "the resident solver runs in FP64 only"; return IRLS_ERR_OPTIONS; }
-  if (o.precond >= 1 && (o.precision != 0 || o.solver == 2)) {
-    err = "block-Jacobi runs in FP64 on the multi-workgroup solver";
+  if (o.precond >= 1 && o.solver == 2) {
+    err = "block-Jacobi runs on the multi-workgroup solver";
+    return IRLS_ERR_OPTIONS;
+  }
+  if (o.precond == 1 && o.precision != 0) {
+    err = "exact line blocks run in FP64";
     return IRLS_ERR_OPTIONS;
   }
   if (o.precond == 1 && o.format == 1) {

@@ -80,10 +80,15 @@ struct CGArgs {
   int32_t weights_fp64;           // precision 1: compute conductances in FP64
   double cst;                     // s-t capacity
   double rtol;                    // CG stopping tolerance relative to ||b||
-  // block-Jacobi (precond 1, FP64): the residual kept explicitly and, per row,
-  // the forward multiplier, 1/pivot and backward multiplier of its block's
-  // tridiagonal LU factors; bj_block rows per block (0: Jacobi)
-  double *rbuf, *bj_f, *bj_im, *bj_g;
+  // block-Jacobi: the residual kept explicitly (rbuf) and, for exact line
+  // blocks (precond 1), per row the forward multiplier, 1/pivot and backward
+  // multiplier of its block's tridiagonal LU factors; bj_block rows per block
+  // (0: Jacobi).  rbuf and bj_im are in the working precision: FP32 only for
+  // ILU(0) of 4x4x4 tiles in the precision form, FP64 for every other kind.
+  T *rbuf;
+  double *bj_f;
+  T *bj_im;
+  double *bj_g;
   int32_t bj_block;
   // bj_kind 2: ILU(0) of cubic tiles of a 3-D grid (bj_tile rows on a side,
   // bj_block = bj_tile^3); bj_im then holds the ILU(0) pivot of each row.
@@ -168,7 +173,9 @@ template <typename T> hipError_t launch_direction(const CGArgs<T> &a, int grid, 
 template <typename T> hipError_t launch_update(const CGArgs<T> &a, int grid, hipStream_t st);
 // With ILU(0) of 4x4x4 tiles the CG update and the application z = M^-1 r of
 // an iteration are one kernel, launched by launch_update; the iteration then
-// makes no launch_bj_apply call.
+// makes no launch_bj_apply call.  In the precision form the FP64 residual
+// replacement of these tiles also applies the preconditioner to the new
+// residual, in the same kernel (launch_replace_residual).
 template <typename T> inline bool bj_update_fused(const CGArgs<T> &a) { return a.bj_kind == 2 && a.bj_tile == 4; }
 // block-Jacobi: factors once per round, and z = M^-1 r with r^T z into partial slot `slot`
 template <typename T> hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st);

@@ -106,16 +106,63 @@ def test_ilu0_tiles_match_oracle(P, oracle_mod, case):
     assert all(r["true_rel_res"] <= 1e-9 for r in st)
 
 
+# The precision form with ILU(0) of 4x4x4 tiles: FP32 conductances, pivots,
+# residual, direction and SpMV, the substitutions in FP32; FP64 potentials,
+# dot products and an FP64 residual replacement (followed by the application)
+# every 20 iterations.  Against the oracle's FP64 run with the same tiles.
+# Where the tiles along x come in pairs each lane applies two of them; with an
+# odd number of tiles a line (the 20-row lines) one.
+# Bars: cut within 1e-4 relative (the precision form's bar), the GPU cut's
+# value exact for its set, every round's true residual within 2x the
+# tolerance, and CG iterations within 10 % + 5 of the FP64 run's, which a
+# wrong preconditioner (still symmetric positive definite) would break.
+PREC_CASES = [("box 16x12x10 (a short top tile)", lambda: gen.grid3d_box(16, 12, 16 * 12 * 10, seed=5), 16, 12, 20),
+              ("box 32x32x24 (the marching SpMV)", lambda: gen.grid3d_box(32, 32, 32 * 32 * 24, seed=7), 32, 32, 20),
+              ("box 20x12x9 (five tiles a line: one tile per lane)",
+               lambda: gen.grid3d_box(20, 12, 20 * 12 * 9, seed=8), 20, 12, 20),
+              ("segmentation grid 48^3", lambda: gen.grid3d_seg(48, seed=3), 48, 48, 40)]
+
+
+@pytest.mark.parametrize("case", range(len(PREC_CASES)))
+def test_ilu0_tiles_precision_form(P, oracle_mod, case):
+    name, make, nx, ny, rounds = PREC_CASES[case]
+    g = make()
+    opts = dict(rounds=rounds, cg_rtol=1e-8)
+    say(f"ILU(0) tiles, precision form: {name}")
+    with P.MinCut.from_graph(g, precond=2, precision=1, refine_every=20, **opts) as mc:
+        info = mc.info()
+        assert info["solver"] == 1 and info["format"] == 2
+        rc, st = mc.solve()
+        x = mc.potentials()
+        S, v, _ = mc.cut()
+    blk = tile_ids(nx, ny, g.n - 2, 4)
+    xo, so, _ = oracle_mod.irls(g, precond=2, block_of=blk, **opts)
+    _, vo, _, _ = oracle_mod.sweep(g, xo)
+    err = max_pot_err(x, xo)
+    rel = abs(v - vo) / vo
+    it_g = sum(r["cg_iters"] for r in st)
+    it_o = sum(r["cg_iters"] for r in so)
+    say(f"  cut rel {rel:.2e}, potential error {err:.2e}, CG {it_g} (oracle FP64 {it_o})")
+    assert rc == P.OK
+    assert rel <= 1e-4
+    assert oracle_mod.cut_value(g, S) == v
+    assert all(r["true_rel_res"] <= 2e-8 for r in st[1:])
+    assert abs(it_g - it_o) <= 0.1 * it_o + 5
+
+
 def test_ilu0_tile_option_errors(P):
     ok = gen.grid3d_box(16, 12, 16 * 12 * 4, seed=1)
     assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2) == P.OK
+    # the precision form takes 4x4x4 tiles (only)
+    assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2, precision=1) == P.OK
     # format 1 on the same grid is allowed: CSR blocks instead of tiles
     assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2, format=1, solver=1) == P.OK
     g16 = gen.grid3d_box(16, 16, 16 * 16 * 3, seed=1)
     assert P.create_error(g16.n, g16.eu, g16.ev, g16.cap, g16.s, g16.t, precond=2, block_size=8) == P.OK
     for g, kw in ((ok, dict(block_size=8)),                                  # lines of 12: not a multiple of 8
-                  (ok, dict(block_size=6)), (g16, dict(block_size=16)), (ok, dict(precision=1)),
-                  (ok, dict(solver=2)),
+                  (ok, dict(block_size=6)), (g16, dict(block_size=16)),
+                  (ok, dict(precision=1, block_size=2)), (g16, dict(precision=1, block_size=8)),
+                  (ok, dict(precision=1, format=1)), (ok, dict(solver=2)),
                   (gen.grid3d_box(18, 12, 18 * 12 * 4, seed=1), {}),        # lines not a multiple of 4
                   (gen.grid3d_box(16, 12, 16 * 12 * 4 + 5, seed=1), {}),    # a partial plane
                   (gen.grid2d(64, 64, seed=0), {})):                       # not a 3-D grid

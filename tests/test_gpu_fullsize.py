@@ -35,6 +35,13 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 # take different rounding orders: the GPU solves the symmetrically scaled
 # system).  Precision form: 1e-4 (measured 4.6e-5 at 256^3).
 POT_BAR = 1e-8
+# ILU(0) tiles: the GPU's application multiplies by 1/d where the oracle
+# divides, and runs its substitutions in another order.  On this instance a
+# change of rounding order alone moves the round-40 potentials by about 1e-7
+# (measured: the same Jacobi CG with the potential update regrouped, every
+# round's CG count equal), because the last rounds are ill-conditioned; so
+# the bar for a path whose rounding order differs is twice that.
+POT_BAR_ILU = 2e-7
 POT_BAR_PRECISION = 1e-4
 ITER_BAR = 1              # CG iterations per round (measured: equal in every round)
 STAT_RTOL = 1e-6          # S_eps, ||CBx||_1, flows of every round
@@ -58,7 +65,7 @@ def P():
     return P
 
 
-def check_run(name, G, x, st, inS, val, k, exact=True):
+def check_run(name, G, x, st, inS, val, k, exact=True, pot_bar=POT_BAR):
     """Compare a GPU run with the oracle's golden run; returns the largest
     potential difference at the samples."""
     ids = np.asarray(G["sample_ids"], dtype=np.int64)
@@ -75,7 +82,7 @@ def check_run(name, G, x, st, inS, val, k, exact=True):
         assert val == sw["value"] and k == sw["k_star"]
         assert int(np.sum(inS)) == sw["source_side_size"]
         assert mask_sha(inS) == sw["mask_sha256"]
-        assert err <= POT_BAR
+        assert err <= pot_bar
         assert len(it_g) == len(it_o) and d_it <= ITER_BAR
         for l, (rg, ro) in enumerate(zip(st, G["rounds"])):
             for f in ("s_eps", "l1", "flow", "flow_s", "flow_t", "lower_bound"):
@@ -119,6 +126,34 @@ def test_fullsize_128_equals_oracle_run(P, oracle_mod, seg128):
     assert info2["n_sc"] < g.n // 10
     assert lo <= mu <= hi
     assert lo == pytest.approx(G["rounds"][0]["flow"], rel=1e-6)        # E01 of round 0
+
+
+def test_fullsize_128_ilu0_tiles(P, seg128):
+    """128^3 with block-Jacobi PCG over 4x4x4 tiles, each by ILU(0), against
+    the oracle's run with the same preconditioner (seg128-ilu_oracle.json):
+    FP64 to the bars of the plain path except potentials (POT_BAR_ILU); the
+    precision form's cut within 1e-4.
+    Beside the oracle's Jacobi run (seg128_oracle.json) only the cut value is
+    compared (within 1e-6; 1e-4 for the precision form): in the last rounds
+    (eps about 2e-13) conductances span six orders of magnitude, so two correct
+    solves by different preconditioners, both stopped at a relative residual
+    of 1e-8, leave potentials that differ by up to about 1e-2 (measured)."""
+    G = golden("seg128-ilu")
+    GJ = golden("seg128")
+    for kw in (dict(), dict(precision=1, refine_every=20)):
+        name = "128^3 ILU(0) tiles, precision form" if kw else "128^3 ILU(0) tiles, FP64"
+        with P.MinCut.from_graph(seg128, precond=2, block_size=4, **OPTS, **kw) as mc:
+            rc, st = mc.solve()
+            x = mc.potentials()
+            inS, val, k = mc.cut()
+        assert rc == P.OK
+        check_run(name, G, x, st, inS, val, k, exact=not kw, pot_bar=POT_BAR_ILU)
+        rel = abs(val - G["sweep"]["value"]) / G["sweep"]["value"]
+        rel_j = abs(val - GJ["sweep"]["value"]) / GJ["sweep"]["value"]
+        say(f"{name}: cut relative error vs the oracle's ILU(0) run {rel:.2e}, vs its Jacobi run {rel_j:.2e}")
+        assert rel <= (1e-4 if kw else 0.0)
+        assert rel_j <= (1e-4 if kw else 1e-6)
+        assert all(r["true_rel_res"] <= 2e-8 for r in st[1:])
 
 
 def test_fullsize_256_equals_oracle_run(P):
