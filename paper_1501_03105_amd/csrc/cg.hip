@@ -1546,7 +1546,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
 }
 
 // Tiles per lane of k_ilu_apply4w: two in FP32 where the tiles along x come
-// in pairs (lines a multiple of 8 rows), else one.
+// in pairs (lines a multiple of 8 rows), else one; one for the replacement.
 template <typename T>
 inline int ilu_tpl(const CGArgs<T> &a) {
   return (sizeof(T) == 4 && (a.off[1] / 4) % 2 == 0) ? 2 : 1;
@@ -1554,7 +1554,9 @@ inline int ilu_tpl(const CGArgs<T> &a) {
 
 template <typename T, int MODE>
 void launch_ilu_apply4w(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
-  if constexpr (sizeof(T) == 4) {
+  // the replacement (MODE 2) moves mostly FP64 data, already 32 bytes a lane
+  // with one tile per lane, and two would double its live vectors
+  if constexpr (sizeof(T) == 4 && MODE != 2) {
     if (ilu_tpl(a) == 2) {
       hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
       return;
