@@ -1380,7 +1380,7 @@ __device__ __forceinline__ vec_t<T, W> dppv(vec_t<T, W> v) {
 // lane (q, y, z) owns the (y, z) segments of tiles 2q and 2q + 1 of its
 // wavefront's eight, which are adjacent in x: 8 rows, one 32-byte vector per
 // array as in FP64, and two independent recurrences in each step.
-template <typename T, int MODE, int TPL>
+template <typename T, int MODE, int TPL, bool PF>
 __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
   constexpr int S = 4 * TPL;                                     // rows per lane
   __shared__ double lds[4 * (kBlock / 64)];
@@ -1404,21 +1404,48 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
   const int64_t nwv = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const V zero = (T)0;
   double x[2] = {0.0, 0.0};
-  for (int64_t tb = wv * 4 * TPL; tb < tl.tiles; tb += nwv * 4 * TPL) {   // the same trip count on every lane
-    const int64_t k = tb + q * TPL;
-    bool ok = false;
-    int64_t u = 0;
-    if (k < tl.tiles) u = ilu_seg(tl, 4, k, y, z, ok);
+  // one trip's loads; with PF (prefetch) the next trip's are issued before
+  // this trip's substitutions, so they are in flight while those run
+  struct TripLoads {
+    V r0, qv, pv, d, wx, wy, wz;
+    vec_t<double, S> vv;
+    int64_t u;
+    bool ok;
+  };
+  auto fetch = [&](int64_t tb_, TripLoads &L) {
+    const int64_t k = tb_ + q * TPL;
+    L.ok = false;
+    L.u = 0;
+    if (k < tl.tiles) L.u = ilu_seg(tl, 4, k, y, z, L.ok);
+    const bool ok = L.ok;
+    const int64_t u = L.u;
+    if constexpr (MODE != 2) L.r0 = ok ? vload<T, S>(a.rbuf + u) : zero;
+    if constexpr (MODE == 1) {
+      L.qv = ok ? vload<T, S>(a.q + u) : zero;
+      L.pv = ok ? vload<T, S>(pdir + u) : zero;
+      L.vv = ok ? vload<double, S>(a.v + u) : vec_t<double, S>(0.0);
+    }
+    L.d = ok ? vload<T, S>(a.bj_im + u) : V((T)1);
+    L.wx = ok ? vload<T, S>(w0 + u) : zero;                    // wx[i] couples rows i and i + 1
+    L.wy = ok ? vload<T, S>(w1 + u) : zero;                    // edges to y + 1
+    L.wz = ok ? vload<T, S>(w2 + u) : zero;                    // edges to z + 1
+  };
+  const int64_t step = nwv * 4 * TPL;
+  TripLoads cur;
+  fetch(wv * 4 * TPL, cur);
+  for (int64_t tb = wv * 4 * TPL; tb < tl.tiles; tb += step) {   // the same trip count on every lane
+    TripLoads nxt;
+    if constexpr (PF) fetch(tb + step, nxt);
+    const bool ok = cur.ok;
+    const int64_t u = cur.u;
     V r;
     if constexpr (MODE == 1) {
       if (ok) {
-        const V r0 = vload<T, S>(a.rbuf + u), qv = vload<T, S>(a.q + u);
-        const V pv = vload<T, S>(pdir + u);
-        vec_t<double, S> vv = vload<double, S>(a.v + u);
+        vec_t<double, S> vv = cur.vv;
 #pragma unroll
         for (int i = 0; i < S; i++) {
-          vv[i] += alpha * (double)pv[i];
-          r[i] = (T)((double)r0[i] - alpha * (double)qv[i]);
+          vv[i] += alpha * (double)cur.pv[i];
+          r[i] = (T)((double)cur.r0[i] - alpha * (double)cur.qv[i]);
           x[1] += (double)r[i] * (double)r[i];
         }
         vstore<double, S>(a.v + u, vv);
@@ -1467,12 +1494,9 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
         r = zero;
       }
     } else {
-      r = ok ? vload<T, S>(a.rbuf + u) : zero;
+      r = cur.r0;
     }
-    const V d = ok ? vload<T, S>(a.bj_im + u) : V((T)1);
-    const V wx = ok ? vload<T, S>(w0 + u) : zero;               // wx[i] couples rows i and i + 1
-    const V wy = ok ? vload<T, S>(w1 + u) : zero;               // edges to y + 1
-    const V wz = ok ? vload<T, S>(w2 + u) : zero;               // edges to z + 1
+    const V d = cur.d, wx = cur.wx, wy = cur.wy, wz = cur.wz;
     V di;
 #pragma unroll
     for (int i = 0; i < S; i++) di[i] = (T)1 / d[i];
@@ -1529,6 +1553,8 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
       }
     }
     if (ok) vstore<T, S>(a.z + u, zv);
+    if constexpr (PF) cur = nxt;
+    else fetch(tb + step, cur);
   }
   if constexpr (MODE == 1) {
     write_partials<2>(x, a.partials, kPUpd, lds);
@@ -1558,11 +1584,11 @@ void launch_ilu_apply4w(const CGArgs<T> &a, int grid, int slot, hipStream_t st) 
   // with one tile per lane, and two would double its live vectors
   if constexpr (sizeof(T) == 4 && MODE != 2) {
     if (ilu_tpl(a) == 2) {
-      hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 2>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 2, MODE == 1>), dim3(grid), dim3(kBlock), 0, st, a, slot);
       return;
     }
   }
-  hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 1>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+  hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 1, false>), dim3(grid), dim3(kBlock), 0, st, a, slot);
 }
 
 // ILU(0) of 8x8x8 tiles, a wavefront per tile: lane y + 8 z owns the x
