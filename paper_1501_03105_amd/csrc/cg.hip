@@ -1081,8 +1081,9 @@ __global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
   }
 }
 
-// After CG in the scaled form: if the last completed update was an even
-// iteration, its alpha p is still pending; add it (its direction is in p1).
+// After CG in the scaled form (and with the precision form's ILU(0) tiles):
+// if the last completed update was an even iteration, its alpha p is still
+// pending; add it (its direction is in p1).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_flush_v(CGArgs<T> a) {
   const int64_t done_updates = a.sc->iter_b;
@@ -1380,15 +1381,29 @@ __device__ __forceinline__ vec_t<T, W> dppv(vec_t<T, W> v) {
 // lane (q, y, z) owns the (y, z) segments of tiles 2q and 2q + 1 of its
 // wavefront's eight, which are adjacent in x: 8 rows, one 32-byte vector per
 // array as in FP64, and two independent recurrences in each step.
-template <typename T, int MODE, int TPL, bool PF>
+// VU (MODE 1): how the potentials move.  0: v += alpha p every iteration
+// (FP64).  In the precision form they move every second iteration, as in the
+// scaled form: 1 (even iterations) leaves v alone and reads no direction;
+// 2 (odd iterations) adds alpha_{i-1} p_{i-1} + alpha_i p_i (p_{i-1} is in p1,
+// p_i in p0).  A step left pending when CG stops is added by k_flush_v, and
+// the replacement includes it.  The kernel checks the parity the host chose.
+template <typename T, int MODE, int TPL, bool PF, int VU>
 __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
   constexpr int S = 4 * TPL;                                     // rows per lane
+  constexpr bool kPaired = sizeof(T) == 4;                       // the precision form (bj_pair_v)
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   int64_t it = 0;
-  double alpha = 0.0, pq = 0.0;
+  double alpha = 0.0, pq = 0.0, alpha_prev = 0.0;
   if constexpr (MODE == 1) {
+    if constexpr (VU == 2) alpha_prev = a.sc->alpha_par[0];
     if (!cg_update_start(a, lds, bc, it, alpha, pq)) return;
+    if constexpr (VU != 0) {
+      if (((it & 1) != 0) != (VU == 2)) {                        // the launch sequence is out of step
+        if (first_thread()) { a.sc->done = 1; a.sc->status = IRLS_ERR_DEVICE; }
+        return;
+      }
+    }
   } else if constexpr (MODE == 2) {
     if (!replace_due(a, lds, bc, it)) return;
   } else {
@@ -1407,7 +1422,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
   // one trip's loads; with PF (prefetch) the next trip's are issued before
   // this trip's substitutions, so they are in flight while those run
   struct TripLoads {
-    V r0, qv, pv, d, wx, wy, wz;
+    V r0, qv, pv, pp, d, wx, wy, wz;
     vec_t<double, S> vv;
     int64_t u;
     bool ok;
@@ -1422,8 +1437,11 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
     if constexpr (MODE != 2) L.r0 = ok ? vload<T, S>(a.rbuf + u) : zero;
     if constexpr (MODE == 1) {
       L.qv = ok ? vload<T, S>(a.q + u) : zero;
-      L.pv = ok ? vload<T, S>(pdir + u) : zero;
-      L.vv = ok ? vload<double, S>(a.v + u) : vec_t<double, S>(0.0);
+      if constexpr (VU != 1) {
+        L.pv = ok ? vload<T, S>(pdir + u) : zero;
+        L.vv = ok ? vload<double, S>(a.v + u) : vec_t<double, S>(0.0);
+      }
+      if constexpr (VU == 2) L.pp = ok ? vload<T, S>(a.p1 + u) : zero;
     }
     L.d = ok ? vload<T, S>(a.bj_im + u) : V((T)1);
     L.wx = ok ? vload<T, S>(w0 + u) : zero;                    // wx[i] couples rows i and i + 1
@@ -1444,11 +1462,12 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
         vec_t<double, S> vv = cur.vv;
 #pragma unroll
         for (int i = 0; i < S; i++) {
-          vv[i] += alpha * (double)cur.pv[i];
+          if constexpr (VU == 0) vv[i] += alpha * (double)cur.pv[i];
+          if constexpr (VU == 2) vv[i] += alpha_prev * (double)cur.pp[i] + alpha * (double)cur.pv[i];
           r[i] = (T)((double)cur.r0[i] - alpha * (double)cur.qv[i]);
           x[1] += (double)r[i] * (double)r[i];
         }
-        vstore<double, S>(a.v + u, vv);
+        if constexpr (VU != 1) vstore<double, S>(a.v + u, vv);
         vstore<T, S>(a.rbuf + u, r);
       } else {
         r = zero;
@@ -1464,12 +1483,26 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
         const double *W = a.w64 ? a.w64 : (const double *)a.w;
         const double *Dv = a.D64 ? a.D64 : (const double *)a.D;
         const V64 z64 = 0.0;
-        const V64 vc = vload<double, S>(a.v + u);
-        const double vxm = u >= 1 ? a.v[u - 1] : 0.0, vxp = u + S < nt ? a.v[u + S] : 0.0;
-        const V64 vym = u >= tl.N ? vload<double, S>(a.v + u - tl.N) : z64;
-        const V64 vyp = u + tl.N < nt ? vload<double, S>(a.v + u + tl.N) : z64;
-        const V64 vzm = u >= tl.P ? vload<double, S>(a.v + u - tl.P) : z64;
-        const V64 vzp = u + tl.P < nt ? vload<double, S>(a.v + u + tl.P) : z64;
+        // the true potentials: v plus the step an even iteration left pending
+        // (iter_b odd; its direction is in p1)
+        const bool pend = kPaired && (it & 1) != 0;
+        const double ap = pend ? a.sc->alpha_par[0] : 0.0;
+        auto vseg = [&](int64_t at) -> V64 {
+          V64 w = vload<double, S>(a.v + at);
+          if (pend) {
+            const V pp = vload<T, S>(a.p1 + at);
+#pragma unroll
+            for (int i = 0; i < S; i++) w[i] += ap * (double)pp[i];
+          }
+          return w;
+        };
+        auto vone = [&](int64_t at) { return a.v[at] + (pend ? ap * (double)a.p1[at] : 0.0); };
+        const V64 vc = vseg(u);
+        const double vxm = u >= 1 ? vone(u - 1) : 0.0, vxp = u + S < nt ? vone(u + S) : 0.0;
+        const V64 vym = u >= tl.N ? vseg(u - tl.N) : z64;
+        const V64 vyp = u + tl.N < nt ? vseg(u + tl.N) : z64;
+        const V64 vzm = u >= tl.P ? vseg(u - tl.P) : z64;
+        const V64 vzp = u + tl.P < nt ? vseg(u + tl.P) : z64;
         const V64 gx = vload<double, S>(W + u), gy = vload<double, S>(W + nt + u);
         const V64 gz = vload<double, S>(W + 2 * nt + u);
         const double gxm = u >= 1 ? W[u - 1] : 0.0;
@@ -1561,6 +1594,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
     if (first_thread()) {
       a.sc->iter_b = it + 1;
       a.sc->alpha = alpha;
+      if constexpr (VU != 0) a.sc->alpha_par[it & 1] = alpha;
       a.sc->pq = pq;
     }
   } else if constexpr (MODE == 2) {
@@ -1578,17 +1612,27 @@ inline int ilu_tpl(const CGArgs<T> &a) {
   return (sizeof(T) == 4 && (a.off[1] / 4) % 2 == 0) ? 2 : 1;
 }
 
-template <typename T, int MODE>
-void launch_ilu_apply4w(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
+template <typename T, int MODE, int VU>
+void launch_ilu_apply4w_vu(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
   // the replacement (MODE 2) moves mostly FP64 data, already 32 bytes a lane
   // with one tile per lane, and two would double its live vectors
   if constexpr (sizeof(T) == 4 && MODE != 2) {
     if (ilu_tpl(a) == 2) {
-      hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 2, MODE == 1>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+      hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 2, MODE == 1, VU>), dim3(grid), dim3(kBlock), 0, st, a, slot);
       return;
     }
   }
-  hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 1, false>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+  hipLaunchKernelGGL((k_ilu_apply4w<T, MODE, 1, false, VU>), dim3(grid), dim3(kBlock), 0, st, a, slot);
+}
+
+template <typename T, int MODE>
+void launch_ilu_apply4w(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
+  if constexpr (MODE == 1 && sizeof(T) == 4) {                 // paired potential updates
+    if (a.it_hint & 1) launch_ilu_apply4w_vu<T, 1, 2>(a, grid, slot, st);
+    else launch_ilu_apply4w_vu<T, 1, 1>(a, grid, slot, st);
+  } else {
+    launch_ilu_apply4w_vu<T, MODE, 0>(a, grid, slot, st);
+  }
 }
 
 // ILU(0) of 8x8x8 tiles, a wavefront per tile: lane y + 8 z owns the x
@@ -2242,6 +2286,12 @@ hipError_t launch_scale_w(const CGArgs<T> &a, int grid, hipStream_t st) {
 }
 
 template <typename T>
+hipError_t launch_flush_v(const CGArgs<T> &a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_flush_v<T>), dim3(grid), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_scale_v(const CGArgs<T> &a, int dir, int grid, hipStream_t st) {
   if (dir < 0) hipLaunchKernelGGL((k_flush_v<T>), dim3(grid), dim3(kBlock), 0, st, a);
   hipLaunchKernelGGL((k_scale_v<T>), dim3(grid), dim3(kBlock), 0, st, a, dir);
@@ -2515,6 +2565,7 @@ hipError_t launch_scalars_reset(Scalars *sc, int64_t maxit, int32_t refine_every
   template hipError_t launch_cginit<T>(const CGArgs<T> &, int, hipStream_t);               \
   template hipError_t launch_scale_w<T>(const CGArgs<T> &, int, hipStream_t);              \
   template hipError_t launch_scale_v<T>(const CGArgs<T> &, int, int, hipStream_t);         \
+  template hipError_t launch_flush_v<T>(const CGArgs<T> &, int, hipStream_t);              \
   template hipError_t launch_spmv<T>(const CGArgs<T> &, int, int, bool, hipStream_t);      \
   template void spmv_layout<T>(CGArgs<T> &, int);                                          \
   template int spmv_variant<T>(const CGArgs<T> &);                                         \
