@@ -671,10 +671,12 @@ def main():
             _, valp, _ = mp.cut()
             torch.cuda.synchronize()
             dtp = time.perf_counter() - t0
+            _, valp2, _ = mp.cut_two_level()             # untimed, as for the FP64 run
         out = {"seconds_to_cut": round(dtp, 4), "cuts_per_s": round(1.0 / dtp, 3),
                "speedup_vs_fp64": round(ms_step / 1000.0 / dtp, 3),
                "cg_iters": int(sum(r["cg_iters"] for r in stp)), "cut_value": valp,
-               "relative_cut_difference_vs_fp64": abs(valp - val) / val}
+               "relative_cut_difference_vs_fp64": abs(valp - val) / val,
+               "two_level_cut": valp2, "two_level_cut_equals_fp64_run": valp2 == val2}
         if gold:
             ov = gold["sweep"]["value"]
             out["relative_cut_error_vs_fp64_oracle"] = abs(valp - ov) / ov
