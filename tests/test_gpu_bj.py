@@ -150,6 +150,58 @@ def test_ilu0_tiles_precision_form(P, oracle_mod, case):
     assert abs(it_g - it_o) <= 0.1 * it_o + 5
 
 
+def test_ilu0_tiles_precision_form_driver_paths(P, oracle_mod):
+    """The precision form over 4x4x4 ILU(0) tiles through the round driver's
+    other paths, where its potentials (moved every second iteration, a
+    pending step flushed after CG) must come out whole: a continuation after
+    new capacities from the oracle's old potentials against the oracle's FP64
+    continuation with the same tiles (cut within 1e-4, value exact for its
+    set); the certified-gap stop (the cut at or above the exact minimum cut,
+    the last round's gap within the stated fraction); in-solve timing of the
+    update (one launch per CG iteration) and of the replacement."""
+    from gen import Graph
+    g1 = gen.grid3d_box(32, 32, 32 * 32 * 24, seed=7)
+    f = 1.0 + 0.2 * (2.0 * np.random.default_rng(17).random(g1.cap.shape[0]) - 1.0)
+    g2 = Graph(g1.n, g1.s, g1.t, g1.eu, g1.ev, g1.cap * f, meta=dict(g1.meta))
+    blk = tile_ids(32, 32, 32 * 32 * 24, 4)
+    opts = dict(rounds=20, cg_rtol=1e-8)
+    x_old, _, _ = oracle_mod.irls(g1, precond=2, block_of=blk, **opts)
+    xo, so, _ = oracle_mod.irls(g2, init=2, x0=x_old, eps0=1e-3, rounds=12, cg_rtol=1e-8, precond=2, block_of=blk)
+    _, vo, _, _ = oracle_mod.sweep(g2, xo)
+    prec = dict(precond=2, precision=1, refine_every=20)
+    with P.MinCut.from_graph(g1, **prec, **opts) as mc:
+        mc.solve()
+        mc.update_capacities(g2.eu, g2.ev, g2.cap)
+        mc.set_potentials(x_old)
+        rc, cs = mc.solve_range(1, 12, eps_first=1e-3)
+        x = mc.potentials()
+        S, v, _ = mc.cut()
+    rel = abs(v - vo) / vo
+    say(f"ILU(0) tiles, precision form, continuation: cut rel {rel:.2e}, potential error "
+        f"{max_pot_err(x, xo):.2e}, CG {sum(r['cg_iters'] for r in cs[1:])} (oracle FP64 "
+        f"{sum(r['cg_iters'] for r in so[1:])})")
+    assert rc == P.OK and rel <= 1e-4
+    assert oracle_mod.cut_value(g2, S) == v
+    assert all(cs[l]["true_rel_res"] <= 2e-8 for l in range(1, 13))
+    _, mu = oracle_mod.maxflow(g1)
+    with P.MinCut.from_graph(g1, **prec, rounds=40, cg_rtol=1e-8, stop_gap=0.01) as mc:
+        rc, st = mc.solve()
+        S, v, _ = mc.cut()
+        last = st[-1]
+    say(f"  stop_gap 0.01: {len(st)} rounds, cut {v!r}, exact minimum {mu!r}")
+    assert rc == P.OK and len(st) <= 41
+    assert v >= mu * (1 - 1e-12) and oracle_mod.cut_value(g1, S) == v
+    if len(st) < 41:                                       # stopped on the gap
+        assert last["l1"] - last["lower_bound"] <= 0.01 * last["l1"]
+    with P.MinCut.from_graph(g1, **prec, rounds=4, cg_rtol=1e-8) as mc:
+        mc.set_kernel_timing(1, 1)
+        rc, st = mc.solve()
+        assert rc == P.OK and mc.kernel_timing()["n_working"] == sum(r["cg_iters"] for r in st)
+        mc.set_kernel_timing(2, 1)
+        rc2, st2 = mc.solve()
+        assert rc2 == P.OK and [r["cg_iters"] for r in st2] == [r["cg_iters"] for r in st]
+
+
 def test_ilu0_tile_option_errors(P):
     ok = gen.grid3d_box(16, 12, 16 * 12 * 4, seed=1)
     assert P.create_error(ok.n, ok.eu, ok.ev, ok.cap, ok.s, ok.t, precond=2) == P.OK
