@@ -1381,16 +1381,16 @@ __device__ __forceinline__ vec_t<T, W> dppv(vec_t<T, W> v) {
 // lane (q, y, z) owns the (y, z) segments of tiles 2q and 2q + 1 of its
 // wavefront's eight, which are adjacent in x: 8 rows, one 32-byte vector per
 // array as in FP64, and two independent recurrences in each step.
-// VU (MODE 1): how the potentials move.  0: v += alpha p every iteration
-// (FP64).  In the precision form they move every second iteration, as in the
-// scaled form: 1 (even iterations) leaves v alone and reads no direction;
+// VU (MODE 1): how the potentials move.  0: v += alpha p every iteration.
+// In the CG iterations they move every second iteration, as in the scaled
+// form: 1 (even iterations) leaves v alone and reads no direction;
 // 2 (odd iterations) adds alpha_{i-1} p_{i-1} + alpha_i p_i (p_{i-1} is in p1,
 // p_i in p0).  A step left pending when CG stops is added by k_flush_v, and
 // the replacement includes it.  The kernel checks the parity the host chose.
 template <typename T, int MODE, int TPL, bool PF, int VU>
 __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
   constexpr int S = 4 * TPL;                                     // rows per lane
-  constexpr bool kPaired = sizeof(T) == 4;                       // the precision form (bj_pair_v)
+  constexpr bool kPaired = true;                                 // bj_pair_v
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   int64_t it = 0;
@@ -1627,7 +1627,7 @@ void launch_ilu_apply4w_vu(const CGArgs<T> &a, int grid, int slot, hipStream_t s
 
 template <typename T, int MODE>
 void launch_ilu_apply4w(const CGArgs<T> &a, int grid, int slot, hipStream_t st) {
-  if constexpr (MODE == 1 && sizeof(T) == 4) {                 // paired potential updates
+  if constexpr (MODE == 1) {                                     // paired potential updates
     if (a.it_hint & 1) launch_ilu_apply4w_vu<T, 1, 2>(a, grid, slot, st);
     else launch_ilu_apply4w_vu<T, 1, 1>(a, grid, slot, st);
   } else {
