@@ -1070,7 +1070,7 @@ static irls_status cut_impl(irls_mincut_t h, bool noalloc, uint8_t *in_source_si
         HIPCHK(h, h->dalloc(&b.idB, g.nt), "alloc");
         HIPCHK(h, h->dalloc(&b.rank, g.nt), "alloc");
         HIPCHK(h, h->dalloc(&b.delta, g.nt), "alloc");
-        HIPCHK(h, h->dalloc(&b.hist, 256 * nb), "alloc");
+        HIPCHK(h, h->dalloc(&b.hist, 256 * nb + 256), "alloc");   // counts, then the 256 digit totals
         HIPCHK(h, h->dalloc(&b.bsum, sb), "alloc");
         HIPCHK(h, h->dalloc(&b.bmin, sb), "alloc");
         HIPCHK(h, h->dalloc(&b.barg, sb), "alloc");
@@ -1938,7 +1938,7 @@ irls_status irls_mincut_cut_batch(irls_mincut_t h, uint8_t *in_source_side, doub
       HIPCHK(h, h->dalloc(&b.idB, rows), "alloc");
       HIPCHK(h, h->dalloc(&b.rank, rows), "alloc");
       HIPCHK(h, h->dalloc(&b.delta, rows), "alloc");
-      HIPCHK(h, h->dalloc(&b.hist, 256 * nb), "alloc");
+      HIPCHK(h, h->dalloc(&b.hist, 256 * nb + 256), "alloc");   // counts, then the 256 digit totals
       HIPCHK(h, h->dalloc(&b.bsum, sb), "alloc");
       HIPCHK(h, h->dalloc(&h->swb.best, h->G), "alloc");
       HIPCHK(h, h->dalloc(&h->swb.mask, h->nodes_total), "alloc");

@@ -143,7 +143,7 @@ struct SweepBufs {
   uint32_t *idA = nullptr, *idB = nullptr;
   uint32_t *rank = nullptr;
   __int128 *delta = nullptr;      // per rank position
-  uint32_t *hist = nullptr;       // [256 * blocks]
+  uint32_t *hist = nullptr;       // [256 * blocks + 256]: digit counts per block, digit totals
   __int128 *bsum = nullptr;       // per scan block
   __int128 *bmin = nullptr;
   int64_t *barg = nullptr;

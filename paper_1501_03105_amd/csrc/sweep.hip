@@ -5,8 +5,9 @@
 //   1. keys:    potential -> 64-bit key whose ascending order is descending x
 //   2. sort:    stable LSD radix sort, 8 passes of 8-bit digits; per pass a
 //               per-workgroup digit histogram, one exclusive scan over
-//               (digit, workgroup), and a stable scatter ranked with
-//               wavefront ballots
+//               (digit, workgroup) (a workgroup per digit: digit totals,
+//               then each digit's counts from its offset), and a stable
+//               scatter ranked with wavefront ballots
 //   3. rank:    rank[id] = position + 1
 //   4. delta:   cut(S_k) - cut(S_{k-1}) for the node entering at step k, in
 //               128-bit fixed point round(c 2^k): edges to nodes already in S
@@ -77,28 +78,84 @@ __global__ __launch_bounds__(kBlock) void k_hist(const uint64_t *key, int64_t nt
   hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of hist[256 * nb] (digit-major) in place, one workgroup
-__global__ __launch_bounds__(1024) void k_scan_hist(uint32_t *hist, int64_t total) {
-  __shared__ uint32_t part[1024];
-  const int64_t per = (total + 1023) / 1024;
-  const int64_t lo = (int64_t)threadIdx.x * per;
-  const int64_t hi = lo + per < total ? lo + per : total;
+// Exclusive scan of hist[256 * nb] (digit-major: digit d's count in block b
+// at hist[d * nb + b]) in place, by two kernels of one workgroup per digit.
+// The first writes each digit's total to dsum[d] (the 256 entries after the
+// histogram); the second starts digit d at the sum of dsum over the digits
+// below it and scans the digit's nb counts in tiles of kScanThreads.  Integer
+// sums: the result is the sequential scan's exactly.
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_hist_digit_sum(const uint32_t *hist, int64_t nb, uint32_t *dsum) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t *h = hist + (size_t)blockIdx.x * nb;
   uint32_t s = 0;
-  for (int64_t i = lo; i < hi; i++) s += hist[i];
-  part[threadIdx.x] = s;
+  for (int64_t i = threadIdx.x; i < nb; i += kScanThreads) s += h[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) wsum[wid] = s;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += add;
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kScanThreads / 64; w++) t += wsum[w];
+    dsum[blockIdx.x] = t;
   }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (int64_t i = lo; i < hi; i++) {
-    uint32_t c = hist[i];
-    hist[i] = run;
-    run += c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_hist_digit_scan(uint32_t *hist, int64_t nb, const uint32_t *dsum) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  __shared__ uint32_t s_off;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int nw = kScanThreads / 64;
+  // digit offset: the totals of the digits below this one (fewer than 256 < kScanThreads)
+  uint32_t o = threadIdx.x < blockIdx.x ? dsum[threadIdx.x] : 0u;
+#pragma unroll
+  for (int k = 32; k > 0; k >>= 1) o += __shfl_xor(o, k, 64);
+  if (lane == 0) wsum[wid] = o;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < nw; w++) t += wsum[w];
+    s_off = t;
   }
+  __syncthreads();
+  uint32_t carry = s_off;
+  uint32_t *h = hist + (size_t)blockIdx.x * nb;
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? h[i] : 0u;
+    const uint32_t inc = wave_inclusive_scan(v, lane);
+    __syncthreads();                                   // wsum is free again
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0, tile = 0;
+    for (int w = 0; w < nw; w++) {
+      const uint32_t t = wsum[w];
+      if (w < wid) before += t;
+      tile += t;
+    }
+    if (i < nb) h[i] = carry + before + inc - v;
+    carry += tile;
+  }
+}
+
+// The exclusive scan of one radix pass's histogram (its 256 * nb counts,
+// then 256 digit totals, in hist).
+static void scan_hist(uint32_t *hist, int64_t nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_hist_digit_sum, dim3(256), dim3(kScanThreads), 0, st, (const uint32_t *)hist, nb,
+                     hist + 256 * nb);
+  hipLaunchKernelGGL(k_hist_digit_scan, dim3(256), dim3(kScanThreads), 0, st, hist, nb,
+                     (const uint32_t *)(hist + 256 * nb));
 }
 
 // stable scatter: sub-tiles of kBlock keys in order; within a sub-tile the
@@ -395,7 +452,7 @@ hipError_t sweep_run(const SweepArgs &a, SweepBufs &b, hipStream_t st) {
     for (int pass = 0; pass < 8; pass++) {
       const int shift = 8 * pass;
       hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kBlock), 0, st, kin, nt, shift, b.hist);
-      hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, st, b.hist, (int64_t)256 * nb);
+      scan_hist(b.hist, nb, st);
       hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, kin, iin, kout, iout, nt, shift,
                          (const uint32_t *)b.hist);
       uint64_t *tk = kin; kin = kout; kout = tk;
@@ -444,7 +501,7 @@ constexpr SweepLayout sweep_layout(int64_t nt, int64_t n) {
   L.idB = place(4 * (size_t)nt);
   L.rank = place(4 * (size_t)nt);
   L.delta = place(16 * (size_t)nt);
-  L.hist = place(4 * 256 * nb);
+  L.hist = place(4 * (256 * nb + 256));                  // the counts, then the digit totals
   L.bsum = place(16 * sb);
   L.bmin = place(16 * sb);
   L.barg = place(8 * sb);
@@ -518,7 +575,7 @@ hipError_t sweep_batch_run(const SweepBatchArgs &a, SweepBufs &b, SweepBatchBufs
         hipLaunchKernelGGL(k_gidkey, dim3(gs), dim3(kBlock), 0, st, (const uint32_t *)iin, a.gid, n, kin);
       const int shift = pass < 8 ? 8 * pass : 8 * (pass - 8);
       hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kBlock), 0, st, kin, n, shift, b.hist);
-      hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, st, b.hist, (int64_t)256 * nb);
+      scan_hist(b.hist, nb, st);
       hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, kin, iin, kout, iout, n, shift,
                          (const uint32_t *)b.hist);
       uint64_t *tk = kin; kin = kout; kout = tk;
