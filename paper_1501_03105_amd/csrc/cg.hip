@@ -1390,7 +1390,6 @@ __device__ __forceinline__ vec_t<T, W> dppv(vec_t<T, W> v) {
 template <typename T, int MODE, int TPL, bool PF, int VU>
 __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
   constexpr int S = 4 * TPL;                                     // rows per lane
-  constexpr bool kPaired = true;                                 // bj_pair_v
   __shared__ double lds[4 * (kBlock / 64)];
   __shared__ double bc[4];
   int64_t it = 0;
@@ -1485,7 +1484,7 @@ __global__ __launch_bounds__(kBlock) void k_ilu_apply4w(CGArgs<T> a, int slot) {
         const V64 z64 = 0.0;
         // the true potentials: v plus the step an even iteration left pending
         // (iter_b odd; its direction is in p1)
-        const bool pend = kPaired && (it & 1) != 0;
+        const bool pend = (it & 1) != 0;
         const double ap = pend ? a.sc->alpha_par[0] : 0.0;
         auto vseg = [&](int64_t at) -> V64 {
           V64 w = vload<double, S>(a.v + at);

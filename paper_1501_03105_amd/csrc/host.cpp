@@ -468,7 +468,7 @@ irls_status solve_multi(irls_mincut_t h, irls_round_stats *stats) {
       irls_status rc = run_cg(h, a, pred, &it, &st);
       if (rc != IRLS_OK) return rc;
       if (a.scaled) HIPCHK(h, launch_scale_v(a, -1, h->grid, h->stream), "scaling");
-      else if (bj_pair_v(a)) HIPCHK(h, launch_flush_v(a, h->grid, h->stream), "pending step");
+      else if (bj_update_fused(a)) HIPCHK(h, launch_flush_v(a, h->grid, h->stream), "pending step");
       pred = it;
       h->last_iters = it;
       if (st == IRLS_ERR_DEVICE) {

@@ -175,11 +175,10 @@ template <typename T> hipError_t launch_update(const CGArgs<T> &a, int grid, hip
 // an iteration are one kernel, launched by launch_update; the iteration then
 // makes no launch_bj_apply call.  In the precision form the FP64 residual
 // replacement of these tiles also applies the preconditioner to the new
-// residual, in the same kernel (launch_replace_residual).
+// residual, in the same kernel (launch_replace_residual).  That kernel moves
+// the potentials every second iteration (as the scaled form does); a step
+// left pending when CG stops is added by launch_flush_v.
 template <typename T> inline bool bj_update_fused(const CGArgs<T> &a) { return a.bj_kind == 2 && a.bj_tile == 4; }
-// That kernel moves the potentials every second iteration (as the scaled
-// form does); a step left pending when CG stops is added by launch_flush_v.
-template <typename T> inline bool bj_pair_v(const CGArgs<T> &a) { return bj_update_fused(a); }
 template <typename T> hipError_t launch_flush_v(const CGArgs<T> &a, int grid, hipStream_t st);
 // block-Jacobi: factors once per round, and z = M^-1 r with r^T z into partial slot `slot`
 template <typename T> hipError_t launch_bj_factor(const CGArgs<T> &a, int grid, hipStream_t st);
