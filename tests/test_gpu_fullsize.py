@@ -160,15 +160,19 @@ def test_fullsize_256_equals_oracle_run(P):
     """256^3 (16.8M rows; the working set is ten times the Infinity Cache):
     the plain FP64 path equals the oracle's run, and the precision form (FP32
     conductances, SpMV and CG vectors; FP64 potentials, dots and residual
-    replacement every 20 steps) is within 1e-4 of the FP64 oracle's cut."""
+    replacement every 20 steps) is within 1e-4 of the FP64 oracle's cut, and
+    so is the precision form over ILU(0) tiles."""
     g = gen.grid3d_seg(256, seed=2)
     G = golden("seg256")
+    two_level_fp64 = None
     for kw, exact in ((dict(), True), (dict(precision=1, refine_every=20), False)):
         with P.MinCut.from_graph(g, **OPTS, **kw) as mc:
             assert mc.spmv_variant()[0] == 4                   # the scaled marching SpMV
             rc, st = mc.solve()
             x = mc.potentials()
             inS, val, k = mc.cut()
+            if exact:
+                two_level_fp64 = mc.cut_two_level()[1]
         assert rc == P.OK
         name = "256^3 precision form" if kw else "256^3 FP64"
         err = check_run(name, G, x, st, inS, val, k, exact=exact)
@@ -180,3 +184,17 @@ def test_fullsize_256_equals_oracle_run(P):
             assert r["lower_bound"] <= val * (1 + 1e-12), l
         if not exact:
             assert err <= POT_BAR_PRECISION
+    # the precision form over 4x4x4 ILU(0) tiles at the same size: its cut
+    # within 1e-4 of the oracle's (another preconditioner: potentials are not
+    # compared), and the two-level cut of its potentials equal to that of the
+    # plain FP64 path's (both the exact minimum on this instance)
+    with P.MinCut.from_graph(g, **OPTS, precision=1, refine_every=20, precond=2, block_size=4) as mc:
+        rc, st = mc.solve()
+        inS, val, k = mc.cut()
+        _, v2, _ = mc.cut_two_level()
+    assert rc == P.OK
+    rel = abs(val - G["sweep"]["value"]) / G["sweep"]["value"]
+    say(f"256^3 precision form, ILU(0) tiles: cut {val!r}, relative error vs the FP64 oracle {rel:.2e}; "
+        f"two-level cut {v2!r} (the FP64 path's {two_level_fp64!r})")
+    assert rel <= 1e-4
+    assert v2 == two_level_fp64
