@@ -216,6 +216,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale_w(CGArgs<T> a) {
   FOR_ROWS(u, a.nt) {
     const double du = diag64(a, u);
+    if constexpr (sizeof(T) == 8) a.Dn[u] = (float)du;          // the stopping norm's weights
     for (int k = 0; k < a.K; k++) {
       const int64_t j = u + a.off[k];
       const double wv = j < a.nt ? (a.w64 ? a.w64[k * a.nt + u] : (double)a.w[k * a.nt + u]) : 0.0;
@@ -995,7 +996,10 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
 }
 
 // Vector update of the scaled form (z holds D^-1/2 r): z -= alpha q,
-// r^T M^-1 r = z^T z and ||r||^2 = sum D z^2.  The potentials move every
+// r^T M^-1 r = z^T z and ||r||^2 = sum D z^2, which only decides when CG
+// stops: its weights D are read in FP32 (Dn; 4 bytes a row instead of 8 in
+// the FP64 form), which changes the norm by at most 2^-24 relative, so a stop
+// moves only when the residual lands that close to the tolerance.  The potentials move every
 // second iteration: an even iteration leaves its alpha p pending, and the odd
 // one after it adds alpha_{it-1} p_{it-1} + alpha_it p_it, reading both
 // direction buffers (iteration j's direction is in p0 for odd j, p1 for
@@ -1004,7 +1008,8 @@ __global__ __launch_bounds__(kBlock) void k_update_vec(CGArgs<T> a) {
 // reads.  Rows are processed in pairs of groups as in k_update_vec.
 template <typename T, int R, bool ODD>
 struct ScaledGroup {
-  vec_t<T, R> z, q, D, p, pp;
+  vec_t<T, R> z, q, p, pp;
+  vec_t<float, R> Dn;                       // the stopping norm's weights (D in FP32)
   vec_t<double, R> v;
 };
 
@@ -1021,7 +1026,7 @@ __global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
   const T *__restrict__ p_prev = ODD ? a.p1 : a.p0;
   auto load = [&](int64_t g, ScaledGroup<T, R, ODD> &b) {
     const int64_t u0 = g * R;
-    b.z = vload_s<NT, T, R>(a.z + u0); b.q = vload_s<NT, T, R>(a.q + u0); b.D = vload_s<NT, T, R>(a.D + u0);
+    b.z = vload_s<NT, T, R>(a.z + u0); b.q = vload_s<NT, T, R>(a.q + u0); b.Dn = vload_s<NT, float, R>(a.Dn + u0);
     if constexpr (ODD) {
       b.p = vload_s<NT, T, R>(p_it + u0); b.pp = vload_s<NT, T, R>(p_prev + u0);
       b.v = vload_s<NT, double, R>(a.v + u0);
@@ -1047,7 +1052,7 @@ __global__ __launch_bounds__(kBlock) void k_update_scaled(CGArgs<T> a) {
       if constexpr (ODD) b.v[i] += alpha_prev * (double)b.pp[i] + alpha * (double)b.p[i];
       zn[i] = (T)((double)b.z[i] - alpha * (double)b.q[i]);
       x[0] += (double)zn[i] * (double)zn[i];
-      x[1] += (double)b.D[i] * (double)zn[i] * (double)zn[i];
+      x[1] += (double)b.Dn[i] * (double)zn[i] * (double)zn[i];
     }
     if constexpr (ODD) vstore_s<NT, double, R>(a.v + g * R, b.v);
     vstore_s<NT, T, R>(a.z + g * R, zn);

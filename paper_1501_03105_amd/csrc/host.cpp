@@ -135,6 +135,7 @@ struct irls_mincut_s {
   // working-precision state (double for precision 0, float for 1)
   void *w = nullptr, *D = nullptr, *r = nullptr, *q = nullptr, *p0 = nullptr, *p1 = nullptr;
   void *wh = nullptr;               // scaled conductances (scaled form only)
+  float *Dn = nullptr;              // FP64 scaled form: D in FP32 for the stopping norm
   double *wh64 = nullptr;           // their FP64 values (precision 1, scaled form)
   bool scaled = false;              // CG on D^-1/2 L~ D^-1/2 (Jacobi as symmetric scaling)
   double *partials = nullptr;
@@ -285,6 +286,7 @@ CGArgs<T> make_args(irls_mincut_t h) {
   a.bj_g = h->bj_g;
   a.wh = (T *)h->wh;
   a.wh64 = h->wh64;
+  a.Dn = sizeof(T) == 4 ? (float *)h->D : h->Dn;
   a.scaled = h->scaled ? 1 : 0;
   return a;
 }
@@ -679,6 +681,7 @@ irls_status alloc_state(irls_mincut_t h) {
   HIPCHK(h, rawalloc(&h->p0, nt * ts), "alloc");
   if (h->g.format == 2) HIPCHK(h, rawalloc(&h->p1, nt * ts), "alloc");
   if (h->scaled) HIPCHK(h, rawalloc(&h->wh, nw * ts), "alloc");
+  if (h->scaled && !f32) HIPCHK(h, h->dalloc(&h->Dn, nt), "alloc");
   if (f32) {
     HIPCHK(h, h->dalloc(&h->w64, nw), "alloc");
     HIPCHK(h, h->dalloc(&h->D64, nt), "alloc");

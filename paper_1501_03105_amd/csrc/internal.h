@@ -68,6 +68,8 @@ struct CGArgs {
   // scaled conductances w_uj / sqrt(D_u D_j) in the diagonal layout.
   T *wh;
   double *wh64;                   // precision 1, scaled: FP64 scaled conductances (replacement)
+  float *Dn;                      // scaled form: D rounded to FP32, the weights of the stopping
+                                  // norm ||r||^2 = sum D r^2 (the FP32 form: its D)
   int32_t scaled;
   // reductions
   double *partials;               // [kNumPSlots][kNumPartial][kMaxGrid]
