@@ -126,6 +126,20 @@ static void check_host_graph() {
   CHECK(check_options(o, err) == IRLS_OK, "default options");
   o.precond = 7;
   CHECK(check_options(o, err) == IRLS_ERR_OPTIONS, "precond out of range");
+  // block-Jacobi: ILU(0) blocks also in the precision form (which blocks the
+  // graph allows is decided at create); exact line blocks only in FP64;
+  // neither on the resident solver
+  irls_options_default(&o);
+  o.precond = 2;
+  o.precision = 1;
+  CHECK(check_options(o, err) == IRLS_OK, "precision form with ILU(0) blocks");
+  o.precond = 1;
+  CHECK(check_options(o, err) == IRLS_ERR_OPTIONS, "precision form with exact line blocks");
+  o.precision = 0;
+  CHECK(check_options(o, err) == IRLS_OK, "exact line blocks in FP64");
+  o.precond = 2;
+  o.solver = 2;
+  CHECK(check_options(o, err) == IRLS_ERR_OPTIONS, "block-Jacobi on the resident solver");
 }
 
 static void check_fixed_point() {
